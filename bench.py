@@ -1,0 +1,184 @@
+"""Benchmark of the AIR reconstruction path on one MI355X.
+
+A step is one full AIR reconstruction of a batch of independent 512 x 512
+fan-beam cases (720 views x 736 bins, split Bregman 50 x 5 CG, the whole hot
+path: Joseph projector, ramp GEMM, matched backprojector, CG updates,
+framelet shrinkage), from the noisy sinograms already resident in HBM.
+
+    python bench.py [--steps K] [--warmup W] [--batch B]
+
+Prints one JSON line: recon/s (float32 path) with p50/p99 step latency, the
+same for the mixed-precision ramp, projector GRays/s, the roofline position of
+the dominant kernel (HIP-event timing inside this run) and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "mixed_f16": 2500.0, "mixed_bf16": 2500.0}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2_25", "c5"])
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-timing-only", action="store_true",
+                    help="skip the timed steps; run only the instrumented pass (for profiler runs)")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1310_1434_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".cuh", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def timed_steps(torch, plan, y, w, steps, warmup, ws):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.solve(y, w.lam, w.mu, w.n_outer, w.n_cg, workspace=ws, with_resid=False)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(steps):
+        plan.solve(y, w.lam, w.mu, w.n_outer, w.n_cg, workspace=ws, with_resid=False)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+    return wall, lat
+
+
+def ray_steps(plan) -> int:
+    _, lo, hi = plan.tables()
+    return int(np.maximum(hi - lo + 1, 0).sum())
+
+
+def cpu_baseline(w, y0):
+    """FP64 oracle on 2 of the 50 Bregman iterations of one case, scaled to a full solve."""
+    import oracle
+    oracle.build(force=False)
+    g = oracle.Geom(w.geom)
+    k = 2
+    t = time.perf_counter()
+    oracle.solve(g, y0.astype(np.float64), w.lam, w.mu, k, w.n_cg)
+    dt = time.perf_counter() - t
+    per_recon = dt * w.n_outer / k
+    return {"value": 1.0 / per_recon, "unit": "recon/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, {k} of {w.n_outer} Bregman iterations (x{w.n_cg} CG) of one "
+                      f"{w.geom.n}^2 x {w.geom.n_views}-view case in {dt:.2f} s, scaled x{w.n_outer // k}"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {a.gpus} is not supported "
+              "(independent reconstructions shard across GPUs with no communication)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    from paper_1310_1434_amd import air
+
+    w = synth.workload(a.workload)
+    B = a.batch
+    ys = np.stack([synth.make_case(w, s)["y"] for s in range(B)]).astype(np.float32)
+    y = torch.from_numpy(ys).cuda()
+    g = w.geom
+    plan = air.Plan(g, max_batch=B, precision="fp32")
+    ws = torch.empty(plan.solve_workspace_bytes(B), dtype=torch.uint8, device="cuda")
+    rsteps = ray_steps(plan)
+
+    out = {"metric": "recon/s + p99 latency, 512^2x720-view AIR, mixed vs FP32; proj GRays/s",
+           "unit": "recon/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded ellipse phantoms, exact line integrals, Poisson noise)",
+           "config": {"workload": w.name, "beam": g.beam, "n": g.n, "views": g.n_views, "bins": g.n_bins,
+                      "batch": B, "n_outer": w.n_outer, "n_cg": w.n_cg, "lambda": w.lam, "mu": w.mu,
+                      "precision": "fp32"}}
+
+    if not a.kernel_timing_only:
+        wall, lat = timed_steps(torch, plan, y, w, a.steps, a.warmup, ws)
+        out["value"] = B * a.steps / wall
+        out["ms_per_step"] = 1e3 * wall / a.steps
+        out["p50_ms"] = float(np.percentile(lat, 50))
+        out["p99_ms"] = float(np.percentile(lat, 99))
+        if not a.no_mixed:
+            mp = air.Plan(g, max_batch=B, precision="mixed_f16")
+            wall_m, lat_m = timed_steps(torch, mp, y, w, a.steps, a.warmup, ws)
+            out["mixed"] = {"precision": "mixed_f16 (ramp as f16 hi/lo MFMA)", "value": B * a.steps / wall_m,
+                            "ms_per_step": 1e3 * wall_m / a.steps, "p50_ms": float(np.percentile(lat_m, 50)),
+                            "p99_ms": float(np.percentile(lat_m, 99))}
+            del mp
+
+    # instrumented pass: one more step with every kernel bracketed by HIP events
+    plan.kernel_timing(True)
+    plan.solve(y, w.lam, w.mu, w.n_outer, w.n_cg, workspace=ws, with_resid=False)
+    kt = plan.collect_kernel_timing()
+    plan.kernel_timing(False)
+    kernel_ms = {k: {"avg_ms": (v[0] / v[1]) if v[1] else 0.0, "launches": v[1], "total_ms": v[0]}
+                 for k, v in kt.items()}
+    out["kernel_ms"] = kernel_ms
+    rays = B * g.n_views * g.n_bins
+    t_proj = kernel_ms["project"]["avg_ms"] * 1e-3
+    t_bp = kernel_ms["backproject"]["avg_ms"] * 1e-3
+    out["proj_grays_s"] = rays / t_proj / 1e9 if t_proj else None
+    out["backproj_grays_s"] = rays / t_bp / 1e9 if t_bp else None
+
+    # roofline of the dominant kernel; projector bytes = the traffic of the explicit
+    # sparse matrix A (one 4-byte image sample per nonzero, 2 per ray-step) + the sinogram
+    dom = max(("project", "backproject", "ramp"), key=lambda k: kernel_ms[k]["total_ms"])
+    t_dom = kernel_ms[dom]["avg_ms"] * 1e-3
+    if dom == "ramp":
+        flops = 2.0 * B * g.n_views * g.n_bins * g.n_bins
+        achieved = flops / t_dom / 1e12
+        roof = {"kernel": "k_ramp_f32", "bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK_TFLOPS["fp32"],
+                "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK_TFLOPS["fp32"]}
+    else:
+        if dom == "project":
+            bytes_alg = B * (8.0 * rsteps + 4.0 * g.n_views * g.n_bins)
+            kname = "k_project"
+        else:
+            bytes_alg = B * (8.0 * rsteps + 4.0 * g.n * g.n)
+            kname = "k_backproject"
+        achieved = bytes_alg / t_dom / 1e9
+        roof = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": bytes_alg, "avg_launch_ms": t_dom * 1e3,
+                "ray_steps_per_image": rsteps}
+    roof["traffic"] = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        ent = tr.get(roof["kernel"])
+        if ent and ent.get("source_hash") == kernel_source_hash() and ent.get("batch") == B:
+            roof["traffic"] = ent["bytes_per_launch"]
+    out["roofline"] = roof
+    out["kernel_source_hash"] = kernel_source_hash()
+
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, ys[0])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * air.h -- C ABI of the MI355X (gfx950) AIR reconstruction library.
+ *
+ * AIR, the fused analytical and iterative reconstruction of arXiv 1310.1434,
+ * minimises ||P(AX - Y)||^2 + lambda R(X) with P^T P = C, the analytic
+ * method's filtration (Methods, Eq. (1)-(3)).  Its solvers only ever need
+ * A, the filtered adjoint A'^T = A^T C (Methods, text before Eq. (5)) and,
+ * for R = ||W X||_1 with a tensor framelet W (Materials), the split Bregman
+ * L2 step, solved like Eq. (5).  This library runs exactly that hot path on
+ * one GPU with hand-written HIP kernels.
+ *
+ * Conventions
+ *   - Every function returns air_status; AIR_OK is 0.  On failure
+ *     air_last_error() gives a thread-local message.  No C++ exception
+ *     crosses the ABI.  Argument checks happen before any GPU work is
+ *     queued, so they need no GPU.
+ *   - The library never allocates device memory.  The caller owns every
+ *     device buffer (inputs, outputs and workspaces) and passes plain device
+ *     pointers; host pointers are marked "host".
+ *   - Work is queued on the caller's hipStream_t (0 = the legacy default
+ *     stream) and is asynchronous unless stated otherwise.  Calls that use
+ *     the same plan workspace must be ordered on one stream.
+ *   - Layouts are row-major, last index fastest, batch outermost:
+ *       image    X[b][j][i]       j = row (y), i = column (x), n x n
+ *       sinogram Y[b][v][k]       v = view, k = detector bin
+ *       framelet Z[b][band][j][i] band = 3 m_y + m_x, band 0 = low-pass
+ *     All are float32.
+ *
+ * Geometry (shared with the scan model the inputs come from)
+ *   pixel (i, j) centre: ((i - (n-1)/2) pixel, (j - (n-1)/2) pixel)
+ *   bin k: u_k = (k - (n_bins-1)/2) bin
+ *   parallel beam, view (c, s) = (cos, sin):  ray through u_k (c, s), direction (-s, c)
+ *   flat fan beam: source sod (c, s), ray direction (-sdd c - u_k s, -sdd s + u_k c)
+ *   The view cosines/sines are passed in (float64, host) so the caller's
+ *   angle set is used bit for bit.
+ */
+#ifndef AIR_H
+#define AIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AIR_OK = 0,
+    AIR_E_INVALID = -1,      /* bad argument (null pointer, size, geometry, batch > max_batch) */
+    AIR_E_UNSUPPORTED = -2,  /* valid but outside what the kernels handle (e.g. n > 16384) */
+    AIR_E_NOMEM = -3,        /* workspace too small, or host allocation failed */
+    AIR_E_HIP = -4,          /* a HIP call failed (message holds hipGetErrorString) */
+    AIR_E_NONFINITE = -5     /* a solve produced a non-finite residual */
+} air_status;
+
+typedef enum { AIR_PARALLEL = 0, AIR_FAN_FLAT = 1 } air_beam;
+
+/* Arithmetic of the ramp filtration (the only dense contraction on the path).
+ *   AIR_FP32        float32 MFMA (v_mfma_f32_16x16x4f32), float32 accumulation
+ *   AIR_MIXED_F16   float16 MFMA on a hi/lo split of sinogram and filter,
+ *                   three products, float32 accumulation
+ *   AIR_MIXED_BF16  bfloat16 MFMA on a three-way split, six products,
+ *                   float32 accumulation
+ * Projectors and vectors are float32 in all modes; CG inner products, the
+ * step sizes alpha/beta and the Bregman residual norm are float64. */
+typedef enum { AIR_FP32 = 0, AIR_MIXED_F16 = 1, AIR_MIXED_BF16 = 2 } air_precision;
+
+typedef struct {
+    air_beam beam;
+    int32_t n;                 /* image is n x n, 1 <= n <= 16384 */
+    double pixel_mm;           /* pixel side > 0 */
+    int32_t n_views;           /* >= 1 */
+    const double* view_cos;    /* host, [n_views]; copied at plan creation */
+    const double* view_sin;    /* host, [n_views]; copied at plan creation */
+    int32_t n_bins;            /* 1 <= n_bins <= 8192 */
+    double bin_mm;             /* detector pitch > 0 */
+    double sod_mm, sdd_mm;     /* fan beam: 0 < sod < sdd; ignored for parallel beam */
+} air_geometry;
+
+typedef struct air_plan_s* air_plan;
+
+/* Create a plan: validates the geometry and builds, on the host in float64,
+ * the per-ray Joseph tables (driving axis, index range, intercept, slope,
+ * step length) and the ramp taps.  Nothing touches the GPU.
+ * max_batch bounds the batch of the operator calls that use the plan's
+ * workspace (air_project, air_filtered_backproject, air_ramp,
+ * air_normal_apply).  flags must be 0. */
+air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_precision prec,
+                           uint32_t flags, air_plan* out);
+
+/* Device bytes the plan needs: tables, taps and operator scratch for max_batch. */
+air_status air_plan_workspace_size(air_plan plan, size_t* bytes);
+
+/* Hand the plan its workspace (device, 256-byte aligned, >= workspace_size
+ * bytes, caller-owned, must outlive the plan's use) and upload the tables.
+ * Synchronises `stream` once (the host tables are copied before returning). */
+air_status air_plan_bind_workspace(air_plan plan, void* dev_ptr, size_t bytes, hipStream_t stream);
+
+/* Host copies of the index tables, each [n_views * n_bins]:
+ *   axis 0 = x-driven (steps over columns), 1 = y-driven;
+ *   lo/hi = first/last driving index whose intercept t satisfies -1 < t < n,
+ *   evaluated in float64 without fused multiply-add; (0, -1) if none.
+ * Any pointer may be NULL. */
+air_status air_plan_tables(air_plan plan, int8_t* axis, int32_t* lo, int32_t* hi);
+
+void air_plan_destroy(air_plan plan);
+
+/* y = A x: Joseph projection (ray-driven, linear interpolation along the
+ * non-driving axis, times pixel |d| / |d_drive|).  x [batch][n][n] -> y [batch][V][D].
+ * 1 <= batch <= max_batch. */
+air_status air_project(air_plan plan, const float* x, float* y, int32_t batch, hipStream_t stream);
+
+/* y' = C y, C = kappa R per view, R the symmetric Toeplitz Ram-Lak matrix
+ * (r(0) = 1/4, r(odd m) = -1/(pi m)^2, r(even m != 0) = 0), kappa =
+ * pi / (n_views pixel^2); linear convolution truncated to the detector
+ * (paper: Methods, Eq. (2): C is a filtration diagonal in Fourier space).
+ * In-place (y == yf) is not allowed. */
+air_status air_ramp(air_plan plan, const float* y, float* yf, int32_t batch, hipStream_t stream);
+
+/* x = A'^T y = A^T C y (filter = 1, the filtered adjoint of AIR), or the plain
+ * adjoint x = A^T y (filter = 0, the IR arm).  A^T is the matched transpose of
+ * air_project, computed per pixel (gather form, no atomics).
+ * y [batch][V][D] -> x [batch][n][n]. */
+air_status air_filtered_backproject(air_plan plan, const float* y, float* x, int32_t batch,
+                                    int32_t filter, hipStream_t stream);
+
+/* out = A^T C A x + mu x (filter = 1) or A^T A x + mu x (filter = 0): the
+ * operator of Eq. (5) and of the split Bregman L2 step.  out != x. */
+air_status air_normal_apply(air_plan plan, const float* x, float* out, int32_t batch, double mu,
+                            int32_t filter, hipStream_t stream);
+
+/* Tensor framelet (Materials): one level, undecimated, periodic boundary,
+ * filters h0 = [1,2,1]/4, h1 = sqrt2 [1,0,-1]/4, h2 = [-1,2,-1]/4 (correlation
+ * form, taps at offsets -1, 0, +1); band (m_y, m_x) applies h_{m_y} along
+ * rows' index j and h_{m_x} along i.
+ *   adjoint = 0: out[b][9][n][n] = W in[b][n][n]
+ *   adjoint = 1: out[b][n][n] = W^T in[b][9][n][n]       (W^T W = I)
+ * Uses no plan workspace (batch is not bounded by max_batch). */
+air_status air_framelet(air_plan plan, const float* in, float* out, int32_t batch, int32_t adjoint,
+                        hipStream_t stream);
+
+typedef struct {
+    double lambda;     /* framelet weight (reg = 0) or L2 weight of Eq. (5) (reg = 1), >= 0 */
+    double mu;         /* Bregman penalty, > 0 (unused for reg = 1) */
+    int32_t n_outer;   /* Bregman iterations, >= 0 (unused for reg = 1) */
+    int32_t n_cg;      /* CG steps per L2 sub-problem, >= 0 */
+    int32_t reg;       /* 0 = tensor framelet via split Bregman, 1 = L2 (Eq. (5)) */
+    int32_t filter;    /* 1 = AIR (A'^T = A^T C), 0 = IR (A^T) */
+} air_solve_params;
+
+/* Device bytes of the solve workspace for `batch` reconstructions. */
+air_status air_solve_workspace_size(air_plan plan, int32_t batch, size_t* bytes);
+
+/* Reconstruct `batch` independent images from Y [batch][V][D].
+ * X [batch][n][n] holds the start image on entry (zeros for the standard
+ * start) and the result on exit.  Split Bregman (reg = 0):
+ *   g = A'^T Y;  d = b = 0
+ *   n_outer times:  X <- n_cg CG steps on (A'^T A + mu I) X = g + mu W^T (d - b),
+ *                   started from X (a fresh CG each time);
+ *                   v = W X + b; d = shrink(v, lambda / (2 mu)) on bands 1..8,
+ *                   d = v on band 0; b = v - d
+ * L2 (reg = 1): n_cg CG steps on (A'^T A + lambda I) X = A'^T Y from X.
+ * resid (device, may be NULL) receives [batch][n_outer] float64 ||W X - d||_2.
+ * ws: device, >= air_solve_workspace_size(plan, batch) bytes, 256-byte
+ * aligned; it is scratch for this call only.  The plan's own workspace is
+ * not used, so batch may exceed max_batch. */
+air_status air_solve(air_plan plan, const float* Y, float* X, int32_t batch, const air_solve_params* p,
+                     double* resid, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Per-kernel timing (measurement support).  While enabled on a plan, every
+ * kernel launch that plan makes (operators and air_solve) is bracketed by a
+ * pair of HIP events on the launch stream.  air_kernel_timing_collect waits
+ * for the recorded events and adds their elapsed times to *stats, then
+ * forgets them.  Kinds index air_kernel_stats' arrays. */
+typedef enum {
+    AIR_K_PROJECT = 0,      /* Joseph forward projector */
+    AIR_K_BACKPROJECT = 1,  /* gather-form matched backprojector (all epilogues) */
+    AIR_K_RAMP = 2,         /* Toeplitz ramp GEMM (MFMA) */
+    AIR_K_CG = 3,           /* CG vector updates */
+    AIR_K_FRAMELET = 4,     /* framelet, shrink and right-hand side */
+    AIR_K_OTHER = 5,        /* padded copies, repacking, fills */
+    AIR_K_COUNT = 6
+} air_kernel_kind;
+typedef struct {
+    double ms[AIR_K_COUNT];        /* summed kernel time */
+    int64_t launches[AIR_K_COUNT]; /* number of launches */
+} air_kernel_stats;
+air_status air_kernel_timing_enable(air_plan plan, int32_t enable);
+air_status air_kernel_timing_collect(air_plan plan, air_kernel_stats* stats /* host */);
+
+/* Thread-local message of the last failure on this thread ("" if none). */
+const char* air_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

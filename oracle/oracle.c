@@ -99,6 +99,7 @@ static double img_at(const double* x, int n, int axis, int a, int b) {
 int orc_tables(const orc_geom* g, int8_t* axis, int32_t* lo, int32_t* hi) {
     if (!geom_ok(g) || !axis || !lo || !hi) return -1;
     const int n = g->n;
+#pragma omp parallel for schedule(dynamic, 4)
     for (int v = 0; v < g->n_views; v++) {
         for (int k = 0; k < g->n_bins; k++) {
             const orc_ray r = make_ray(g, v, k);

@@ -1,0 +1,253 @@
+"""ctypes binding of libair.so, the MI355X AIR library (C ABI in include/air.h).
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+kernels of libair.so.  torch provides device memory and streams; tensors are
+passed as raw device pointers on the current torch stream.  There is no CPU
+fallback: if libair.so is missing this module raises at import time.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libair.so")
+
+AIR_OK, AIR_E_INVALID, AIR_E_UNSUPPORTED, AIR_E_NOMEM, AIR_E_HIP, AIR_E_NONFINITE = 0, -1, -2, -3, -4, -5
+PRECISIONS = {"fp32": 0, "mixed_f16": 1, "mixed_bf16": 2}
+
+
+class AirError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+class _Geometry(ctypes.Structure):
+    _fields_ = [("beam", ctypes.c_int), ("n", ctypes.c_int32), ("pixel_mm", ctypes.c_double),
+                ("n_views", ctypes.c_int32), ("view_cos", ctypes.c_void_p), ("view_sin", ctypes.c_void_p),
+                ("n_bins", ctypes.c_int32), ("bin_mm", ctypes.c_double), ("sod_mm", ctypes.c_double),
+                ("sdd_mm", ctypes.c_double)]
+
+
+class _SolveParams(ctypes.Structure):
+    _fields_ = [("lam", ctypes.c_double), ("mu", ctypes.c_double), ("n_outer", ctypes.c_int32),
+                ("n_cg", ctypes.c_int32), ("reg", ctypes.c_int32), ("filter", ctypes.c_int32)]
+
+
+KERNEL_KINDS = ("project", "backproject", "ramp", "cg", "framelet", "other")
+
+
+class _KernelStats(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * len(KERNEL_KINDS)), ("launches", ctypes.c_int64 * len(KERNEL_KINDS))]
+
+
+# Every symbol include/air.h declares, with its ctypes signature.
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+SIGNATURES = {
+    "air_plan_create": ([ctypes.POINTER(_Geometry), _I, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(_P)], ctypes.c_int),
+    "air_plan_workspace_size": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "air_plan_bind_workspace": ([_P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "air_plan_tables": ([_P, _P, _P, _P], ctypes.c_int),
+    "air_plan_destroy": ([_P], None),
+    "air_project": ([_P, _P, _P, _I, _P], ctypes.c_int),
+    "air_ramp": ([_P, _P, _P, _I, _P], ctypes.c_int),
+    "air_filtered_backproject": ([_P, _P, _P, _I, _I, _P], ctypes.c_int),
+    "air_normal_apply": ([_P, _P, _P, _I, ctypes.c_double, _I, _P], ctypes.c_int),
+    "air_framelet": ([_P, _P, _P, _I, _I, _P], ctypes.c_int),
+    "air_solve_workspace_size": ([_P, _I, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "air_solve": ([_P, _P, _P, _I, ctypes.POINTER(_SolveParams), _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "air_kernel_timing_enable": ([_P, _I], ctypes.c_int),
+    "air_kernel_timing_collect": ([_P, ctypes.POINTER(_KernelStats)], ctypes.c_int),
+    "air_last_error": ([], ctypes.c_char_p),
+}
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1310_1434_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _check(status: int, where: str):
+    if status != AIR_OK:
+        raise AirError(status, where, lib.air_last_error().decode())
+
+
+def _stream(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_f32(t: torch.Tensor, device, shape, name):
+    if not isinstance(t, torch.Tensor) or t.device != device or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 tensor on {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _geometry_struct(geom):
+    cos = np.ascontiguousarray(geom.view_cos, dtype=np.float64)
+    sin = np.ascontiguousarray(geom.view_sin, dtype=np.float64)
+    g = _Geometry(0 if geom.beam == "parallel" else 1, int(geom.n), float(geom.pixel), int(geom.n_views),
+                  cos.ctypes.data, sin.ctypes.data, int(geom.n_bins), float(geom.bin),
+                  float(getattr(geom, "sod", 0.0)), float(getattr(geom, "sdd", 0.0)))
+    return g, (cos, sin)
+
+
+def host_tables(geom):
+    """Index tables of a geometry, built on the host (no GPU needed):
+    (axis int8, lo int32, hi int32), each [n_views, n_bins]."""
+    g, keep = _geometry_struct(geom)
+    h = ctypes.c_void_p()
+    _check(lib.air_plan_create(ctypes.byref(g), 1, 0, 0, ctypes.byref(h)), "air_plan_create")
+    try:
+        nr = int(geom.n_views) * int(geom.n_bins)
+        axis = np.empty(nr, np.int8)
+        lo = np.empty(nr, np.int32)
+        hi = np.empty(nr, np.int32)
+        _check(lib.air_plan_tables(h, axis.ctypes.data, lo.ctypes.data, hi.ctypes.data), "air_plan_tables")
+    finally:
+        lib.air_plan_destroy(h)
+    s = (int(geom.n_views), int(geom.n_bins))
+    return axis.reshape(s), lo.reshape(s), hi.reshape(s)
+
+
+class Plan:
+    """A scan geometry with its device tables.
+
+    ``geom`` is any object with the fields beam ("parallel"/"fan"), n, pixel,
+    n_views, n_bins, bin, sod, sdd, view_cos, view_sin (float64 arrays).
+    """
+
+    def __init__(self, geom, max_batch: int = 1, precision: str = "fp32", device="cuda:0"):
+        self.device = torch.device(device)
+        self.n, self.n_views, self.n_bins = int(geom.n), int(geom.n_views), int(geom.n_bins)
+        self.precision = precision
+        self.max_batch = int(max_batch)
+        g, self._keep = _geometry_struct(geom)
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        h = ctypes.c_void_p()
+        _check(lib.air_plan_create(ctypes.byref(g), self.max_batch, PRECISIONS[precision], 0, ctypes.byref(h)),
+               "air_plan_create")
+        self._h = h
+        size = ctypes.c_size_t()
+        _check(lib.air_plan_workspace_size(h, ctypes.byref(size)), "air_plan_workspace_size")
+        self._ws = torch.empty(max(int(size.value), 256), dtype=torch.uint8, device=self.device)
+        _check(lib.air_plan_bind_workspace(h, ctypes.c_void_p(self._ws.data_ptr()), size.value,
+                                           _stream(self.device)), "air_plan_bind_workspace")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.air_plan_destroy(h)
+            self._h = None
+
+    # ---- per-kernel event timing
+    def kernel_timing(self, enable: bool) -> None:
+        _check(lib.air_kernel_timing_enable(self._h, int(bool(enable))), "air_kernel_timing_enable")
+
+    def collect_kernel_timing(self) -> dict:
+        """{kind: (total_ms, launches)} for the launches recorded since the last collect."""
+        st = _KernelStats()
+        _check(lib.air_kernel_timing_collect(self._h, ctypes.byref(st)), "air_kernel_timing_collect")
+        return {k: (st.ms[i], int(st.launches[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+    # ---- host tables
+    def tables(self):
+        nr = self.n_views * self.n_bins
+        axis = np.empty(nr, np.int8)
+        lo = np.empty(nr, np.int32)
+        hi = np.empty(nr, np.int32)
+        _check(lib.air_plan_tables(self._h, axis.ctypes.data, lo.ctypes.data, hi.ctypes.data), "air_plan_tables")
+        s = (self.n_views, self.n_bins)
+        return axis.reshape(s), lo.reshape(s), hi.reshape(s)
+
+    # ---- operators (batch = leading dimension)
+    def _img(self, x, name="x"):
+        return _dev_f32(x, self.device, (x.shape[0], self.n, self.n), name)
+
+    def _sino(self, y, name="y"):
+        return _dev_f32(y, self.device, (y.shape[0], self.n_views, self.n_bins), name)
+
+    def project(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        b = x.shape[0]
+        y = out if out is not None else torch.empty((b, self.n_views, self.n_bins), device=self.device)
+        _check(lib.air_project(self._h, self._img(x), self._sino(y, "out"), b, _stream(self.device)), "air_project")
+        return y
+
+    def ramp(self, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        b = y.shape[0]
+        yf = out if out is not None else torch.empty_like(y)
+        _check(lib.air_ramp(self._h, self._sino(y), self._sino(yf, "out"), b, _stream(self.device)), "air_ramp")
+        return yf
+
+    def filtered_backproject(self, y: torch.Tensor, filter: int = 1, out: torch.Tensor | None = None) -> torch.Tensor:
+        b = y.shape[0]
+        x = out if out is not None else torch.empty((b, self.n, self.n), device=self.device)
+        _check(lib.air_filtered_backproject(self._h, self._sino(y), self._img(x, "out"), b, int(filter),
+                                            _stream(self.device)), "air_filtered_backproject")
+        return x
+
+    def normal_apply(self, x: torch.Tensor, mu: float, filter: int = 1, out=None) -> torch.Tensor:
+        b = x.shape[0]
+        o = out if out is not None else torch.empty_like(x)
+        _check(lib.air_normal_apply(self._h, self._img(x), self._img(o, "out"), b, float(mu), int(filter),
+                                    _stream(self.device)), "air_normal_apply")
+        return o
+
+    def framelet(self, x: torch.Tensor) -> torch.Tensor:
+        b = x.shape[0]
+        z = torch.empty((b, 9, self.n, self.n), device=self.device)
+        _check(lib.air_framelet(self._h, self._img(x), ctypes.c_void_p(z.data_ptr()), b, 0, _stream(self.device)),
+               "air_framelet")
+        return z
+
+    def framelet_adjoint(self, z: torch.Tensor) -> torch.Tensor:
+        b = z.shape[0]
+        _dev_f32(z, self.device, (b, 9, self.n, self.n), "z")
+        x = torch.empty((b, self.n, self.n), device=self.device)
+        _check(lib.air_framelet(self._h, ctypes.c_void_p(z.data_ptr()), self._img(x, "out"), b, 1,
+                                _stream(self.device)), "air_framelet")
+        return x
+
+    # ---- solver
+    def solve_workspace_bytes(self, batch: int) -> int:
+        size = ctypes.c_size_t()
+        _check(lib.air_solve_workspace_size(self._h, int(batch), ctypes.byref(size)), "air_solve_workspace_size")
+        return int(size.value)
+
+    def solve(self, y: torch.Tensor, lam: float, mu: float, n_outer: int, n_cg: int, reg: int = 0,
+              filter: int = 1, x0: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+              with_resid: bool = True):
+        """Split Bregman AIR (reg=0) or the L2 problem of Eq. (5) (reg=1).
+
+        Returns (X [B, n, n], resid [B, n_outer] float64 or None); asynchronous
+        on the current stream."""
+        b = y.shape[0]
+        x = torch.zeros((b, self.n, self.n), device=self.device) if x0 is None else x0.clone()
+        need = self.solve_workspace_bytes(b)
+        ws = workspace if workspace is not None else torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        if ws.numel() < need:
+            raise ValueError("workspace too small")
+        resid = torch.zeros((b, max(n_outer, 1)), dtype=torch.float64, device=self.device) if with_resid else None
+        p = _SolveParams(float(lam), float(mu), int(n_outer), int(n_cg), int(reg), int(filter))
+        _check(lib.air_solve(self._h, self._sino(y), self._img(x), b, ctypes.byref(p),
+                             ctypes.c_void_p(resid.data_ptr()) if resid is not None else None,
+                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(self.device)), "air_solve")
+        if resid is not None:
+            resid = resid[:, :n_outer]
+        return x, resid

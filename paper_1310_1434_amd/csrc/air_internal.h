@@ -1,0 +1,118 @@
+// Internal declarations of the AIR library: plan layout, kernel parameter
+// blocks and kernel launchers.  Not part of the ABI.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "air.h"
+#include "geometry.h"
+
+namespace air {
+
+// Geometry block passed by value to the projector kernels.
+struct KGeom {
+    int n;          // image side
+    int n_views;
+    int n_bins;
+    int ds;         // sinogram row stride of internal buffers (n_bins rounded up to 32)
+    int line;       // padded image line length, n + 2 kPad
+    int c0;         // reference driving index of the intercept tables (n / 2)
+    int beam;       // 0 parallel, 1 fan
+    float pixel;    // mm
+    float half_n;   // (n - 1) / 2
+    float inv_bin;  // 1 / bin (1/mm)
+    float half_d;   // (n_bins - 1) / 2
+    float sod, sdd; // fan geometry, mm
+    const RayEntry* rays;   // [n_views][n_bins]
+    const float2* views;    // [n_views] (cos, sin) as float
+};
+
+// Per-launch description of where an image batch and its padded copies live.
+struct PadBuf {
+    float* base;    // [batch][2][n][line]: line set 0 = columns (for x-driven rays), 1 = rows
+};
+
+// ---- kernel launchers (kernels_*.hip) -------------------------------------------------
+hipError_t launch_pad(const KGeom& g, const float* x, PadBuf pad, int batch, hipStream_t s);
+hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, hipStream_t s);
+
+// Backprojection epilogue modes (per pixel, acc = (A^T y)_pixel):
+enum BpMode {
+    BP_PLAIN = 0,     // out = acc
+    BP_MATVEC = 1,    // out = acc + mu * p;  scalar pq[b] = p . out   (float64)
+    BP_RESIDUAL = 2,  // r = rhs - (acc + mu * x) (rhs read from `out`, r written there);
+                      // p = r, padded copy of p; scalar rr[b] = r . r
+};
+struct BpArgs {
+    int mode;
+    float mu;
+    const float* aux;   // p (MATVEC) or x (RESIDUAL)
+    float* out;         // [batch][n][n]
+    float* p_out;       // RESIDUAL: p
+    PadBuf pad_out;     // RESIDUAL: padded copy of p
+    double* red_partial;    // [batch][blocks] float64 partial sums
+    unsigned* red_count;    // [batch] arrival counters (zero on entry, re-zeroed by the last block)
+    double* red_out;        // [batch] reduced scalar
+};
+hipError_t launch_backproject(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s);
+
+// Sinogram repacking between the public [V][D] layout and internal [V][ds] rows.
+hipError_t launch_repack(const float* src, int src_stride, float* dst, int dst_stride, int rows, int cols,
+                         int dst_cols, hipStream_t s);
+
+// Ramp filtration y' = C y over rows of stride ds (internal layout).
+struct RampTables {
+    const float* taps32;       // [2 ds] kappa r(m) at index m + ds
+    const uint4* frag_a;       // 16-bit fragments, first split term (f16 hi / bf16 t1)
+    const uint4* frag_b;       // second split term (f16 lo / bf16 t2)
+    const uint4* frag_c;       // third split term (bf16 t3), or null
+    int n_frag;                // fragments per term (indexed by (k0 - n0 - dmin) / 16)
+    int dmin;
+    float out_scale;           // kappa * 2^-12 for the 16-bit modes
+};
+hipError_t launch_ramp(int prec, const RampTables& t, const float* y, float* yf, int rows, int ds,
+                       hipStream_t s);
+
+// CG vector updates on 16x16 tiles (float32 vectors, float64 scalars).
+struct CgArgs {
+    int n;
+    float* x; float* r; float* p; const float* q;
+    PadBuf pad;                 // padded copy target (x or p), or base = null
+    const double* rho_cur;      // [batch]
+    const double* pq;           // [batch]
+    const double* rho_new_in;   // [batch] (update_p)
+    double* red_partial; unsigned* red_count; double* red_out;
+};
+hipError_t launch_cg_update_xr(const CgArgs& a, int batch, hipStream_t s);   // x += a p, r -= a q, rho' = r.r
+hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s);    // p = r + b p (+ pad)
+
+// Framelet kernels.
+hipError_t launch_framelet_fwd(int n, const float* x, float* z, int batch, hipStream_t s);
+hipError_t launch_framelet_adj(int n, const float* z, float* x, int batch, hipStream_t s);
+// rhs = g + mu W^T e
+hipError_t launch_tf_rhs(int n, const float* g, const float* e, float mu, float* rhs, int batch, hipStream_t s);
+// v = W x + b (bands 1..8 of b), d = shrink(v, thr) (band 0: d = v), b <- v - d, e <- d - b,
+// resid[b] = ||W x - d||_2 (float64, written at resid + b * resid_stride when resid != null)
+struct TfArgs {
+    int n;
+    const float* x;
+    float* bb;          // [batch][8][n][n]
+    float* e;           // [batch][9][n][n]
+    float thr;
+    double* red_partial; unsigned* red_count; double* red_out;
+    double* resid; int resid_stride;
+};
+hipError_t launch_tf_shrink(const TfArgs& a, int batch, hipStream_t s);
+hipError_t launch_fill(float* p, size_t count, float v, hipStream_t s);
+hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t s);
+
+// Number of 16x16 tiles of an n x n image (blocks per batch item of tile kernels).
+inline int tiles16(int n) { return ((n + 15) / 16) * ((n + 15) / 16); }
+
+}  // namespace air

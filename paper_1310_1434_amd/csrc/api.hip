@@ -1,0 +1,672 @@
+// C ABI of the AIR library: plans, operator entry points and the split
+// Bregman solver.  Host code; all arithmetic runs in the kernels.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "air_internal.h"
+
+using namespace air;
+
+namespace {
+
+thread_local std::string g_err;
+
+air_status fail(air_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define AIR_HIP(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(AIR_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    }
+};
+
+// float -> IEEE half, round to nearest even (host side, for the filter fragments)
+uint16_t f32_to_f16(float f) {
+    uint32_t x;
+    std::memcpy(&x, &f, 4);
+    const uint32_t sign = (x >> 16) & 0x8000u;
+    const uint32_t e8 = (x >> 23) & 0xffu;
+    uint32_t mant = x & 0x7fffffu;
+    if (e8 == 0xffu) return (uint16_t)(sign | 0x7c00u | (mant ? 0x200u : 0u));
+    const int exp = (int)e8 - 127 + 15;
+    if (exp >= 31) return (uint16_t)(sign | 0x7c00u);
+    if (exp <= 0) {
+        if (exp < -10) return (uint16_t)sign;
+        mant |= 0x800000u;
+        const int shift = 14 - exp;
+        uint32_t hm = mant >> shift;
+        const uint32_t rem = mant & ((1u << shift) - 1u), half = 1u << (shift - 1);
+        if (rem > half || (rem == half && (hm & 1u))) hm++;
+        return (uint16_t)(sign | hm);
+    }
+    uint32_t h = sign | ((uint32_t)exp << 10) | (mant >> 13);
+    const uint32_t rem = mant & 0x1fffu;
+    if (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) h++;
+    return (uint16_t)h;
+}
+
+float f16_to_f32(uint16_t h) {
+    const uint32_t sign = (uint32_t)(h & 0x8000u) << 16;
+    const int e = (h >> 10) & 0x1f;
+    const uint32_t m = h & 0x3ffu;
+    float v;
+    if (e == 0) v = std::ldexp((float)m, -24);
+    else if (e == 31) v = m ? NAN : INFINITY;
+    else v = std::ldexp((float)(m | 0x400u), e - 25);
+    uint32_t x;
+    std::memcpy(&x, &v, 4);
+    x |= sign;
+    std::memcpy(&v, &x, 4);
+    return v;
+}
+
+uint16_t f32_to_bf16(float f) {
+    uint32_t x;
+    std::memcpy(&x, &f, 4);
+    if ((x & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((x >> 16) | 0x40u);
+    x += 0x7fffu + ((x >> 16) & 1u);
+    return (uint16_t)(x >> 16);
+}
+
+float bf16_to_f32(uint16_t h) {
+    const uint32_t x = (uint32_t)h << 16;
+    float v;
+    std::memcpy(&v, &x, 4);
+    return v;
+}
+
+}  // namespace
+
+struct air_plan_s {
+    GeomHost g;
+    int max_batch = 1;
+    air_precision prec = AIR_FP32;
+    int ds = 0, line = 0, c0 = 0;
+    double kappa = 0.0;
+    std::vector<RayEntry> rays;
+    std::vector<int8_t> axis;
+    std::vector<int32_t> lo, hi;
+    std::vector<float> views;      // interleaved (cos, sin) as float
+    std::vector<float> taps32;     // [2 ds]
+    std::vector<uint16_t> frag[3];
+    int n_terms = 0, n_frag = 0, dmin = 0;
+    // workspace layout (bytes)
+    size_t off_rays = 0, off_views = 0, off_taps = 0, off_frag[3] = {0, 0, 0};
+    size_t off_pad = 0, off_s1 = 0, off_s2 = 0, off_part = 0, off_cnt = 0, off_scal = 0, total = 0;
+    char* ws = nullptr;
+    // per-kernel event timing (air_kernel_timing_enable)
+    struct Timed {
+        int kind;
+        hipEvent_t a, b;
+    };
+    bool timing = false;
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> pool;
+
+    ~air_plan_s() {
+        for (const Timed& t : pending) {
+            (void)hipEventDestroy(t.a);
+            (void)hipEventDestroy(t.b);
+        }
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+    hipEvent_t take_event() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+
+    KGeom kgeom() const {
+        KGeom k;
+        k.n = g.n;
+        k.n_views = g.n_views;
+        k.n_bins = g.n_bins;
+        k.ds = ds;
+        k.line = line;
+        k.c0 = c0;
+        k.beam = g.beam;
+        k.pixel = (float)g.pixel;
+        k.half_n = (float)(0.5 * (g.n - 1));
+        k.inv_bin = (float)(1.0 / g.bin);
+        k.half_d = (float)(0.5 * (g.n_bins - 1));
+        k.sod = (float)g.sod;
+        k.sdd = (float)g.sdd;
+        k.rays = reinterpret_cast<const RayEntry*>(ws + off_rays);
+        k.views = reinterpret_cast<const float2*>(ws + off_views);
+        return k;
+    }
+    RampTables ramp_tables() const {
+        RampTables t;
+        t.taps32 = reinterpret_cast<const float*>(ws + off_taps);
+        t.frag_a = n_terms > 0 ? reinterpret_cast<const uint4*>(ws + off_frag[0]) : nullptr;
+        t.frag_b = n_terms > 1 ? reinterpret_cast<const uint4*>(ws + off_frag[1]) : nullptr;
+        t.frag_c = n_terms > 2 ? reinterpret_cast<const uint4*>(ws + off_frag[2]) : nullptr;
+        t.n_frag = n_frag;
+        t.dmin = dmin;
+        t.out_scale = (float)(kappa / 4096.0);
+        return t;
+    }
+    template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+    bool direct(const void* p) const { return g.n_bins == ds && (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+};
+
+namespace {
+
+// Brackets one kernel launch with events when timing is enabled on the plan.
+struct KTimer {
+    air_plan_s* p;
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    KTimer(air_plan_s* p_, int kind_, hipStream_t s_) : p(p_), kind(kind_), s(s_) {
+        if (p->timing) {
+            a = p->take_event();
+            b = p->take_event();
+            if (a && b && hipEventRecord(a, s) != hipSuccess) a = nullptr;
+        }
+    }
+    void done() {
+        if (a && b && hipEventRecord(b, s) == hipSuccess) p->pending.push_back({kind, a, b});
+    }
+};
+
+#define AIR_K(kind, expr)             \
+    do {                              \
+        KTimer t_(p, kind, s);        \
+        AIR_HIP(expr);                \
+        t_.done();                    \
+    } while (0)
+
+air_status check_plan(air_plan p, bool need_ws) {
+    if (!p) return fail(AIR_E_INVALID, "plan is null");
+    if (need_ws && !p->ws) return fail(AIR_E_INVALID, "plan has no workspace bound");
+    return AIR_OK;
+}
+
+air_status check_batch(air_plan p, int32_t batch, bool bounded) {
+    if (batch < 1) return fail(AIR_E_INVALID, "batch must be >= 1");
+    if (bounded && batch > p->max_batch) return fail(AIR_E_INVALID, "batch exceeds the plan's max_batch");
+    return AIR_OK;
+}
+
+// y (public stride n_bins) -> internal rows of stride ds, unless it can be read in place.
+air_status stage_sino(air_plan p, const float* y, int32_t batch, float* scratch, const float** out, hipStream_t s) {
+    if (p->direct(y)) {
+        *out = y;
+        return AIR_OK;
+    }
+    const int rows = batch * p->g.n_views;
+    AIR_K(AIR_K_OTHER, launch_repack(y, p->g.n_bins, scratch, p->ds, rows, p->g.n_bins, p->ds, s));
+    *out = scratch;
+    return AIR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* air_last_error(void) { return g_err.c_str(); }
+
+air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_precision prec, uint32_t flags,
+                           air_plan* out) {
+    if (!out) return fail(AIR_E_INVALID, "out is null");
+    *out = nullptr;
+    if (!geom) return fail(AIR_E_INVALID, "geometry is null");
+    if (flags != 0) return fail(AIR_E_INVALID, "flags must be 0");
+    if (geom->beam != AIR_PARALLEL && geom->beam != AIR_FAN_FLAT) return fail(AIR_E_INVALID, "unknown beam");
+    if (geom->n < 1 || geom->n_views < 1 || geom->n_bins < 1) return fail(AIR_E_INVALID, "sizes must be >= 1");
+    if (geom->n > kMaxN) return fail(AIR_E_UNSUPPORTED, "n exceeds 16384");
+    if (geom->n_bins > kMaxBins) return fail(AIR_E_UNSUPPORTED, "n_bins exceeds 8192");
+    if ((int64_t)geom->n_views * geom->n_bins > (int64_t)1 << 30) return fail(AIR_E_UNSUPPORTED, "too many rays");
+    if (!(geom->pixel_mm > 0.0) || !std::isfinite(geom->pixel_mm)) return fail(AIR_E_INVALID, "pixel_mm must be > 0");
+    if (!(geom->bin_mm > 0.0) || !std::isfinite(geom->bin_mm)) return fail(AIR_E_INVALID, "bin_mm must be > 0");
+    if (!geom->view_cos || !geom->view_sin) return fail(AIR_E_INVALID, "view tables are null");
+    if (max_batch < 1) return fail(AIR_E_INVALID, "max_batch must be >= 1");
+    if (prec != AIR_FP32 && prec != AIR_MIXED_F16 && prec != AIR_MIXED_BF16)
+        return fail(AIR_E_INVALID, "unknown precision");
+    if (geom->beam == AIR_FAN_FLAT) {
+        if (!(geom->sod_mm > 0.0) || !(geom->sdd_mm > geom->sod_mm) || !std::isfinite(geom->sdd_mm))
+            return fail(AIR_E_INVALID, "fan beam needs 0 < sod_mm < sdd_mm");
+        // every pixel (grown by one pixel) must lie strictly in front of the source
+        const double reach = (0.5 * geom->n + 1.5) * geom->pixel_mm * 1.41421356237309515;
+        if (!(geom->sod_mm > reach)) return fail(AIR_E_UNSUPPORTED, "image reaches the source circle");
+    }
+    for (int v = 0; v < geom->n_views; v++) {
+        const double c = geom->view_cos[v], s = geom->view_sin[v];
+        if (!std::isfinite(c) || !std::isfinite(s) || std::fabs(c * c + s * s - 1.0) > 1e-6)
+            return fail(AIR_E_INVALID, "view (cos, sin) must be finite unit vectors");
+    }
+    air_plan_s* p = new (std::nothrow) air_plan_s;
+    if (!p) return fail(AIR_E_NOMEM, "host allocation failed");
+    try {
+        GeomHost& g = p->g;
+        g.beam = geom->beam;
+        g.n = geom->n;
+        g.n_views = geom->n_views;
+        g.n_bins = geom->n_bins;
+        g.pixel = geom->pixel_mm;
+        g.bin = geom->bin_mm;
+        g.sod = geom->beam == AIR_FAN_FLAT ? geom->sod_mm : 0.0;
+        g.sdd = geom->beam == AIR_FAN_FLAT ? geom->sdd_mm : 0.0;
+        g.cosv.assign(geom->view_cos, geom->view_cos + g.n_views);
+        g.sinv.assign(geom->view_sin, geom->view_sin + g.n_views);
+        p->max_batch = max_batch;
+        p->prec = prec;
+        p->ds = (g.n_bins + 31) / 32 * 32;
+        p->line = g.n + 2 * kPad;
+        p->c0 = g.n / 2;
+        p->kappa = 3.14159265358979323846 / ((double)g.n_views * g.pixel * g.pixel);
+        const std::string err = build_ray_tables(g, p->rays, p->axis, p->lo, p->hi);
+        if (!err.empty()) {
+            delete p;
+            return fail(AIR_E_UNSUPPORTED, err);
+        }
+        p->views.resize(2 * (size_t)g.n_views);
+        for (int v = 0; v < g.n_views; v++) {
+            p->views[2 * v] = (float)g.cosv[v];
+            p->views[2 * v + 1] = (float)g.sinv[v];
+        }
+        std::vector<double> r;
+        ramp_taps64(g.n_bins, r);
+        const int ds = p->ds;
+        p->taps32.assign(2 * (size_t)ds, 0.f);
+        for (int idx = 0; idx < 2 * ds; idx++) {
+            const int d = std::abs(idx - ds);
+            if (d < g.n_bins) p->taps32[idx] = (float)(p->kappa * r[d]);
+        }
+        if (prec != AIR_FP32) {
+            p->n_terms = prec == AIR_MIXED_F16 ? 2 : 3;
+            p->dmin = -(ds - 16);
+            p->n_frag = (2 * ds - 48) / 16 + 1;
+            for (int t = 0; t < p->n_terms; t++) p->frag[t].assign((size_t)p->n_frag * 64 * 8, 0);
+            for (int f = 0; f < p->n_frag; f++) {
+                const int delta = p->dmin + 16 * f;
+                for (int l = 0; l < 64; l++) {
+                    for (int i = 0; i < 8; i++) {
+                        const int d = std::abs(delta + 8 * (l / 16) + i - (l % 16));
+                        const float T = d < g.n_bins ? (float)(r[d] * 4096.0) : 0.f;
+                        const size_t at = ((size_t)f * 64 + l) * 8 + i;
+                        if (prec == AIR_MIXED_F16) {
+                            const uint16_t h = f32_to_f16(T);
+                            p->frag[0][at] = h;
+                            p->frag[1][at] = f32_to_f16((T - f16_to_f32(h)) * 2048.f);
+                        } else {
+                            const uint16_t c1 = f32_to_bf16(T);
+                            const float r1 = T - bf16_to_f32(c1);
+                            const uint16_t c2 = f32_to_bf16(r1);
+                            p->frag[0][at] = c1;
+                            p->frag[1][at] = c2;
+                            p->frag[2][at] = f32_to_bf16(r1 - bf16_to_f32(c2));
+                        }
+                    }
+                }
+            }
+        }
+        // workspace layout
+        Carver c;
+        const size_t nr = (size_t)g.n_views * g.n_bins;
+        p->off_rays = c.take(nr * sizeof(RayEntry));
+        p->off_views = c.take(p->views.size() * sizeof(float));
+        p->off_taps = c.take(p->taps32.size() * sizeof(float));
+        for (int t = 0; t < p->n_terms; t++) p->off_frag[t] = c.take(p->frag[t].size() * sizeof(uint16_t));
+        const size_t mb = (size_t)max_batch;
+        p->off_pad = c.take(mb * 2 * g.n * p->line * sizeof(float));
+        p->off_s1 = c.take(mb * g.n_views * ds * sizeof(float));
+        p->off_s2 = c.take(mb * g.n_views * ds * sizeof(float));
+        p->off_part = c.take(mb * tiles16(g.n) * sizeof(double));
+        p->off_cnt = c.take(mb * sizeof(unsigned));
+        p->off_scal = c.take(mb * 4 * sizeof(double));
+        p->total = c.off;
+    } catch (const std::bad_alloc&) {
+        delete p;
+        return fail(AIR_E_NOMEM, "host allocation failed");
+    }
+    *out = p;
+    return AIR_OK;
+}
+
+air_status air_plan_workspace_size(air_plan p, size_t* bytes) {
+    if (air_status st = check_plan(p, false)) return st;
+    if (!bytes) return fail(AIR_E_INVALID, "bytes is null");
+    *bytes = p->total;
+    return AIR_OK;
+}
+
+air_status air_plan_bind_workspace(air_plan p, void* dev, size_t bytes, hipStream_t s) {
+    if (air_status st = check_plan(p, false)) return st;
+    if (!dev) return fail(AIR_E_INVALID, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(dev) & 255u) return fail(AIR_E_INVALID, "workspace must be 256-byte aligned");
+    if (bytes < p->total) return fail(AIR_E_NOMEM, "workspace smaller than air_plan_workspace_size");
+    char* ws = static_cast<char*>(dev);
+    AIR_HIP(hipMemcpyAsync(ws + p->off_rays, p->rays.data(), p->rays.size() * sizeof(RayEntry),
+                           hipMemcpyHostToDevice, s));
+    AIR_HIP(hipMemcpyAsync(ws + p->off_views, p->views.data(), p->views.size() * sizeof(float),
+                           hipMemcpyHostToDevice, s));
+    AIR_HIP(hipMemcpyAsync(ws + p->off_taps, p->taps32.data(), p->taps32.size() * sizeof(float),
+                           hipMemcpyHostToDevice, s));
+    for (int t = 0; t < p->n_terms; t++)
+        AIR_HIP(hipMemcpyAsync(ws + p->off_frag[t], p->frag[t].data(), p->frag[t].size() * sizeof(uint16_t),
+                               hipMemcpyHostToDevice, s));
+    AIR_HIP(hipMemsetAsync(ws + p->off_cnt, 0, (size_t)p->max_batch * sizeof(unsigned), s));
+    AIR_HIP(hipStreamSynchronize(s));
+    p->ws = ws;
+    return AIR_OK;
+}
+
+air_status air_plan_tables(air_plan p, int8_t* axis, int32_t* lo, int32_t* hi) {
+    if (air_status st = check_plan(p, false)) return st;
+    const size_t nr = p->axis.size();
+    if (axis) std::memcpy(axis, p->axis.data(), nr);
+    if (lo) std::memcpy(lo, p->lo.data(), nr * sizeof(int32_t));
+    if (hi) std::memcpy(hi, p->hi.data(), nr * sizeof(int32_t));
+    return AIR_OK;
+}
+
+void air_plan_destroy(air_plan p) { delete p; }
+
+air_status air_project(air_plan p, const float* x, float* y, int32_t batch, hipStream_t s) {
+    if (air_status st = check_plan(p, true)) return st;
+    if (air_status st = check_batch(p, batch, true)) return st;
+    if (!x || !y) return fail(AIR_E_INVALID, "null pointer");
+    const KGeom kg = p->kgeom();
+    PadBuf pad{p->at<float>(p->off_pad)};
+    AIR_K(AIR_K_OTHER, launch_pad(kg, x, pad, batch, s));
+    if (p->direct(y)) {
+        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, y, batch, s));
+    } else {
+        float* s1 = p->at<float>(p->off_s1);
+        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, s));
+        AIR_K(AIR_K_OTHER, launch_repack(s1, p->ds, y, p->g.n_bins, batch * p->g.n_views, p->g.n_bins, p->g.n_bins, s));
+    }
+    return AIR_OK;
+}
+
+air_status air_ramp(air_plan p, const float* y, float* yf, int32_t batch, hipStream_t s) {
+    if (air_status st = check_plan(p, true)) return st;
+    if (air_status st = check_batch(p, batch, true)) return st;
+    if (!y || !yf) return fail(AIR_E_INVALID, "null pointer");
+    if (y == yf) return fail(AIR_E_INVALID, "air_ramp is not in-place");
+    const float* src = nullptr;
+    if (air_status st = stage_sino(p, y, batch, p->at<float>(p->off_s1), &src, s)) return st;
+    const int rows = batch * p->g.n_views;
+    if (p->direct(yf)) {
+        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, yf, rows, p->ds, s));
+    } else {
+        float* s2 = p->at<float>(p->off_s2);
+        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, s2, rows, p->ds, s));
+        AIR_K(AIR_K_OTHER, launch_repack(s2, p->ds, yf, p->g.n_bins, rows, p->g.n_bins, p->g.n_bins, s));
+    }
+    return AIR_OK;
+}
+
+air_status air_filtered_backproject(air_plan p, const float* y, float* x, int32_t batch, int32_t filter,
+                                    hipStream_t s) {
+    if (air_status st = check_plan(p, true)) return st;
+    if (air_status st = check_batch(p, batch, true)) return st;
+    if (!y || !x) return fail(AIR_E_INVALID, "null pointer");
+    if (filter != 0 && filter != 1) return fail(AIR_E_INVALID, "filter must be 0 or 1");
+    const float* src = nullptr;
+    if (air_status st = stage_sino(p, y, batch, p->at<float>(p->off_s1), &src, s)) return st;
+    if (filter) {
+        float* s2 = p->at<float>(p->off_s2);
+        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, s2, batch * p->g.n_views, p->ds, s));
+        src = s2;
+    }
+    BpArgs a{};
+    a.mode = BP_PLAIN;
+    a.out = x;
+    AIR_K(AIR_K_BACKPROJECT, launch_backproject(p->kgeom(), src, a, batch, s));
+    return AIR_OK;
+}
+
+air_status air_normal_apply(air_plan p, const float* x, float* out, int32_t batch, double mu, int32_t filter,
+                            hipStream_t s) {
+    if (air_status st = check_plan(p, true)) return st;
+    if (air_status st = check_batch(p, batch, true)) return st;
+    if (!x || !out) return fail(AIR_E_INVALID, "null pointer");
+    if (x == out) return fail(AIR_E_INVALID, "air_normal_apply is not in-place");
+    if (filter != 0 && filter != 1) return fail(AIR_E_INVALID, "filter must be 0 or 1");
+    if (!std::isfinite(mu)) return fail(AIR_E_INVALID, "mu must be finite");
+    const KGeom kg = p->kgeom();
+    PadBuf pad{p->at<float>(p->off_pad)};
+    float* s1 = p->at<float>(p->off_s1);
+    float* s2 = p->at<float>(p->off_s2);
+    AIR_K(AIR_K_OTHER, launch_pad(kg, x, pad, batch, s));
+    AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, s));
+    const float* src = s1;
+    if (filter) {
+        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), s1, s2, batch * p->g.n_views, p->ds, s));
+        src = s2;
+    }
+    BpArgs a{};
+    a.mode = BP_MATVEC;
+    a.mu = (float)mu;
+    a.aux = x;
+    a.out = out;
+    AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, src, a, batch, s));
+    return AIR_OK;
+}
+
+air_status air_kernel_timing_enable(air_plan p, int32_t enable) {
+    if (air_status st = check_plan(p, false)) return st;
+    p->timing = enable != 0;
+    return AIR_OK;
+}
+
+air_status air_kernel_timing_collect(air_plan p, air_kernel_stats* stats) {
+    if (air_status st = check_plan(p, false)) return st;
+    if (!stats) return fail(AIR_E_INVALID, "stats is null");
+    air_status result = AIR_OK;
+    for (const air_plan_s::Timed& t : p->pending) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.a, t.b);
+        if (e != hipSuccess && result == AIR_OK) result = fail(AIR_E_HIP, std::string("event timing: ") + hipGetErrorString(e));
+        stats->ms[t.kind] += ms;
+        stats->launches[t.kind] += 1;
+        p->pool.push_back(t.a);
+        p->pool.push_back(t.b);
+    }
+    p->pending.clear();
+    return result;
+}
+
+air_status air_framelet(air_plan p, const float* in, float* out, int32_t batch, int32_t adjoint, hipStream_t s) {
+    if (air_status st = check_plan(p, false)) return st;
+    if (air_status st = check_batch(p, batch, false)) return st;
+    if (!in || !out) return fail(AIR_E_INVALID, "null pointer");
+    if (in == out) return fail(AIR_E_INVALID, "air_framelet is not in-place");
+    if (adjoint != 0 && adjoint != 1) return fail(AIR_E_INVALID, "adjoint must be 0 or 1");
+    if (adjoint) AIR_K(AIR_K_FRAMELET, launch_framelet_adj(p->g.n, in, out, batch, s));
+    else AIR_K(AIR_K_FRAMELET, launch_framelet_fwd(p->g.n, in, out, batch, s));
+    return AIR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct SolveLayout {
+    size_t pad, s1, s2, g, r, p, q, bb, e, part, cnt, scal, total;
+};
+
+SolveLayout solve_layout(const air_plan_s* p, int batch) {
+    const size_t B = (size_t)batch, n = (size_t)p->g.n, np = n * n;
+    Carver c;
+    SolveLayout L;
+    L.pad = c.take(B * 2 * n * p->line * sizeof(float));
+    L.s1 = c.take(B * p->g.n_views * p->ds * sizeof(float));
+    L.s2 = c.take(B * p->g.n_views * p->ds * sizeof(float));
+    L.g = c.take(B * np * sizeof(float));
+    L.r = c.take(B * np * sizeof(float));
+    L.p = c.take(B * np * sizeof(float));
+    L.q = c.take(B * np * sizeof(float));
+    L.bb = c.take(B * 8 * np * sizeof(float));
+    L.e = c.take(B * 9 * np * sizeof(float));
+    L.part = c.take(B * tiles16((int)n) * sizeof(double));
+    L.cnt = c.take(B * sizeof(unsigned));
+    L.scal = c.take(B * 4 * sizeof(double));
+    L.total = c.off;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+air_status air_solve_workspace_size(air_plan p, int32_t batch, size_t* bytes) {
+    if (air_status st = check_plan(p, false)) return st;
+    if (air_status st = check_batch(p, batch, false)) return st;
+    if (!bytes) return fail(AIR_E_INVALID, "bytes is null");
+    *bytes = solve_layout(p, batch).total;
+    return AIR_OK;
+}
+
+air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const air_solve_params* prm,
+                     double* resid, void* ws, size_t ws_bytes, hipStream_t s) {
+    if (air_status st = check_plan(p, true)) return st;
+    if (air_status st = check_batch(p, batch, false)) return st;
+    if (!Y || !X || !prm || !ws) return fail(AIR_E_INVALID, "null pointer");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(AIR_E_INVALID, "workspace must be 256-byte aligned");
+    if (prm->reg != 0 && prm->reg != 1) return fail(AIR_E_INVALID, "reg must be 0 or 1");
+    if (prm->filter != 0 && prm->filter != 1) return fail(AIR_E_INVALID, "filter must be 0 or 1");
+    if (!(prm->lambda >= 0.0) || !std::isfinite(prm->lambda)) return fail(AIR_E_INVALID, "lambda must be >= 0");
+    if (prm->reg == 0 && (!(prm->mu > 0.0) || !std::isfinite(prm->mu))) return fail(AIR_E_INVALID, "mu must be > 0");
+    if (prm->n_outer < 0 || prm->n_cg < 0) return fail(AIR_E_INVALID, "iteration counts must be >= 0");
+    const SolveLayout L = solve_layout(p, batch);
+    if (ws_bytes < L.total) return fail(AIR_E_NOMEM, "workspace smaller than air_solve_workspace_size");
+
+    char* w = static_cast<char*>(ws);
+    auto F = [&](size_t off) { return reinterpret_cast<float*>(w + off); };
+    const KGeom kg = p->kgeom();
+    const RampTables rt = p->ramp_tables();
+    const int n = p->g.n, rows = batch * p->g.n_views;
+    const size_t np = (size_t)n * n;
+    PadBuf pad{F(L.pad)};
+    float *s1 = F(L.s1), *s2 = F(L.s2), *g = F(L.g), *r = F(L.r), *pv = F(L.p), *q = F(L.q);
+    float *bb = F(L.bb), *e = F(L.e);
+    double* part = reinterpret_cast<double*>(w + L.part);
+    unsigned* cnt = reinterpret_cast<unsigned*>(w + L.cnt);
+    double* scal = reinterpret_cast<double*>(w + L.scal);
+    double* rho[2] = {scal, scal + batch};
+    double* pq = scal + 2 * batch;
+    double* tfred = scal + 3 * batch;
+    const bool tf = prm->reg == 0;
+    const float mu_op = (float)(tf ? prm->mu : prm->lambda);
+
+    AIR_K(AIR_K_OTHER, launch_fill_u32(cnt, (size_t)batch, 0u, s));
+    // g = A'^T Y (or A^T Y)
+    const float* src = nullptr;
+    if (air_status st = stage_sino(p, Y, batch, s1, &src, s)) return st;
+    if (prm->filter) {
+        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, src, s2, rows, p->ds, s));
+        src = s2;
+    }
+    {
+        BpArgs a{};
+        a.mode = BP_PLAIN;
+        a.out = g;
+        AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, src, a, batch, s));
+    }
+    if (tf) {
+        AIR_K(AIR_K_OTHER, launch_fill(bb, (size_t)batch * 8 * np, 0.f, s));
+        AIR_K(AIR_K_OTHER, launch_fill(e, (size_t)batch * 9 * np, 0.f, s));
+    }
+    AIR_K(AIR_K_OTHER, launch_pad(kg, X, pad, batch, s));
+    const int n_out = tf ? prm->n_outer : 1;
+    for (int k = 0; k < n_out; k++) {
+        if (tf) AIR_K(AIR_K_FRAMELET, launch_tf_rhs(n, g, e, (float)prm->mu, r, batch, s));
+        else AIR_HIP(hipMemcpyAsync(r, g, (size_t)batch * np * sizeof(float), hipMemcpyDeviceToDevice, s));
+        // r = rhs - M X, p = r, rho = r.r
+        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, s));
+        const float* bsrc = s1;
+        if (prm->filter) {
+            AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, s1, s2, rows, p->ds, s));
+            bsrc = s2;
+        }
+        {
+            BpArgs a{};
+            a.mode = BP_RESIDUAL;
+            a.mu = mu_op;
+            a.aux = X;
+            a.out = r;
+            a.p_out = pv;
+            a.pad_out = pad;
+            a.red_partial = part;
+            a.red_count = cnt;
+            a.red_out = rho[0];
+            AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, bsrc, a, batch, s));
+        }
+        int c = 0;
+        for (int it = 0; it < prm->n_cg; it++) {
+            AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, s));
+            if (prm->filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, s1, s2, rows, p->ds, s));
+            BpArgs a{};
+            a.mode = BP_MATVEC;
+            a.mu = mu_op;
+            a.aux = pv;
+            a.out = q;
+            a.red_partial = part;
+            a.red_count = cnt;
+            a.red_out = pq;
+            AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, prm->filter ? s2 : s1, a, batch, s));
+            CgArgs cg{};
+            cg.n = n;
+            cg.x = X;
+            cg.r = r;
+            cg.p = pv;
+            cg.q = q;
+            cg.pad.base = it == prm->n_cg - 1 ? pad.base : nullptr;
+            cg.rho_cur = rho[c];
+            cg.pq = pq;
+            cg.red_partial = part;
+            cg.red_count = cnt;
+            cg.red_out = rho[1 - c];
+            AIR_K(AIR_K_CG, launch_cg_update_xr(cg, batch, s));
+            if (it < prm->n_cg - 1) {
+                cg.pad = pad;
+                cg.rho_new_in = rho[1 - c];
+                AIR_K(AIR_K_CG, launch_cg_update_p(cg, batch, s));
+            }
+            c = 1 - c;
+        }
+        if (prm->n_cg == 0) AIR_K(AIR_K_OTHER, launch_pad(kg, X, pad, batch, s));
+        if (tf) {
+            TfArgs t{};
+            t.n = n;
+            t.x = X;
+            t.bb = bb;
+            t.e = e;
+            t.thr = (float)(prm->lambda / (2.0 * prm->mu));
+            t.red_partial = part;
+            t.red_count = cnt;
+            t.red_out = tfred;
+            t.resid = resid ? resid + k : nullptr;
+            t.resid_stride = prm->n_outer;
+            AIR_K(AIR_K_FRAMELET, launch_tf_shrink(t, batch, s));
+        }
+    }
+    return AIR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,239 @@
+// Conjugate-gradient vector updates and the tensor-framelet kernels.
+//
+// All image kernels work on 16 x 16 pixel tiles (256 threads), one batch item
+// per grid z.  Vectors are float32; inner products, alpha, beta and the
+// Bregman residual norm are float64 and are reduced with a fixed-order tree
+// (block_reduce_last), so every batch item gets the same bits whatever the
+// batch size.  Scalars never leave the device.
+#include "common.cuh"
+
+namespace air {
+
+// ---------------------------------------------------------------------------- CG
+// x += alpha p, r -= alpha q, rho' = r . r  with alpha = rho / (p . q) (0 if rho or p.q is 0).
+// When a.pad.base is set, x is also written to its padded line sets.
+__global__ __launch_bounds__(256) void k_cg_xr(CgArgs a) {
+    __shared__ float tile[16][17];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16, b = blockIdx.z;
+    const int n = a.n, i = i0 + tx, j = j0 + ty;
+    const bool valid = i < n && j < n;
+    const double rho = a.rho_cur[b], pq = a.pq[b];
+    const double alpha = (rho == 0.0 || pq == 0.0) ? 0.0 : rho / pq;
+    const size_t idx = (size_t)b * n * n + (size_t)j * n + i;
+    double part = 0.0;
+    float xn = 0.f;
+    if (valid) {
+        xn = (float)fma(alpha, (double)a.p[idx], (double)a.x[idx]);
+        const float rn = (float)fma(-alpha, (double)a.q[idx], (double)a.r[idx]);
+        a.x[idx] = xn;
+        a.r[idx] = rn;
+        part = (double)rn * (double)rn;
+    }
+    if (a.pad.base) {
+        const int line = n + 2 * kPad;
+        store_padded_tile(a.pad.base + (size_t)b * 2 * n * line, n, line, i0, j0, tx, ty, xn, tile);
+    }
+    const int nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
+    block_reduce_last<256>(part, a.red_partial + (size_t)b * nblk, a.red_count + b, a.red_out + b, nblk, blk);
+}
+
+// p = r + beta p, beta = rho' / rho (0 if rho is 0); p also goes to its padded line sets.
+__global__ __launch_bounds__(256) void k_cg_p(CgArgs a) {
+    __shared__ float tile[16][17];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16, b = blockIdx.z;
+    const int n = a.n, i = i0 + tx, j = j0 + ty;
+    const bool valid = i < n && j < n;
+    const double rho = a.rho_cur[b], rho_new = a.rho_new_in[b];
+    const double beta = rho == 0.0 ? 0.0 : rho_new / rho;
+    const size_t idx = (size_t)b * n * n + (size_t)j * n + i;
+    float pn = 0.f;
+    if (valid) {
+        pn = (float)fma(beta, (double)a.p[idx], (double)a.r[idx]);
+        a.p[idx] = pn;
+    }
+    const int line = n + 2 * kPad;
+    store_padded_tile(a.pad.base + (size_t)b * 2 * n * line, n, line, i0, j0, tx, ty, pn, tile);
+}
+
+hipError_t launch_cg_update_xr(const CgArgs& a, int batch, hipStream_t s) {
+    dim3 grid((a.n + 15) / 16, (a.n + 15) / 16, batch);
+    hipLaunchKernelGGL(k_cg_xr, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s) {
+    dim3 grid((a.n + 15) / 16, (a.n + 15) / 16, batch);
+    hipLaunchKernelGGL(k_cg_p, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- framelet
+// Piecewise-linear filters at offsets -1, 0, +1 (correlation form):
+//   h0 = [1, 2, 1] / 4,  h1 = sqrt2 [1, 0, -1] / 4,  h2 = [-1, 2, -1] / 4.
+__device__ __forceinline__ float fl_h(int m, int off) {
+    const float q = 0.35355339059327373f;   // sqrt(2) / 4
+    if (m == 0) return off == 0 ? 0.5f : 0.25f;
+    if (m == 1) return off == 0 ? 0.f : (off < 0 ? q : -q);
+    return off == 0 ? 0.5f : -0.25f;
+}
+
+__device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// All nine bands of W x at pixel (i, j), periodic boundary.
+__device__ __forceinline__ void framelet_at(const float* __restrict__ xb, int n, int i, int j, float z[9]) {
+    float rowf[3][3];   // [dy][m_x]: filtered along x
+#pragma unroll
+    for (int dy = -1; dy <= 1; dy++) {
+        const float* row = xb + (size_t)wrap(j + dy, n) * n;
+        const float l = row[wrap(i - 1, n)], c = row[i], r = row[wrap(i + 1, n)];
+#pragma unroll
+        for (int mx = 0; mx < 3; mx++) rowf[dy + 1][mx] = fl_h(mx, -1) * l + fl_h(mx, 0) * c + fl_h(mx, 1) * r;
+    }
+#pragma unroll
+    for (int my = 0; my < 3; my++)
+#pragma unroll
+        for (int mx = 0; mx < 3; mx++)
+            z[3 * my + mx] = fl_h(my, -1) * rowf[0][mx] + fl_h(my, 0) * rowf[1][mx] + fl_h(my, 1) * rowf[2][mx];
+}
+
+// (W^T z)(i, j) = sum_band sum_{dy,dx} h_{my}(dy) h_{mx}(dx) z_band(j - dy, i - dx)
+__device__ __forceinline__ float framelet_adj_at(const float* __restrict__ zb, int n, int i, int j) {
+    const size_t np = (size_t)n * n;
+    float s = 0.f;
+#pragma unroll
+    for (int dy = -1; dy <= 1; dy++) {
+        const size_t roff = (size_t)wrap(j - dy, n) * n;
+#pragma unroll
+        for (int dx = -1; dx <= 1; dx++) {
+            const size_t off = roff + wrap(i - dx, n);
+#pragma unroll
+            for (int my = 0; my < 3; my++) {
+                float t = 0.f;
+#pragma unroll
+                for (int mx = 0; mx < 3; mx++) t = fmaf(fl_h(mx, dx), zb[(3 * my + mx) * np + off], t);
+                s = fmaf(fl_h(my, dy), t, s);
+            }
+        }
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_framelet_fwd(const float* __restrict__ x, float* __restrict__ z, int n) {
+    const int i = blockIdx.x * 16 + (threadIdx.x & 15), j = blockIdx.y * 16 + (threadIdx.x >> 4), b = blockIdx.z;
+    if (i >= n || j >= n) return;
+    const size_t np = (size_t)n * n;
+    float zz[9];
+    framelet_at(x + b * np, n, i, j, zz);
+#pragma unroll
+    for (int band = 0; band < 9; band++) z[(size_t)b * 9 * np + band * np + (size_t)j * n + i] = zz[band];
+}
+
+__global__ __launch_bounds__(256) void k_framelet_adj(const float* __restrict__ z, float* __restrict__ x, int n) {
+    const int i = blockIdx.x * 16 + (threadIdx.x & 15), j = blockIdx.y * 16 + (threadIdx.x >> 4), b = blockIdx.z;
+    if (i >= n || j >= n) return;
+    const size_t np = (size_t)n * n;
+    x[b * np + (size_t)j * n + i] = framelet_adj_at(z + (size_t)b * 9 * np, n, i, j);
+}
+
+// rhs = g + mu W^T e
+__global__ __launch_bounds__(256) void k_tf_rhs(const float* __restrict__ g, const float* __restrict__ e, float mu,
+                                                float* __restrict__ rhs, int n) {
+    const int i = blockIdx.x * 16 + (threadIdx.x & 15), j = blockIdx.y * 16 + (threadIdx.x >> 4), b = blockIdx.z;
+    if (i >= n || j >= n) return;
+    const size_t np = (size_t)n * n, idx = b * np + (size_t)j * n + i;
+    rhs[idx] = fmaf(mu, framelet_adj_at(e + (size_t)b * 9 * np, n, i, j), g[idx]);
+}
+
+// Bregman update after the L2 step: z = W x; v = z + b; d = shrink(v, thr) on
+// bands 1..8 (band 0: d = v, b stays 0); b <- v - d; e <- d - b (what the next
+// right-hand side needs); resid = ||z - d||_2.
+__global__ __launch_bounds__(256) void k_tf_shrink(TfArgs a) {
+    const int i = blockIdx.x * 16 + (threadIdx.x & 15), j = blockIdx.y * 16 + (threadIdx.x >> 4), b = blockIdx.z;
+    const int n = a.n;
+    const size_t np = (size_t)n * n;
+    double part = 0.0;
+    if (i < n && j < n) {
+        float z[9];
+        framelet_at(a.x + b * np, n, i, j, z);
+        const size_t pix = (size_t)j * n + i;
+        float* eb = a.e + (size_t)b * 9 * np;
+        float* bb = a.bb + (size_t)b * 8 * np;
+        eb[pix] = z[0];                           // d0 = z0, b0 = 0
+#pragma unroll
+        for (int band = 1; band < 9; band++) {
+            const float bo = bb[(band - 1) * np + pix];
+            const float v = z[band] + bo;
+            const float mag = fabsf(v) - a.thr;
+            const float d = mag > 0.f ? copysignf(mag, v) : 0.f;
+            const float bn = v - d;
+            bb[(band - 1) * np + pix] = bn;
+            eb[band * np + pix] = d - bn;
+            const double dz = (double)z[band] - (double)d;
+            part = fma(dz, dz, part);
+        }
+    }
+    const int nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
+    block_reduce_last<256>(part, a.red_partial + (size_t)b * nblk, a.red_count + b, a.red_out + b, nblk, blk);
+}
+
+// resid[b * stride] = sqrt(red[b])
+__global__ void k_store_sqrt(const double* __restrict__ red, double* __restrict__ resid, int stride, int batch) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < batch) resid[(size_t)b * stride] = sqrt(red[b]);
+}
+
+hipError_t launch_framelet_fwd(int n, const float* x, float* z, int batch, hipStream_t s) {
+    dim3 grid((n + 15) / 16, (n + 15) / 16, batch);
+    hipLaunchKernelGGL(k_framelet_fwd, grid, dim3(256), 0, s, x, z, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_framelet_adj(int n, const float* z, float* x, int batch, hipStream_t s) {
+    dim3 grid((n + 15) / 16, (n + 15) / 16, batch);
+    hipLaunchKernelGGL(k_framelet_adj, grid, dim3(256), 0, s, z, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_tf_rhs(int n, const float* g, const float* e, float mu, float* rhs, int batch, hipStream_t s) {
+    dim3 grid((n + 15) / 16, (n + 15) / 16, batch);
+    hipLaunchKernelGGL(k_tf_rhs, grid, dim3(256), 0, s, g, e, mu, rhs, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_tf_shrink(const TfArgs& a, int batch, hipStream_t s) {
+    dim3 grid((a.n + 15) / 16, (a.n + 15) / 16, batch);
+    hipLaunchKernelGGL(k_tf_shrink, grid, dim3(256), 0, s, a);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess || !a.resid) return err;
+    hipLaunchKernelGGL(k_store_sqrt, dim3((batch + 63) / 64), dim3(64), 0, s, a.red_out, a.resid, a.resid_stride,
+                       batch);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- fills
+__global__ void k_fill(float* __restrict__ p, size_t count, float v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u32(unsigned* __restrict__ p, size_t count, unsigned v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill(float* p, size_t count, float v, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    const size_t blocks = (count + 255) / 256 < 4096 ? (count + 255) / 256 : 4096;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    const size_t blocks = (count + 255) / 256 < 4096 ? (count + 255) / 256 : 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, count, v);
+    return hipGetLastError();
+}
+
+}  // namespace air

@@ -1,0 +1,163 @@
+// Ramp filtration y' = C y as a dense Toeplitz GEMM on the matrix cores.
+//
+// Rows of the sinogram batch (batch x views) form M, detector bins form K and
+// N: Y'[m][n] = sum_k Y[m][k] T(k - n), T(d) = kappa r(|d|) for |d| < n_bins.
+// The Toeplitz operand is never stored as a matrix: the float32 kernel reads
+// it from a copy of the taps in LDS, the 16-bit kernels from precomputed MFMA
+// fragments, one per diagonal offset k0 - n0.
+//
+// Tiles: a block of 4 waves covers 64 rows x 32 columns; each wave owns 16
+// rows and two 16x16 accumulator tiles.  Rows have stride ds (n_bins rounded
+// up to 32, zero-filled), so the K loop needs no bounds tests.  Within one
+// MFMA the assignment of actual k to the instruction's k slots is free as
+// long as both operands agree; it is chosen so that each lane reads
+// contiguous sinogram values (one 16-byte load per lane per 16 k for f32,
+// two per 32 k for the 16-bit kernels).
+#include "common.cuh"
+
+namespace air {
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 b8_t __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------- float32
+__global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, float* __restrict__ yf,
+                                                  const float* __restrict__ taps, int rows, int ds) {
+    extern __shared__ float T[];   // [2 ds]: T[d + ds] = kappa r(|d|)
+    for (int i = threadIdx.x; i < 2 * ds; i += 256) T[i] = taps[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = blockIdx.x * 64 + w * 16 + (lane & 15);   // A row of this lane
+    const int slot = lane >> 4;                              // k slot 0..3
+    const int n0 = blockIdx.y * 32;
+    const int ncol = n0 + (lane & 15);
+    const float* arow = y + (size_t)min(m, rows - 1) * ds;
+    const bool mvalid = m < rows;
+    f4_t acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < ds; k0 += 16) {
+        float4 av = *reinterpret_cast<const float4*>(arow + k0 + 4 * slot);
+        if (!mvalid) av = make_float4(0.f, 0.f, 0.f, 0.f);
+        // MFMA #q uses actual k = k0 + 4 slot + q in this lane's slot
+        const int d = k0 + 4 * slot - ncol + ds;
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, T[d + 0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, T[d + 0 - 16], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, T[d + 1], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, T[d + 1 - 16], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, T[d + 2], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, T[d + 2 - 16], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, T[d + 3], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, T[d + 3 - 16], acc1, 0, 0, 0);
+    }
+    // accumulator layout: lane holds C[4 (lane/16) + r][lane % 16]
+    const int rbase = blockIdx.x * 64 + w * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const int row = rbase + r;
+        if (row < rows) {
+            yf[(size_t)row * ds + ncol] = acc0[r];
+            yf[(size_t)row * ds + ncol + 16] = acc1[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------- 16-bit splits
+// Fragment f of a split term holds, for lane l, the 8 values T16(delta + 8 (l/16) + i - l%16),
+// i = 0..7, with delta = dmin + 16 f (delta = k0 - n0 of the tile).
+template <int PREC>
+__global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y, float* __restrict__ yf,
+                                                    RampTables t, int rows, int ds) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = blockIdx.x * 64 + w * 16 + (lane & 15);
+    const int slot = lane >> 4;                 // k slots 8 slot .. 8 slot + 7
+    const int n0 = blockIdx.y * 32;
+    const float* arow = y + (size_t)min(m, rows - 1) * ds;
+    const bool mvalid = m < rows;
+    f4_t accA0 = {0.f, 0.f, 0.f, 0.f}, accA1 = accA0, accB0 = accA0, accB1 = accA0;
+    for (int k0 = 0; k0 < ds; k0 += 32) {
+        float4 a0 = *reinterpret_cast<const float4*>(arow + k0 + 8 * slot);
+        float4 a1 = *reinterpret_cast<const float4*>(arow + k0 + 8 * slot + 4);
+        if (!mvalid) {
+            a0 = make_float4(0.f, 0.f, 0.f, 0.f);
+            a1 = a0;
+        }
+        const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+        const int f0 = (k0 - n0 - t.dmin) >> 4;      // fragment of the first n tile
+        const int f1 = f0 - 1;                        // n0 + 16: delta - 16
+        if (PREC == AIR_MIXED_F16) {
+            h8_t hi, lo;
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const _Float16 h = (_Float16)av[i];
+                hi[i] = h;
+                lo[i] = (_Float16)((av[i] - (float)h) * 2048.f);
+            }
+            const uint4 bh0 = t.frag_a[(size_t)f0 * 64 + lane], bl0 = t.frag_b[(size_t)f0 * 64 + lane];
+            const uint4 bh1 = t.frag_a[(size_t)f1 * 64 + lane], bl1 = t.frag_b[(size_t)f1 * 64 + lane];
+            const h8_t Bh0 = __builtin_bit_cast(h8_t, bh0), Bl0 = __builtin_bit_cast(h8_t, bl0);
+            const h8_t Bh1 = __builtin_bit_cast(h8_t, bh1), Bl1 = __builtin_bit_cast(h8_t, bl1);
+            accA0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, Bh0, accA0, 0, 0, 0);
+            accA1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, Bh1, accA1, 0, 0, 0);
+            accB0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, Bl0, accB0, 0, 0, 0);
+            accB1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, Bl1, accB1, 0, 0, 0);
+            accB0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo, Bh0, accB0, 0, 0, 0);
+            accB1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo, Bh1, accB1, 0, 0, 0);
+        } else {
+            b8_t s1, s2, s3;
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const __bf16 c1 = (__bf16)av[i];
+                const float r1 = av[i] - (float)c1;
+                const __bf16 c2 = (__bf16)r1;
+                const __bf16 c3 = (__bf16)(r1 - (float)c2);
+                s1[i] = c1; s2[i] = c2; s3[i] = c3;
+            }
+            const b8_t B10 = __builtin_bit_cast(b8_t, t.frag_a[(size_t)f0 * 64 + lane]);
+            const b8_t B20 = __builtin_bit_cast(b8_t, t.frag_b[(size_t)f0 * 64 + lane]);
+            const b8_t B30 = __builtin_bit_cast(b8_t, t.frag_c[(size_t)f0 * 64 + lane]);
+            const b8_t B11 = __builtin_bit_cast(b8_t, t.frag_a[(size_t)f1 * 64 + lane]);
+            const b8_t B21 = __builtin_bit_cast(b8_t, t.frag_b[(size_t)f1 * 64 + lane]);
+            const b8_t B31 = __builtin_bit_cast(b8_t, t.frag_c[(size_t)f1 * 64 + lane]);
+            accA0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s1, B10, accA0, 0, 0, 0);
+            accA1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s1, B11, accA1, 0, 0, 0);
+            accB0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s1, B20, accB0, 0, 0, 0);
+            accB1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s1, B21, accB1, 0, 0, 0);
+            accB0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s2, B10, accB0, 0, 0, 0);
+            accB1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s2, B11, accB1, 0, 0, 0);
+            accB0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s1, B30, accB0, 0, 0, 0);
+            accB1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s1, B31, accB1, 0, 0, 0);
+            accB0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s2, B20, accB0, 0, 0, 0);
+            accB1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s2, B21, accB1, 0, 0, 0);
+            accB0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s3, B10, accB0, 0, 0, 0);
+            accB1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s3, B11, accB1, 0, 0, 0);
+        }
+    }
+    const float cross = (PREC == AIR_MIXED_F16) ? (1.f / 2048.f) : 1.f;
+    const int rbase = blockIdx.x * 64 + w * 16 + 4 * (lane >> 4);
+    const int ncol = n0 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const int row = rbase + r;
+        if (row < rows) {
+            yf[(size_t)row * ds + ncol] = t.out_scale * fmaf(accB0[r], cross, accA0[r]);
+            yf[(size_t)row * ds + ncol + 16] = t.out_scale * fmaf(accB1[r], cross, accA1[r]);
+        }
+    }
+}
+
+hipError_t launch_ramp(int prec, const RampTables& t, const float* y, float* yf, int rows, int ds,
+                       hipStream_t s) {
+    dim3 grid((rows + 63) / 64, ds / 32), block(256);
+    if (prec == AIR_FP32) {
+        hipLaunchKernelGGL(k_ramp_f32, grid, block, 2 * ds * sizeof(float), s, y, yf, t.taps32, rows, ds);
+    } else if (prec == AIR_MIXED_F16) {
+        hipLaunchKernelGGL(k_ramp_split<AIR_MIXED_F16>, grid, block, 0, s, y, yf, t, rows, ds);
+    } else if (prec == AIR_MIXED_BF16) {
+        hipLaunchKernelGGL(k_ramp_split<AIR_MIXED_BF16>, grid, block, 0, s, y, yf, t, rows, ds);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace air
