@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-timing-only", action="store_true",
                     help="skip the timed steps; run only the instrumented pass (for profiler runs)")
+    ap.add_argument("--outer", type=int, default=0,
+                    help="profiler runs only: Bregman iterations of the instrumented pass (0 = the workload's)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="profiler runs only: also run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -133,8 +137,9 @@ def main():
             del mp
 
     # instrumented pass: one more step with every kernel bracketed by HIP events
+    n_outer = a.outer if (a.kernel_timing_only and a.outer > 0) else w.n_outer
     plan.kernel_timing(True)
-    plan.solve(y, w.lam, w.mu, w.n_outer, w.n_cg, workspace=ws, with_resid=False)
+    plan.solve(y, w.lam, w.mu, n_outer, w.n_cg, workspace=ws, with_resid=False)
     kt = plan.collect_kernel_timing()
     plan.kernel_timing(False)
     kernel_ms = {k: {"avg_ms": (v[0] / v[1]) if v[1] else 0.0, "launches": v[1], "total_ms": v[0]}
@@ -175,6 +180,13 @@ def main():
     out["roofline"] = roof
     out["kernel_source_hash"] = kernel_source_hash()
 
+    if a.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = src.numel() * 4
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, ys[0])
     print(json.dumps(out), flush=True)

@@ -132,20 +132,21 @@ std::string build_ray_tables(const GeomHost& g, std::vector<RayEntry>& rays, std
             lo[idx] = a_lo;
             hi[idx] = a_hi;
             RayEntry e;
-            e.tc = (float)t_at(g, r, slope, c0);
-            e.m = (float)slope;
+            e.tc = t_at(g, r, slope, c0);
+            e.m = slope;
             e.s = (float)(g.pixel * std::sqrt(r.da * r.da + r.db * r.db) / std::fabs(r.da));
             e.meta = (int32_t)((uint32_t)a_lo | ((uint32_t)(a_hi + 1) << 15) | ((uint32_t)r.axis << 30));
             if (a_hi < a_lo) e.meta = (int32_t)((uint32_t)r.axis << 30);
-            // The kernels sample padded lines at floor(t32) and floor(t32) + 1 with
-            // t32 = fmaf(a - c0, m, tc); keep both inside the two-sample padding.
+            e.unused[0] = e.unused[1] = 0;
+            // The kernels sample padded lines at floor(t) and floor(t) + 1 with
+            // t = fma(a - c0, m, tc); keep both inside the two-sample padding.
             if (a_hi >= a_lo) {
-                const float ta = std::fmaf((float)(a_lo - c0), e.m, e.tc);
-                const float tb = std::fmaf((float)(a_hi - c0), e.m, e.tc);
-                const float tmin = ta < tb ? ta : tb, tmax = ta < tb ? tb : ta;
-                if (!(tmin >= -(float)kPad) || !(tmax < (float)(n + kPad - 1))) {
+                const double ta = std::fma((double)(a_lo - c0), e.m, e.tc);
+                const double tb = std::fma((double)(a_hi - c0), e.m, e.tc);
+                const double tmin = ta < tb ? ta : tb, tmax = ta < tb ? tb : ta;
+                if (!(tmin >= -(double)kPad) || !(tmax < (double)(n + kPad - 1))) {
                     char buf[160];
-                    snprintf(buf, sizeof buf, "ray (%d, %d): float32 intercept out of the padded range", v, k);
+                    snprintf(buf, sizeof buf, "ray (%d, %d): intercept out of the padded range", v, k);
                     return buf;
                 }
             }

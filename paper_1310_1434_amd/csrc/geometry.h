@@ -10,17 +10,21 @@
 
 namespace air {
 
-// One Joseph ray, as the GPU kernels read it (16 bytes, float4-loadable).
-//   t(a) = fmaf((float)(a - c0), m, tc)   intercept at driving index a (pixel units)
+// One Joseph ray, as the GPU kernels read it (32 bytes, two 16-byte loads).
+//   t(a) = fma((double)(a - c0), m, tc)   intercept at driving index a (pixel units, float64)
 //   s    = pixel |d| / |d_drive|           path length per driving step
 //   meta = lo | (hi + 1) << 15 | axis << 30
+// The intercept is float64 because the ramp-filtered sinogram is high-pass:
+// a float32 intercept (error ~3e-5 pixel at n = 512) alone moves A^T C y by
+// ~1e-5 relative.  The interpolation weights themselves are float32.
 struct RayEntry {
-    float tc;
-    float m;
+    double tc;
+    double m;
     float s;
     int32_t meta;
+    int32_t unused[2];
 };
-static_assert(sizeof(RayEntry) == 16, "RayEntry must be 16 bytes");
+static_assert(sizeof(RayEntry) == 32, "RayEntry must be 32 bytes");
 
 inline int meta_lo(int32_t meta) { return meta & 0x7FFF; }
 inline int meta_hi(int32_t meta) { return ((meta >> 15) & 0x7FFF) - 1; }

@@ -50,81 +50,114 @@ hipError_t launch_pad(const KGeom& g, const float* x, PadBuf pad, int batch, hip
 }
 
 // ---------------------------------------------------------------------------- forward A
-// One thread per ray.  y[b][v][k] = s * sum_{a=lo..hi} (1-f) L_a[j0] + f L_a[j0+1],
-// t = fmaf(a - c0, m, tc), j0 = floor(t), f = t - j0, L_a the padded line a.
-// Bins k in [n_bins, ds) of the internal row stride are written as zero.
+// One thread per ray and up to BT images of the batch (the intercepts, weights
+// and addresses are shared; only the samples and sums are per image).
+//   y[b][v][k] = s * sum_{a=lo..hi} (1-f) L_a[j0] + f L_a[j0+1],
+//   t = fma(a - c0, m, tc) (float64), j0 = floor(t), f = (float)(t - j0),
+// L_a the padded line a of image b.  Bins k in [n_bins, ds) are written as zero.
+// The driving index runs over the union of the wavefront's ranges, so at every
+// step all lanes of one axis read the same image line (coalesced gathers);
+// lanes outside their own [lo, hi] sit the step out.
 constexpr int kProjBlock = 256;
 
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+template <int BT>
 __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __restrict__ pad,
-                                                         float* __restrict__ y, int chunks) {
+                                                         float* __restrict__ y, int chunks, int batch) {
     const int v = blockIdx.x / chunks;
     const int k = (blockIdx.x - v * chunks) * kProjBlock + threadIdx.x;
-    const int b = blockIdx.y;
-    if (k >= g.ds) return;
-    float* yrow = y + ((size_t)b * g.n_views + v) * g.ds;
-    if (k >= g.n_bins) {
-        yrow[k] = 0.f;
-        return;
-    }
-    const RayEntry e = g.rays[(size_t)v * g.n_bins + k];
-    const int lo = ray_lo(e.meta), hi = ray_hi(e.meta), axis = ray_axis(e.meta);
-    const float* lines = pad + ((size_t)b * 2 + axis) * g.n * g.line + kPad;
+    const int b0 = blockIdx.y * BT;
+    const bool ray = k < g.n_bins;
+    RayEntry e;
+    e.tc = 0.0;
+    e.m = 0.0;
+    e.s = 0.f;
+    e.meta = 0;
+    if (ray) e = g.rays[(size_t)v * g.n_bins + k];
+    const bool hits = ray && ray_hi(e.meta) >= ray_lo(e.meta);
+    const int lo = hits ? ray_lo(e.meta) : 0x7fffffff;    // misses do not widen the wave's range
+    const int hi = hits ? ray_hi(e.meta) : -1;
+    const int axis = ray_axis(e.meta);
+    const int a_lo = __builtin_amdgcn_readfirstlane(wave_min_i(lo));
+    const int a_hi = __builtin_amdgcn_readfirstlane(wave_max_i(hi));
     const int line = g.line;
-    float acc0 = 0.f, acc1 = 0.f;
-    float fa = (float)(lo - g.c0);
-    int a = lo;
-    for (; a + 1 <= hi; a += 2, fa += 2.f) {
-        const float t0 = fmaf(fa, e.m, e.tc);
-        const float t1 = fmaf(fa + 1.f, e.m, e.tc);
-        const float fl0 = floorf(t0), fl1 = floorf(t1);
-        const float f0 = t0 - fl0, f1 = t1 - fl1;
-        const float* p0 = lines + (size_t)a * line + (int)fl0;
-        const float* p1 = lines + (size_t)(a + 1) * line + (int)fl1;
-        const float u0 = p0[0], u1 = p0[1], w0 = p1[0], w1 = p1[1];
-        acc0 = fmaf(1.f - f0, u0, acc0);
-        acc0 = fmaf(f0, u1, acc0);
-        acc1 = fmaf(1.f - f1, w0, acc1);
-        acc1 = fmaf(f1, w1, acc1);
+    const float* lines[BT];
+#pragma unroll
+    for (int q = 0; q < BT; q++)
+        lines[q] = pad + ((size_t)min(b0 + q, batch - 1) * 2 + axis) * g.n * line + kPad;
+    float acc[BT];
+#pragma unroll
+    for (int q = 0; q < BT; q++) acc[q] = 0.f;
+    double da = (double)(a_lo - g.c0);
+#pragma unroll 2
+    for (int a = a_lo; a <= a_hi; a++, da += 1.0) {
+        if (a >= lo && a <= hi) {
+            const double t = fma(da, e.m, e.tc);
+            const double fl = floor(t);
+            const float f = (float)(t - fl);
+            const float f1 = 1.f - f;
+            const size_t off = (size_t)a * line + (int)fl;
+#pragma unroll
+            for (int q = 0; q < BT; q++) {
+                acc[q] = fmaf(f1, lines[q][off], acc[q]);
+                acc[q] = fmaf(f, lines[q][off + 1], acc[q]);
+            }
+        }
     }
-    if (a <= hi) {
-        const float t0 = fmaf(fa, e.m, e.tc);
-        const float fl0 = floorf(t0);
-        const float f0 = t0 - fl0;
-        const float* p0 = lines + (size_t)a * line + (int)fl0;
-        acc0 = fmaf(1.f - f0, p0[0], acc0);
-        acc0 = fmaf(f0, p0[1], acc0);
-    }
-    yrow[k] = (acc0 + acc1) * e.s;
+    if (k >= g.ds) return;
+#pragma unroll
+    for (int q = 0; q < BT; q++)
+        if (b0 + q < batch) y[((size_t)(b0 + q) * g.n_views + v) * g.ds + k] = ray ? acc[q] * e.s : 0.f;
 }
+
+static int batch_tile(int batch) { return batch >= 4 ? 4 : (batch >= 2 ? 2 : 1); }
 
 hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, hipStream_t s) {
     const int chunks = (g.ds + kProjBlock - 1) / kProjBlock;
-    dim3 grid(g.n_views * chunks, batch);
-    hipLaunchKernelGGL(k_project, grid, dim3(kProjBlock), 0, s, g, pad.base, y, chunks);
+    const int bt = 1;   // one image per thread: more waves in flight beat sharing the intercepts
+    dim3 grid(g.n_views * chunks, (batch + bt - 1) / bt);
+    if (bt == 4) hipLaunchKernelGGL(k_project<4>, grid, dim3(kProjBlock), 0, s, g, pad.base, y, chunks, batch);
+    else if (bt == 2) hipLaunchKernelGGL(k_project<2>, grid, dim3(kProjBlock), 0, s, g, pad.base, y, chunks, batch);
+    else hipLaunchKernelGGL(k_project<1>, grid, dim3(kProjBlock), 0, s, g, pad.base, y, chunks, batch);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------- adjoint A^T
-// One thread per pixel, 16x16 pixels per block.  For every view the pixel
-// finds the bins whose rays can give it a non-zero Joseph weight: the
-// detector interval covered by the diamond |dx| + |dy| <= pixel around its
-// centre (any sample that touches the pixel lies inside it), widened by 0.01
-// bin.  For each candidate it re-evaluates the forward projector's own
-// float32 intercept and weight, so the result is the transpose of
-// k_project up to summation order.  No atomics.
-template <int MODE, bool REDUCE>
-__global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __restrict__ y, BpArgs a) {
+// One thread per pixel and up to BT images, 16x16 pixels per block.  For every
+// view the pixel finds the bins whose rays can give it a non-zero Joseph
+// weight: the detector interval covered by the diamond |dx| + |dy| <= pixel
+// around its centre (any sample that touches the pixel lies inside it),
+// widened by 0.01 bin.  For each candidate it re-evaluates the forward
+// projector's own intercept and float32 weight, so the result is the exact
+// transpose of k_project up to summation order.  Per view the (few) terms are
+// summed in float32, across views in float64.  No atomics.
+template <int MODE, bool REDUCE, int BT>
+__global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __restrict__ y, BpArgs a, int batch) {
     __shared__ float tile[16][17];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
     const int i = i0 + tx, j = j0 + ty;
-    const int b = blockIdx.z;
+    const int b0 = blockIdx.z * BT;
     const int n = g.n;
     const bool valid = i < n && j < n;
     const float px = ((float)i - g.half_n) * g.pixel;
     const float py = ((float)j - g.half_n) * g.pixel;
-    const float* yb = y + (size_t)b * g.n_views * g.ds;
-    float acc = 0.f;
+    const float* yb[BT];
+#pragma unroll
+    for (int q = 0; q < BT; q++) yb[q] = y + (size_t)min(b0 + q, batch - 1) * g.n_views * g.ds;
+    double tot[BT];
+#pragma unroll
+    for (int q = 0; q < BT; q++) tot[q] = 0.0;
     if (valid) {
         for (int v = 0; v < g.n_views; v++) {
             const float2 cs = g.views[v];
@@ -139,10 +172,10 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                 const float ap = fmaf(py, c, -px * s);
                 const float bp = g.sod - fmaf(px, c, py * s);
                 const float ds_ = g.pixel * s, dc = g.pixel * c;
-                const float u1 = (ap - ds_) / (bp - dc);
-                const float u2 = (ap + ds_) / (bp + dc);
-                const float u3 = (ap + dc) / (bp - ds_);
-                const float u4 = (ap - dc) / (bp + ds_);
+                const float u1 = (ap - ds_) * __builtin_amdgcn_rcpf(bp - dc);
+                const float u2 = (ap + ds_) * __builtin_amdgcn_rcpf(bp + dc);
+                const float u3 = (ap + dc) * __builtin_amdgcn_rcpf(bp - ds_);
+                const float u4 = (ap - dc) * __builtin_amdgcn_rcpf(bp + ds_);
                 umin = g.sdd * fminf(fminf(u1, u2), fminf(u3, u4));
                 umax = g.sdd * fmaxf(fmaxf(u1, u2), fmaxf(u3, u4));
             }
@@ -151,64 +184,84 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
             const int klo = max(0, (int)ceilf(fmaxf(kmin, -1.f)));
             const int khi = min(g.n_bins - 1, (int)floorf(fminf(kmax, (float)g.n_bins)));
             const RayEntry* rv = g.rays + (size_t)v * g.n_bins;
-            const float* yv = yb + (size_t)v * g.ds;
+            const size_t voff = (size_t)v * g.ds;
+            float part[BT];
+#pragma unroll
+            for (int q = 0; q < BT; q++) part[q] = 0.f;
             for (int k = klo; k <= khi; k++) {
                 const RayEntry e = rv[k];
                 const int ax = ray_axis(e.meta);
                 const int da = ax ? j : i;      // driving index of this pixel for the ray
                 const int ob = ax ? i : j;      // interpolated index
                 if (da < ray_lo(e.meta) || da > ray_hi(e.meta)) continue;
-                const float t = fmaf((float)(da - g.c0), e.m, e.tc);
-                const float fl = floorf(t);
-                const float f = t - fl;
+                const double t = fma((double)(da - g.c0), e.m, e.tc);
+                const double fl = floor(t);
+                const float f = (float)(t - fl);
                 const int j0r = (int)fl;
                 const float w = (ob == j0r) ? (1.f - f) : ((ob == j0r + 1) ? f : 0.f);
-                acc = fmaf(w, e.s * yv[k], acc);
+                const float ws = w * e.s;
+#pragma unroll
+                for (int q = 0; q < BT; q++) part[q] = fmaf(ws, yb[q][voff + k], part[q]);
             }
+#pragma unroll
+            for (int q = 0; q < BT; q++) tot[q] += (double)part[q];
         }
     }
-    const size_t idx = (size_t)b * n * n + (size_t)j * n + i;
-    double part = 0.0;
-    if (MODE == BP_PLAIN) {
-        if (valid) a.out[idx] = acc;
-    } else if (MODE == BP_MATVEC) {
-        if (valid) {
-            const float pv = a.aux[idx];
-            const float q = fmaf(a.mu, pv, acc);
-            a.out[idx] = q;
-            part = (double)pv * (double)q;
+    const int nblk = gridDim.x * gridDim.y;
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+    for (int q = 0; q < BT; q++) {
+        const int b = b0 + q;
+        if (b >= batch) break;     // uniform across the block
+        const size_t idx = (size_t)b * n * n + (size_t)j * n + i;
+        double part = 0.0;
+        if (MODE == BP_PLAIN) {
+            if (valid) a.out[idx] = (float)tot[q];
+        } else if (MODE == BP_MATVEC) {
+            if (valid) {
+                const float pv = a.aux[idx];
+                const float qv = (float)fma((double)a.mu, (double)pv, tot[q]);
+                a.out[idx] = qv;
+                part = (double)pv * (double)qv;
+            }
+        } else {  // BP_RESIDUAL
+            float r = 0.f;
+            if (valid) {
+                const float xv = a.aux[idx];
+                r = (float)((double)a.out[idx] - fma((double)a.mu, (double)xv, tot[q]));
+                a.out[idx] = r;
+                a.p_out[idx] = r;
+                part = (double)r * (double)r;
+            }
+            store_padded_tile(a.pad_out.base + (size_t)b * 2 * n * g.line, n, g.line, i0, j0, tx, ty, r, tile);
+            __syncthreads();   // the tile is reused by the next batch item
         }
-    } else {  // BP_RESIDUAL
-        float r = 0.f;
-        if (valid) {
-            const float xv = a.aux[idx];
-            r = a.out[idx] - fmaf(a.mu, xv, acc);
-            a.out[idx] = r;
-            a.p_out[idx] = r;
-            part = (double)r * (double)r;
-        }
-        store_padded_tile(a.pad_out.base + (size_t)b * 2 * n * g.line, n, g.line, i0, j0, tx, ty, r, tile);
-    }
-    if (REDUCE) {
-        const int nblk = gridDim.x * gridDim.y;
-        const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-        block_reduce_last<256>(part, a.red_partial + (size_t)b * nblk, a.red_count + b, a.red_out + b, nblk, blk);
+        if (REDUCE)
+            block_reduce_last<256>(part, a.red_partial + (size_t)b * nblk, a.red_count + b, a.red_out + b, nblk, blk);
     }
 }
 
+template <int MODE, bool REDUCE>
+static void launch_bp_mode(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s) {
+    const int bt = batch_tile(batch);
+    dim3 grid((g.n + 15) / 16, (g.n + 15) / 16, (batch + bt - 1) / bt), block(256);
+    if (bt == 4) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 4>), grid, block, 0, s, g, y, a, batch);
+    else if (bt == 2) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 2>), grid, block, 0, s, g, y, a, batch);
+    else hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 1>), grid, block, 0, s, g, y, a, batch);
+}
+
 hipError_t launch_backproject(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s) {
-    dim3 grid((g.n + 15) / 16, (g.n + 15) / 16, batch), block(256);
     const bool red = a.red_partial != nullptr;
     switch (a.mode) {
     case BP_PLAIN:
-        hipLaunchKernelGGL((k_backproject<BP_PLAIN, false>), grid, block, 0, s, g, y, a);
+        launch_bp_mode<BP_PLAIN, false>(g, y, a, batch, s);
         break;
     case BP_MATVEC:
-        if (red) hipLaunchKernelGGL((k_backproject<BP_MATVEC, true>), grid, block, 0, s, g, y, a);
-        else hipLaunchKernelGGL((k_backproject<BP_MATVEC, false>), grid, block, 0, s, g, y, a);
+        if (red) launch_bp_mode<BP_MATVEC, true>(g, y, a, batch, s);
+        else launch_bp_mode<BP_MATVEC, false>(g, y, a, batch, s);
         break;
     case BP_RESIDUAL:
-        hipLaunchKernelGGL((k_backproject<BP_RESIDUAL, true>), grid, block, 0, s, g, y, a);
+        launch_bp_mode<BP_RESIDUAL, true>(g, y, a, batch, s);
         break;
     default:
         return hipErrorInvalidValue;
