@@ -120,15 +120,27 @@ __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __
         if (b0 + q < batch) y[((size_t)(b0 + q) * g.n_views + v) * g.ds + k] = ray ? acc[q] * e.s : 0.f;
 }
 
-static int batch_tile(int batch) { return batch >= 4 ? 4 : (batch >= 2 ? 2 : 1); }
+// Images per backprojector thread.  The detector window and the table reads
+// (about two thirds of the per-candidate work) are shared by the tile, so a
+// group of BT images costs roughly (2 + BT) units: pick the tile that
+// minimises ceil(batch / BT) * (2 + BT).
+static int batch_tile(int batch) {
+    int best = 1, best_cost = batch * 3;
+    for (int bt : {2, 4, 8}) {
+        const int cost = (batch + bt - 1) / bt * (2 + bt);
+        if (cost < best_cost) {
+            best = bt;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
 
 hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, hipStream_t s) {
     const int chunks = (g.ds + kProjBlock - 1) / kProjBlock;
     const int bt = 1;   // one image per thread: more waves in flight beat sharing the intercepts
     dim3 grid(g.n_views * chunks, (batch + bt - 1) / bt);
-    if (bt == 4) hipLaunchKernelGGL(k_project<4>, grid, dim3(kProjBlock), 0, s, g, pad.base, y, chunks, batch);
-    else if (bt == 2) hipLaunchKernelGGL(k_project<2>, grid, dim3(kProjBlock), 0, s, g, pad.base, y, chunks, batch);
-    else hipLaunchKernelGGL(k_project<1>, grid, dim3(kProjBlock), 0, s, g, pad.base, y, chunks, batch);
+    hipLaunchKernelGGL(k_project<1>, grid, dim3(kProjBlock), 0, s, g, pad.base, y, chunks, batch);
     return hipGetLastError();
 }
 
@@ -245,7 +257,8 @@ template <int MODE, bool REDUCE>
 static void launch_bp_mode(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s) {
     const int bt = batch_tile(batch);
     dim3 grid((g.n + 15) / 16, (g.n + 15) / 16, (batch + bt - 1) / bt), block(256);
-    if (bt == 4) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 4>), grid, block, 0, s, g, y, a, batch);
+    if (bt == 8) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 8>), grid, block, 0, s, g, y, a, batch);
+    else if (bt == 4) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 4>), grid, block, 0, s, g, y, a, batch);
     else if (bt == 2) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 2>), grid, block, 0, s, g, y, a, batch);
     else hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 1>), grid, block, 0, s, g, y, a, batch);
 }

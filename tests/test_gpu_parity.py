@@ -75,44 +75,48 @@ def sino_for(name, seed=0):
 # ----------------------------------------------------------------------------- operators
 
 @pytest.mark.parametrize("name", ["c1", "ragged", "c2"])
-def test_project_parity(air, torch_mod, orc, name):
+def test_project_parity(air, torch_mod, orc, record, name):
     g = geom(name)
     x = image_for(name).astype(np.float32)
     plan = air.Plan(g, max_batch=1)
     y = host(plan.project(dev(torch_mod, x[None])))[0]
     ref = orc.project(orc.Geom(g), x.astype(np.float64))
+    record("rel_l2_A", rel(y, ref))
     assert rel(y, ref) < 1e-5
 
 
 @pytest.mark.parametrize("prec", ["fp32", "mixed_f16", "mixed_bf16"])
 @pytest.mark.parametrize("name", ["c1", "ragged", "c2"])
-def test_ramp_parity(air, torch_mod, orc, name, prec):
+def test_ramp_parity(air, torch_mod, orc, record, name, prec):
     g = geom(name)
     y = sino_for(name).astype(np.float32)
     plan = air.Plan(g, max_batch=1, precision=prec)
     yf = host(plan.ramp(dev(torch_mod, y[None])))[0]
     ref = orc.ramp(orc.Geom(g), y.astype(np.float64))
+    record("rel_l2_C", rel(yf, ref))
     assert rel(yf, ref) < 1e-5, (name, prec, rel(yf, ref))
 
 
 @pytest.mark.parametrize("filt", [0, 1])
 @pytest.mark.parametrize("name", ["c1", "ragged", "c2"])
-def test_filtered_backproject_parity(air, torch_mod, orc, name, filt):
+def test_filtered_backproject_parity(air, torch_mod, orc, record, name, filt):
     g = geom(name)
     y = sino_for(name).astype(np.float32)
     plan = air.Plan(g, max_batch=1)
     x = host(plan.filtered_backproject(dev(torch_mod, y[None]), filter=filt))[0]
     ref = orc.filtered_backproject(orc.Geom(g), y.astype(np.float64), filt)
+    record("rel_l2_AtC" if filt else "rel_l2_At", rel(x, ref))
     assert rel(x, ref) < 1e-5, rel(x, ref)
 
 
 @pytest.mark.parametrize("name", ["c1", "ragged", "c2"])
-def test_normal_operator_parity(air, torch_mod, orc, name):
+def test_normal_operator_parity(air, torch_mod, orc, record, name):
     g = geom(name)
     x = image_for(name).astype(np.float32)
     plan = air.Plan(g, max_batch=1)
     out = host(plan.normal_apply(dev(torch_mod, x[None]), 1.0, 1))[0]
     ref = orc.apply_normal(orc.Geom(g), x.astype(np.float64), 1.0, 1)
+    record("rel_l2_M", rel(out, ref))
     assert rel(out, ref) < 1e-5
 
 
@@ -182,12 +186,13 @@ def _oracle_solve(orc, g, y32, w, **kw):
     return orc.solve(orc.Geom(g), y32.astype(np.float64), w.lam, w.mu, w.n_outer, w.n_cg, **kw)
 
 
-def test_solve_parity_c1(air, torch_mod, orc):
+def test_solve_parity_c1(air, torch_mod, orc, record):
     w = synth.workload("c1")
     y = synth.make_case(w, 0)["y"].astype(np.float32)
     plan = air.Plan(w.geom)
     x, resid = plan.solve(dev(torch_mod, y[None]), w.lam, w.mu, w.n_outer, w.n_cg)
     xr, rr = _oracle_solve(orc, w.geom, y, w)
+    record("rel_l2_final", rel(host(x)[0], xr))
     assert rel(host(x)[0], xr) < 1e-4
     np.testing.assert_allclose(host(resid)[0], rr, rtol=1e-3)
 
@@ -244,17 +249,18 @@ def test_solve_batch_invariance_and_determinism(air, torch_mod):
 
 
 @pytest.mark.parametrize("prec", ["mixed_f16", "mixed_bf16"])
-def test_solve_mixed_precision_c1(air, torch_mod, orc, prec):
+def test_solve_mixed_precision_c1(air, torch_mod, orc, record, prec):
     w = synth.workload("c1")
     y = synth.make_case(w, 0)["y"].astype(np.float32)
     plan = air.Plan(w.geom, precision=prec)
     x, _ = plan.solve(dev(torch_mod, y[None]), w.lam, w.mu, w.n_outer, w.n_cg)
     xr, _ = _oracle_solve(orc, w.geom, y, w)
+    record("rel_l2_final", rel(host(x)[0], xr))
     assert rel(host(x)[0], xr) < 1e-3
 
 
 @pytest.mark.parametrize("case,wname", [("c2_fan_512_720_seed0", "c2"), ("c2_fan_512_180_seed0", "c2_25")])
-def test_solve_parity_c2_full_size(air, torch_mod, case, wname):
+def test_solve_parity_c2_full_size(air, torch_mod, record, case, wname):
     """512^2 fan beam, 50 Bregman x 5 CG, 720 and 180 views, against the stored
     oracle reconstruction (tests/golden/make_refs.py)."""
     path = os.path.join(HERE, "golden", case + ".npz")
@@ -263,5 +269,6 @@ def test_solve_parity_c2_full_size(air, torch_mod, case, wname):
     y = synth.make_case(w, 0)["y"].astype(np.float32)
     plan = air.Plan(w.geom)
     x, resid = plan.solve(dev(torch_mod, y[None]), w.lam, w.mu, w.n_outer, w.n_cg)
+    record("rel_l2_final", rel(host(x)[0], ref["x"]))
     assert rel(host(x)[0], ref["x"]) < 1e-4
     np.testing.assert_allclose(host(resid)[0], ref["resid"], rtol=1e-2)
