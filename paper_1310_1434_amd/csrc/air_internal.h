@@ -30,6 +30,7 @@ struct KGeom {
     float half_d;   // (n_bins - 1) / 2
     float sod, sdd; // fan geometry, mm
     const RayEntry* rays;   // [n_views][n_bins]
+    const float* step;      // [n_views][ds] path length per driving step (0 in the padding)
     const float2* views;    // [n_views] (cos, sin) as float
 };
 
@@ -40,14 +41,18 @@ struct PadBuf {
 
 // ---- kernel launchers (kernels_*.hip) -------------------------------------------------
 hipError_t launch_pad(const KGeom& g, const float* x, PadBuf pad, int batch, hipStream_t s);
-hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, hipStream_t s);
+// y = J x (scaled = false: bare interpolation weights) or y = A x = S J x (scaled = true).
+hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, bool scaled, hipStream_t s);
+// y <- y * step^power, elementwise over internal rows [batch * n_views][ds] (power 1 or 2).
+hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, int power, hipStream_t s);
 
-// Backprojection epilogue modes (per pixel, acc = (A^T y)_pixel):
+// Backprojection epilogue modes (per pixel, acc = (J^T y)_pixel, J the bare
+// interpolation weights; callers fold the path lengths into y):
 enum BpMode {
     BP_PLAIN = 0,     // out = acc
-    BP_MATVEC = 1,    // out = acc + mu * p;  scalar pq[b] = p . out   (float64)
+    BP_MATVEC = 1,    // out = acc + mu * p;  partial sums of p . out (float64)
     BP_RESIDUAL = 2,  // r = rhs - (acc + mu * x) (rhs read from `out`, r written there);
-                      // p = r, padded copy of p; scalar rr[b] = r . r
+                      // p = r, padded copy of p; partial sums of r . r
 };
 struct BpArgs {
     int mode;
@@ -56,9 +61,7 @@ struct BpArgs {
     float* out;         // [batch][n][n]
     float* p_out;       // RESIDUAL: p
     PadBuf pad_out;     // RESIDUAL: padded copy of p
-    double* red_partial;    // [batch][blocks] float64 partial sums
-    unsigned* red_count;    // [batch] arrival counters (zero on entry, re-zeroed by the last block)
-    double* red_out;        // [batch] reduced scalar
+    double* partial;    // [batch][tiles16(n)] block partial sums, or null (MATVEC only)
 };
 hipError_t launch_backproject(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s);
 
@@ -69,6 +72,8 @@ hipError_t launch_repack(const float* src, int src_stride, float* dst, int dst_s
 // Ramp filtration y' = C y over rows of stride ds (internal layout).
 struct RampTables {
     const float* taps32;       // [2 ds] kappa r(m) at index m + ds
+    const float* step;         // [n_views][ds] path lengths (for the scaled variants)
+    int n_views;
     const uint4* frag_a;       // 16-bit fragments, first split term (f16 hi / bf16 t1)
     const uint4* frag_b;       // second split term (f16 lo / bf16 t2)
     const uint4* frag_c;       // third split term (bf16 t3), or null
@@ -76,7 +81,9 @@ struct RampTables {
     int dmin;
     float out_scale;           // kappa * 2^-12 for the 16-bit modes
 };
-hipError_t launch_ramp(int prec, const RampTables& t, const float* y, float* yf, int rows, int ds,
+// scale: 0 = C y;  RAMP_POST = S C y;  RAMP_PRE | RAMP_POST = S C S y  (S = diag(step))
+enum { RAMP_PRE = 1, RAMP_POST = 2 };
+hipError_t launch_ramp(int prec, const RampTables& t, const float* y, float* yf, int rows, int ds, int scale,
                        hipStream_t s);
 
 // CG vector updates on 16x16 tiles (float32 vectors, float64 scalars).
@@ -84,33 +91,40 @@ struct CgArgs {
     int n;
     float* x; float* r; float* p; const float* q;
     PadBuf pad;                 // padded copy target (x or p), or base = null
-    const double* rho_cur;      // [batch]
-    const double* pq;           // [batch]
-    const double* rho_new_in;   // [batch] (update_p)
-    double* red_partial; unsigned* red_count; double* red_out;
+    const double* alpha;        // [batch] (update_xr)
+    const double* beta;         // [batch] (update_p)
+    double* partial;            // [batch][tiles16(n)] partial sums of r . r (update_xr)
 };
-hipError_t launch_cg_update_xr(const CgArgs& a, int batch, hipStream_t s);   // x += a p, r -= a q, rho' = r.r
+hipError_t launch_cg_update_xr(const CgArgs& a, int batch, hipStream_t s);   // x += a p, r -= a q; partials of r.r
 hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s);    // p = r + b p (+ pad)
+
+// Fixed-order sums of the block partials [batch][nblk] and the scalars derived from them:
+enum FinalizeMode {
+    FIN_RHO = 0,    // rho[b] = sum                                    (initial residual)
+    FIN_ALPHA = 1,  // pq = sum; alpha[b] = rho / pq (0 if either is 0)
+    FIN_BETA = 2,   // rho' = sum; beta[b] = rho' / rho (0 if rho is 0); rho[b] = rho'
+    FIN_RESID = 3,  // out[b * stride] = sqrt(sum)                     (Bregman residual)
+};
+hipError_t launch_finalize(int mode, const double* partial, int nblk, int batch, double* rho, double* coef,
+                           double* out, int stride, hipStream_t s);
 
 // Framelet kernels.
 hipError_t launch_framelet_fwd(int n, const float* x, float* z, int batch, hipStream_t s);
 hipError_t launch_framelet_adj(int n, const float* z, float* x, int batch, hipStream_t s);
 // rhs = g + mu W^T e
 hipError_t launch_tf_rhs(int n, const float* g, const float* e, float mu, float* rhs, int batch, hipStream_t s);
-// v = W x + b (bands 1..8 of b), d = shrink(v, thr) (band 0: d = v), b <- v - d, e <- d - b,
-// resid[b] = ||W x - d||_2 (float64, written at resid + b * resid_stride when resid != null)
+// v = W x + b (bands 1..8 of b), d = shrink(v, thr) (band 0: d = v), b <- v - d, e <- d - b;
+// partial sums of ||W x - d||^2.
 struct TfArgs {
     int n;
     const float* x;
     float* bb;          // [batch][8][n][n]
     float* e;           // [batch][9][n][n]
     float thr;
-    double* red_partial; unsigned* red_count; double* red_out;
-    double* resid; int resid_stride;
+    double* partial;    // [batch][tiles16(n)]
 };
 hipError_t launch_tf_shrink(const TfArgs& a, int batch, hipStream_t s);
 hipError_t launch_fill(float* p, size_t count, float v, hipStream_t s);
-hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t s);
 
 // Number of 16x16 tiles of an n x n image (blocks per batch item of tile kernels).
 inline int tiles16(int n) { return ((n + 15) / 16) * ((n + 15) / 16); }

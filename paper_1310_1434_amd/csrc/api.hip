@@ -99,6 +99,7 @@ struct air_plan_s {
     int ds = 0, line = 0, c0 = 0;
     double kappa = 0.0;
     std::vector<RayEntry> rays;
+    std::vector<float> step;       // [n_views][ds] path length per driving step, 0 in the padding
     std::vector<int8_t> axis;
     std::vector<int32_t> lo, hi;
     std::vector<float> views;      // interleaved (cos, sin) as float
@@ -106,8 +107,8 @@ struct air_plan_s {
     std::vector<uint16_t> frag[3];
     int n_terms = 0, n_frag = 0, dmin = 0;
     // workspace layout (bytes)
-    size_t off_rays = 0, off_views = 0, off_taps = 0, off_frag[3] = {0, 0, 0};
-    size_t off_pad = 0, off_s1 = 0, off_s2 = 0, off_part = 0, off_cnt = 0, off_scal = 0, total = 0;
+    size_t off_rays = 0, off_step = 0, off_views = 0, off_taps = 0, off_frag[3] = {0, 0, 0};
+    size_t off_pad = 0, off_s1 = 0, off_s2 = 0, total = 0;
     char* ws = nullptr;
     // per-kernel event timing (air_kernel_timing_enable)
     struct Timed {
@@ -152,12 +153,15 @@ struct air_plan_s {
         k.sod = (float)g.sod;
         k.sdd = (float)g.sdd;
         k.rays = reinterpret_cast<const RayEntry*>(ws + off_rays);
+        k.step = reinterpret_cast<const float*>(ws + off_step);
         k.views = reinterpret_cast<const float2*>(ws + off_views);
         return k;
     }
     RampTables ramp_tables() const {
         RampTables t;
         t.taps32 = reinterpret_cast<const float*>(ws + off_taps);
+        t.step = reinterpret_cast<const float*>(ws + off_step);
+        t.n_views = g.n_views;
         t.frag_a = n_terms > 0 ? reinterpret_cast<const uint4*>(ws + off_frag[0]) : nullptr;
         t.frag_b = n_terms > 1 ? reinterpret_cast<const uint4*>(ws + off_frag[1]) : nullptr;
         t.frag_c = n_terms > 2 ? reinterpret_cast<const uint4*>(ws + off_frag[2]) : nullptr;
@@ -276,11 +280,15 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
         p->line = g.n + 2 * kPad;
         p->c0 = g.n / 2;
         p->kappa = 3.14159265358979323846 / ((double)g.n_views * g.pixel * g.pixel);
-        const std::string err = build_ray_tables(g, p->rays, p->axis, p->lo, p->hi);
+        std::vector<float> step;
+        const std::string err = build_ray_tables(g, p->rays, step, p->axis, p->lo, p->hi);
         if (!err.empty()) {
             delete p;
             return fail(AIR_E_UNSUPPORTED, err);
         }
+        p->step.assign((size_t)g.n_views * p->ds, 0.f);
+        for (int v = 0; v < g.n_views; v++)
+            for (int k = 0; k < g.n_bins; k++) p->step[(size_t)v * p->ds + k] = step[(size_t)v * g.n_bins + k];
         p->views.resize(2 * (size_t)g.n_views);
         for (int v = 0; v < g.n_views; v++) {
             p->views[2 * v] = (float)g.cosv[v];
@@ -326,6 +334,7 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
         Carver c;
         const size_t nr = (size_t)g.n_views * g.n_bins;
         p->off_rays = c.take(nr * sizeof(RayEntry));
+        p->off_step = c.take(p->step.size() * sizeof(float));
         p->off_views = c.take(p->views.size() * sizeof(float));
         p->off_taps = c.take(p->taps32.size() * sizeof(float));
         for (int t = 0; t < p->n_terms; t++) p->off_frag[t] = c.take(p->frag[t].size() * sizeof(uint16_t));
@@ -333,9 +342,6 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
         p->off_pad = c.take(mb * 2 * g.n * p->line * sizeof(float));
         p->off_s1 = c.take(mb * g.n_views * ds * sizeof(float));
         p->off_s2 = c.take(mb * g.n_views * ds * sizeof(float));
-        p->off_part = c.take(mb * tiles16(g.n) * sizeof(double));
-        p->off_cnt = c.take(mb * sizeof(unsigned));
-        p->off_scal = c.take(mb * 4 * sizeof(double));
         p->total = c.off;
     } catch (const std::bad_alloc&) {
         delete p;
@@ -360,6 +366,8 @@ air_status air_plan_bind_workspace(air_plan p, void* dev, size_t bytes, hipStrea
     char* ws = static_cast<char*>(dev);
     AIR_HIP(hipMemcpyAsync(ws + p->off_rays, p->rays.data(), p->rays.size() * sizeof(RayEntry),
                            hipMemcpyHostToDevice, s));
+    AIR_HIP(hipMemcpyAsync(ws + p->off_step, p->step.data(), p->step.size() * sizeof(float),
+                           hipMemcpyHostToDevice, s));
     AIR_HIP(hipMemcpyAsync(ws + p->off_views, p->views.data(), p->views.size() * sizeof(float),
                            hipMemcpyHostToDevice, s));
     AIR_HIP(hipMemcpyAsync(ws + p->off_taps, p->taps32.data(), p->taps32.size() * sizeof(float),
@@ -367,7 +375,6 @@ air_status air_plan_bind_workspace(air_plan p, void* dev, size_t bytes, hipStrea
     for (int t = 0; t < p->n_terms; t++)
         AIR_HIP(hipMemcpyAsync(ws + p->off_frag[t], p->frag[t].data(), p->frag[t].size() * sizeof(uint16_t),
                                hipMemcpyHostToDevice, s));
-    AIR_HIP(hipMemsetAsync(ws + p->off_cnt, 0, (size_t)p->max_batch * sizeof(unsigned), s));
     AIR_HIP(hipStreamSynchronize(s));
     p->ws = ws;
     return AIR_OK;
@@ -392,10 +399,10 @@ air_status air_project(air_plan p, const float* x, float* y, int32_t batch, hipS
     PadBuf pad{p->at<float>(p->off_pad)};
     AIR_K(AIR_K_OTHER, launch_pad(kg, x, pad, batch, s));
     if (p->direct(y)) {
-        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, y, batch, s));
+        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, y, batch, true, s));
     } else {
         float* s1 = p->at<float>(p->off_s1);
-        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, s));
+        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, true, s));
         AIR_K(AIR_K_OTHER, launch_repack(s1, p->ds, y, p->g.n_bins, batch * p->g.n_views, p->g.n_bins, p->g.n_bins, s));
     }
     return AIR_OK;
@@ -410,10 +417,10 @@ air_status air_ramp(air_plan p, const float* y, float* yf, int32_t batch, hipStr
     if (air_status st = stage_sino(p, y, batch, p->at<float>(p->off_s1), &src, s)) return st;
     const int rows = batch * p->g.n_views;
     if (p->direct(yf)) {
-        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, yf, rows, p->ds, s));
+        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, yf, rows, p->ds, 0, s));
     } else {
         float* s2 = p->at<float>(p->off_s2);
-        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, s2, rows, p->ds, s));
+        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, s2, rows, p->ds, 0, s));
         AIR_K(AIR_K_OTHER, launch_repack(s2, p->ds, yf, p->g.n_bins, rows, p->g.n_bins, p->g.n_bins, s));
     }
     return AIR_OK;
@@ -425,17 +432,17 @@ air_status air_filtered_backproject(air_plan p, const float* y, float* x, int32_
     if (air_status st = check_batch(p, batch, true)) return st;
     if (!y || !x) return fail(AIR_E_INVALID, "null pointer");
     if (filter != 0 && filter != 1) return fail(AIR_E_INVALID, "filter must be 0 or 1");
+    // A^T C y = J^T (S C y); A^T y = J^T (S y)
     const float* src = nullptr;
     if (air_status st = stage_sino(p, y, batch, p->at<float>(p->off_s1), &src, s)) return st;
-    if (filter) {
-        float* s2 = p->at<float>(p->off_s2);
-        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, s2, batch * p->g.n_views, p->ds, s));
-        src = s2;
-    }
+    float* s2 = p->at<float>(p->off_s2);
+    if (filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, s2, batch * p->g.n_views, p->ds,
+                                              RAMP_POST, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(p->kgeom(), src, s2, batch, 1, s));
     BpArgs a{};
     a.mode = BP_PLAIN;
     a.out = x;
-    AIR_K(AIR_K_BACKPROJECT, launch_backproject(p->kgeom(), src, a, batch, s));
+    AIR_K(AIR_K_BACKPROJECT, launch_backproject(p->kgeom(), s2, a, batch, s));
     return AIR_OK;
 }
 
@@ -451,13 +458,13 @@ air_status air_normal_apply(air_plan p, const float* x, float* out, int32_t batc
     PadBuf pad{p->at<float>(p->off_pad)};
     float* s1 = p->at<float>(p->off_s1);
     float* s2 = p->at<float>(p->off_s2);
+    // A^T C A x = J^T (S C S) J x;  A^T A x = J^T S^2 J x
     AIR_K(AIR_K_OTHER, launch_pad(kg, x, pad, batch, s));
-    AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, s));
-    const float* src = s1;
-    if (filter) {
-        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), s1, s2, batch * p->g.n_views, p->ds, s));
-        src = s2;
-    }
+    AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, false, s));
+    if (filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), s1, s2, batch * p->g.n_views, p->ds,
+                                              RAMP_PRE | RAMP_POST, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 2, s));
+    const float* src = s2;
     BpArgs a{};
     a.mode = BP_MATVEC;
     a.mu = (float)mu;
@@ -507,7 +514,7 @@ air_status air_framelet(air_plan p, const float* in, float* out, int32_t batch, 
 namespace {
 
 struct SolveLayout {
-    size_t pad, s1, s2, g, r, p, q, bb, e, part, cnt, scal, total;
+    size_t pad, s1, s2, g, r, p, q, bb, e, part, scal, total;
 };
 
 SolveLayout solve_layout(const air_plan_s* p, int batch) {
@@ -524,7 +531,6 @@ SolveLayout solve_layout(const air_plan_s* p, int batch) {
     L.bb = c.take(B * 8 * np * sizeof(float));
     L.e = c.take(B * 9 * np * sizeof(float));
     L.part = c.take(B * tiles16((int)n) * sizeof(double));
-    L.cnt = c.take(B * sizeof(unsigned));
     L.scal = c.take(B * 4 * sizeof(double));
     L.total = c.off;
     return L;
@@ -560,33 +566,31 @@ air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const 
     auto F = [&](size_t off) { return reinterpret_cast<float*>(w + off); };
     const KGeom kg = p->kgeom();
     const RampTables rt = p->ramp_tables();
-    const int n = p->g.n, rows = batch * p->g.n_views;
+    const int n = p->g.n, rows = batch * p->g.n_views, nblk = tiles16(n);
     const size_t np = (size_t)n * n;
     PadBuf pad{F(L.pad)};
     float *s1 = F(L.s1), *s2 = F(L.s2), *g = F(L.g), *r = F(L.r), *pv = F(L.p), *q = F(L.q);
     float *bb = F(L.bb), *e = F(L.e);
     double* part = reinterpret_cast<double*>(w + L.part);
-    unsigned* cnt = reinterpret_cast<unsigned*>(w + L.cnt);
     double* scal = reinterpret_cast<double*>(w + L.scal);
-    double* rho[2] = {scal, scal + batch};
-    double* pq = scal + 2 * batch;
-    double* tfred = scal + 3 * batch;
+    double* rho = scal;                 // [batch] current r . r
+    double* alpha = scal + batch;       // [batch]
+    double* beta = scal + 2 * batch;    // [batch]
+    double* junk = scal + 3 * batch;    // [batch] residual norms when the caller wants none
     const bool tf = prm->reg == 0;
     const float mu_op = (float)(tf ? prm->mu : prm->lambda);
 
-    AIR_K(AIR_K_OTHER, launch_fill_u32(cnt, (size_t)batch, 0u, s));
     // g = A'^T Y (or A^T Y)
+    // (A = S J: the path lengths are applied in the ramp stage, or by a scaling pass for the IR arm)
     const float* src = nullptr;
     if (air_status st = stage_sino(p, Y, batch, s1, &src, s)) return st;
-    if (prm->filter) {
-        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, src, s2, rows, p->ds, s));
-        src = s2;
-    }
+    if (prm->filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, src, s2, rows, p->ds, RAMP_POST, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(kg, src, s2, batch, 1, s));
     {
         BpArgs a{};
         a.mode = BP_PLAIN;
         a.out = g;
-        AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, src, a, batch, s));
+        AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, s2, a, batch, s));
     }
     if (tf) {
         AIR_K(AIR_K_OTHER, launch_fill(bb, (size_t)batch * 8 * np, 0.f, s));
@@ -598,12 +602,10 @@ air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const 
         if (tf) AIR_K(AIR_K_FRAMELET, launch_tf_rhs(n, g, e, (float)prm->mu, r, batch, s));
         else AIR_HIP(hipMemcpyAsync(r, g, (size_t)batch * np * sizeof(float), hipMemcpyDeviceToDevice, s));
         // r = rhs - M X, p = r, rho = r.r
-        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, s));
-        const float* bsrc = s1;
-        if (prm->filter) {
-            AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, s1, s2, rows, p->ds, s));
-            bsrc = s2;
-        }
+        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, false, s));
+        if (prm->filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, s1, s2, rows, p->ds, RAMP_PRE | RAMP_POST, s));
+        else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 2, s));
+        const float* bsrc = s2;
         {
             BpArgs a{};
             a.mode = BP_RESIDUAL;
@@ -612,24 +614,22 @@ air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const 
             a.out = r;
             a.p_out = pv;
             a.pad_out = pad;
-            a.red_partial = part;
-            a.red_count = cnt;
-            a.red_out = rho[0];
+            a.partial = part;
             AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, bsrc, a, batch, s));
+            AIR_K(AIR_K_CG, launch_finalize(FIN_RHO, part, nblk, batch, rho, nullptr, nullptr, 0, s));
         }
-        int c = 0;
         for (int it = 0; it < prm->n_cg; it++) {
-            AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, s));
-            if (prm->filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, s1, s2, rows, p->ds, s));
+            AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, false, s));
+            if (prm->filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, s1, s2, rows, p->ds, RAMP_PRE | RAMP_POST, s));
+            else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 2, s));
             BpArgs a{};
             a.mode = BP_MATVEC;
             a.mu = mu_op;
             a.aux = pv;
             a.out = q;
-            a.red_partial = part;
-            a.red_count = cnt;
-            a.red_out = pq;
-            AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, prm->filter ? s2 : s1, a, batch, s));
+            a.partial = part;
+            AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, s2, a, batch, s));
+            AIR_K(AIR_K_CG, launch_finalize(FIN_ALPHA, part, nblk, batch, rho, alpha, nullptr, 0, s));
             CgArgs cg{};
             cg.n = n;
             cg.x = X;
@@ -637,18 +637,15 @@ air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const 
             cg.p = pv;
             cg.q = q;
             cg.pad.base = it == prm->n_cg - 1 ? pad.base : nullptr;
-            cg.rho_cur = rho[c];
-            cg.pq = pq;
-            cg.red_partial = part;
-            cg.red_count = cnt;
-            cg.red_out = rho[1 - c];
+            cg.alpha = alpha;
+            cg.beta = beta;
+            cg.partial = part;
             AIR_K(AIR_K_CG, launch_cg_update_xr(cg, batch, s));
             if (it < prm->n_cg - 1) {
+                AIR_K(AIR_K_CG, launch_finalize(FIN_BETA, part, nblk, batch, rho, beta, nullptr, 0, s));
                 cg.pad = pad;
-                cg.rho_new_in = rho[1 - c];
                 AIR_K(AIR_K_CG, launch_cg_update_p(cg, batch, s));
             }
-            c = 1 - c;
         }
         if (prm->n_cg == 0) AIR_K(AIR_K_OTHER, launch_pad(kg, X, pad, batch, s));
         if (tf) {
@@ -658,12 +655,10 @@ air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const 
             t.bb = bb;
             t.e = e;
             t.thr = (float)(prm->lambda / (2.0 * prm->mu));
-            t.red_partial = part;
-            t.red_count = cnt;
-            t.red_out = tfred;
-            t.resid = resid ? resid + k : nullptr;
-            t.resid_stride = prm->n_outer;
+            t.partial = part;
             AIR_K(AIR_K_FRAMELET, launch_tf_shrink(t, batch, s));
+            AIR_K(AIR_K_FRAMELET, launch_finalize(FIN_RESID, part, nblk, batch, nullptr, nullptr,
+                                                  resid ? resid + k : junk, resid ? prm->n_outer : 1, s));
         }
     }
     return AIR_OK;

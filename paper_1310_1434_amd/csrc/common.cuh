@@ -20,46 +20,24 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Deterministic block reduction of one float64 per thread.  Every block writes
-// its partial to partial[blk]; the block that arrives last (device-scope
-// counter) sums all partials in index order with a fixed tree and writes *out,
-// then re-arms the counter.  The result does not depend on which block is last
-// or on how many batch items share the launch.
+// Block sum of one float64 per thread with a fixed tree (wave shuffles, then
+// the waves in order); thread 0 stores it to *slot.  The partials of all
+// blocks are summed by k_finalize in index order, so a reduction gives the
+// same bits whatever the batch size or the order in which blocks run.
 template <int BLOCK>
-__device__ __forceinline__ void block_reduce_last(double v, double* partial, unsigned* count, double* out,
-                                                  int nblk, int blk) {
+__device__ __forceinline__ void block_partial(double v, double* slot) {
     __shared__ double sh[BLOCK / kWave];
-    __shared__ bool last;
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-    const int lane = tid % kWave, wid = tid / kWave;
     v = wave_sum(v);
-    if (lane == 0) sh[wid] = v;
+    if (tid % kWave == 0) sh[tid / kWave] = v;
     __syncthreads();
     if (tid == 0) {
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < BLOCK / kWave; w++) s += sh[w];
-        partial[blk] = s;
-        __threadfence();
-        const unsigned prev = atomicAdd(count, 1u);
-        last = (prev == (unsigned)(nblk - 1));
+        *slot = s;
     }
     __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double s = 0.0;
-    for (int i = tid; i < nblk; i += BLOCK) s += __hip_atomic_load(partial + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s = wave_sum(s);
-    __syncthreads();
-    if (lane == 0) sh[wid] = s;
-    __syncthreads();
-    if (tid == 0) {
-        double t = 0.0;
-#pragma unroll
-        for (int w = 0; w < BLOCK / kWave; w++) t += sh[w];
-        *out = t;
-        atomicExch(count, 0u);
-    }
 }
 
 // Write one 16x16 tile of an image into its two padded line sets: rows (line

@@ -71,11 +71,12 @@ void ramp_taps64(int n_bins, std::vector<double>& r) {
     }
 }
 
-std::string build_ray_tables(const GeomHost& g, std::vector<RayEntry>& rays, std::vector<int8_t>& axis,
-                             std::vector<int32_t>& lo, std::vector<int32_t>& hi) {
+std::string build_ray_tables(const GeomHost& g, std::vector<RayEntry>& rays, std::vector<float>& step,
+                             std::vector<int8_t>& axis, std::vector<int32_t>& lo, std::vector<int32_t>& hi) {
     const int n = g.n;
     const size_t nr = (size_t)g.n_views * g.n_bins;
     rays.resize(nr);
+    step.resize(nr);
     axis.resize(nr);
     lo.resize(nr);
     hi.resize(nr);
@@ -132,19 +133,19 @@ std::string build_ray_tables(const GeomHost& g, std::vector<RayEntry>& rays, std
             lo[idx] = a_lo;
             hi[idx] = a_hi;
             RayEntry e;
-            e.tc = t_at(g, r, slope, c0);
-            e.m = slope;
-            e.s = (float)(g.pixel * std::sqrt(r.da * r.da + r.db * r.db) / std::fabs(r.da));
+            e.tc = std::llround((t_at(g, r, slope, c0) + (double)kPad) * std::ldexp(1.0, kFrac));
+            const double ms = std::nearbyint(slope * std::ldexp(1.0, kSlopeFrac));   // |slope| <= 1
+            e.m = (int32_t)(ms > 2147483647.0 ? 2147483647.0 : (ms < -2147483647.0 ? -2147483647.0 : ms));
+            step[idx] = (float)(g.pixel * std::sqrt(r.da * r.da + r.db * r.db) / std::fabs(r.da));
             e.meta = (int32_t)((uint32_t)a_lo | ((uint32_t)(a_hi + 1) << 15) | ((uint32_t)r.axis << 30));
             if (a_hi < a_lo) e.meta = (int32_t)((uint32_t)r.axis << 30);
-            e.unused[0] = e.unused[1] = 0;
-            // The kernels sample padded lines at floor(t) and floor(t) + 1 with
-            // t = fma(a - c0, m, tc); keep both inside the two-sample padding.
+            // The kernels sample padded lines at T >> kFrac and the next sample;
+            // both must stay inside the line (indices 0 .. n + 2 kPad - 1).
             if (a_hi >= a_lo) {
-                const double ta = std::fma((double)(a_lo - c0), e.m, e.tc);
-                const double tb = std::fma((double)(a_hi - c0), e.m, e.tc);
-                const double tmin = ta < tb ? ta : tb, tmax = ta < tb ? tb : ta;
-                if (!(tmin >= -(double)kPad) || !(tmax < (double)(n + kPad - 1))) {
+                const int64_t ta = e.tc + (int64_t)(a_lo - c0) * e.m * 2;
+                const int64_t tb = e.tc + (int64_t)(a_hi - c0) * e.m * 2;
+                const int64_t tmin = ta < tb ? ta : tb, tmax = ta < tb ? tb : ta;
+                if (tmin < 0 || (tmax >> kFrac) > (int64_t)(n + 2 * kPad - 2)) {
                     char buf[160];
                     snprintf(buf, sizeof buf, "ray (%d, %d): intercept out of the padded range", v, k);
                     return buf;

@@ -10,21 +10,29 @@
 
 namespace air {
 
-// One Joseph ray, as the GPU kernels read it (32 bytes, two 16-byte loads).
-//   t(a) = fma((double)(a - c0), m, tc)   intercept at driving index a (pixel units, float64)
-//   s    = pixel |d| / |d_drive|           path length per driving step
+// One Joseph ray, as the GPU kernels read it (16 bytes, one load).
+//   T(a) = tc + (a - c0) * 2m   intercept at driving index a in fixed point with
+//                               kFrac = 32 fractional bits (m has 31), shifted
+//                               by kPad, so that the high word of T is the
+//                               sample's index in a padded line
 //   meta = lo | (hi + 1) << 15 | axis << 30
-// The intercept is float64 because the ramp-filtered sinogram is high-pass:
-// a float32 intercept (error ~3e-5 pixel at n = 512) alone moves A^T C y by
-// ~1e-5 relative.  The interpolation weights themselves are float32.
+// The path length per driving step, s = pixel |d| / |d_drive|, is kept in a
+// separate per-ray array: A = S J with J the bare interpolation weights, and
+// the normal operator A^T C A = J^T (S C S) J applies S inside the ramp stage.
+// Integer arithmetic makes the intercept exact and associative: the forward
+// projector advances it by 2m per step and the backprojector evaluates it
+// directly, and both get the same bits.  Resolution 2^-32 pixel (the slope's
+// rounding adds at most n/2 * 2^-32); a float32 intercept (error ~3e-5 pixel
+// at n = 512) alone would move A^T C y by ~1e-5 relative, since the
+// ramp-filtered sinogram is high-pass.  The interpolation weights are float32.
+constexpr int kFrac = 32;      // fractional bits of tc and T
+constexpr int kSlopeFrac = 31; // fractional bits of m (|m| <= 1 fits int32)
 struct RayEntry {
-    double tc;
-    double m;
-    float s;
+    int64_t tc;
+    int32_t m;
     int32_t meta;
-    int32_t unused[2];
 };
-static_assert(sizeof(RayEntry) == 32, "RayEntry must be 32 bytes");
+static_assert(sizeof(RayEntry) == 16, "RayEntry must be 16 bytes");
 
 inline int meta_lo(int32_t meta) { return meta & 0x7FFF; }
 inline int meta_hi(int32_t meta) { return ((meta >> 15) & 0x7FFF) - 1; }
@@ -44,8 +52,9 @@ struct GeomHost {
 
 // Builds the per-ray tables (float64 on the host, no FMA contraction).
 // Returns an empty string on success, else an error message.
-std::string build_ray_tables(const GeomHost& g, std::vector<RayEntry>& rays, std::vector<int8_t>& axis,
-                             std::vector<int32_t>& lo, std::vector<int32_t>& hi);
+// step[v * n_bins + k] receives s of each ray.
+std::string build_ray_tables(const GeomHost& g, std::vector<RayEntry>& rays, std::vector<float>& step,
+                             std::vector<int8_t>& axis, std::vector<int32_t>& lo, std::vector<int32_t>& hi);
 
 // Ram-Lak taps r(0..n_bins-1), float64.
 void ramp_taps64(int n_bins, std::vector<double>& r);

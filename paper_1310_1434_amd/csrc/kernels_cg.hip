@@ -2,15 +2,16 @@
 //
 // All image kernels work on 16 x 16 pixel tiles (256 threads), one batch item
 // per grid z.  Vectors are float32; inner products, alpha, beta and the
-// Bregman residual norm are float64 and are reduced with a fixed-order tree
-// (block_reduce_last), so every batch item gets the same bits whatever the
-// batch size.  Scalars never leave the device.
+// Bregman residual norm are float64.  Each block writes one partial sum;
+// k_finalize adds them in index order (one block per batch item) and derives
+// alpha or beta, so every batch item gets the same bits whatever the batch
+// size, and no atomics are used.  Scalars never leave the device.
 #include "common.cuh"
 
 namespace air {
 
 // ---------------------------------------------------------------------------- CG
-// x += alpha p, r -= alpha q, rho' = r . r  with alpha = rho / (p . q) (0 if rho or p.q is 0).
+// x += alpha p, r -= alpha q; partial sums of r . r.
 // When a.pad.base is set, x is also written to its padded line sets.
 __global__ __launch_bounds__(256) void k_cg_xr(CgArgs a) {
     __shared__ float tile[16][17];
@@ -18,8 +19,7 @@ __global__ __launch_bounds__(256) void k_cg_xr(CgArgs a) {
     const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16, b = blockIdx.z;
     const int n = a.n, i = i0 + tx, j = j0 + ty;
     const bool valid = i < n && j < n;
-    const double rho = a.rho_cur[b], pq = a.pq[b];
-    const double alpha = (rho == 0.0 || pq == 0.0) ? 0.0 : rho / pq;
+    const double alpha = a.alpha[b];
     const size_t idx = (size_t)b * n * n + (size_t)j * n + i;
     double part = 0.0;
     float xn = 0.f;
@@ -35,18 +35,17 @@ __global__ __launch_bounds__(256) void k_cg_xr(CgArgs a) {
         store_padded_tile(a.pad.base + (size_t)b * 2 * n * line, n, line, i0, j0, tx, ty, xn, tile);
     }
     const int nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
-    block_reduce_last<256>(part, a.red_partial + (size_t)b * nblk, a.red_count + b, a.red_out + b, nblk, blk);
+    block_partial<256>(part, a.partial + (size_t)b * nblk + blk);
 }
 
-// p = r + beta p, beta = rho' / rho (0 if rho is 0); p also goes to its padded line sets.
+// p = r + beta p; p also goes to its padded line sets.
 __global__ __launch_bounds__(256) void k_cg_p(CgArgs a) {
     __shared__ float tile[16][17];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16, b = blockIdx.z;
     const int n = a.n, i = i0 + tx, j = j0 + ty;
     const bool valid = i < n && j < n;
-    const double rho = a.rho_cur[b], rho_new = a.rho_new_in[b];
-    const double beta = rho == 0.0 ? 0.0 : rho_new / rho;
+    const double beta = a.beta[b];
     const size_t idx = (size_t)b * n * n + (size_t)j * n + i;
     float pn = 0.f;
     if (valid) {
@@ -66,6 +65,47 @@ hipError_t launch_cg_update_xr(const CgArgs& a, int batch, hipStream_t s) {
 hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s) {
     dim3 grid((a.n + 15) / 16, (a.n + 15) / 16, batch);
     hipLaunchKernelGGL(k_cg_p, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// One block per batch item: sum the block partials in index order (each
+// thread a fixed stride, then a fixed tree) and derive the CG scalar.
+__global__ __launch_bounds__(256) void k_finalize(int mode, const double* __restrict__ partial, int nblk,
+                                                  double* __restrict__ rho, double* __restrict__ coef,
+                                                  double* __restrict__ out, int stride) {
+    __shared__ double sh[4];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const double* pb = partial + (size_t)b * nblk;
+    double s = 0.0;
+    for (int i = tid; i < nblk; i += 256) s += pb[i];
+    s = wave_sum(s);
+    if (tid % kWave == 0) sh[tid / kWave] = s;
+    __syncthreads();
+    if (tid != 0) return;
+    const double sum = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    switch (mode) {
+    case FIN_RHO:
+        rho[b] = sum;
+        break;
+    case FIN_ALPHA: {
+        const double r = rho[b];
+        coef[b] = (r == 0.0 || sum == 0.0) ? 0.0 : r / sum;
+        break;
+    }
+    case FIN_BETA: {
+        const double r = rho[b];
+        coef[b] = r == 0.0 ? 0.0 : sum / r;
+        rho[b] = sum;
+        break;
+    }
+    default:
+        out[(size_t)b * stride] = sqrt(sum);
+    }
+}
+
+hipError_t launch_finalize(int mode, const double* partial, int nblk, int batch, double* rho, double* coef,
+                           double* out, int stride, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(256), 0, s, mode, partial, nblk, rho, coef, out, stride);
     return hipGetLastError();
 }
 
@@ -175,13 +215,7 @@ __global__ __launch_bounds__(256) void k_tf_shrink(TfArgs a) {
         }
     }
     const int nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
-    block_reduce_last<256>(part, a.red_partial + (size_t)b * nblk, a.red_count + b, a.red_out + b, nblk, blk);
-}
-
-// resid[b * stride] = sqrt(red[b])
-__global__ void k_store_sqrt(const double* __restrict__ red, double* __restrict__ resid, int stride, int batch) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < batch) resid[(size_t)b * stride] = sqrt(red[b]);
+    block_partial<256>(part, a.partial + (size_t)b * nblk + blk);
 }
 
 hipError_t launch_framelet_fwd(int n, const float* x, float* z, int batch, hipStream_t s) {
@@ -205,10 +239,6 @@ hipError_t launch_tf_rhs(int n, const float* g, const float* e, float mu, float*
 hipError_t launch_tf_shrink(const TfArgs& a, int batch, hipStream_t s) {
     dim3 grid((a.n + 15) / 16, (a.n + 15) / 16, batch);
     hipLaunchKernelGGL(k_tf_shrink, grid, dim3(256), 0, s, a);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess || !a.resid) return err;
-    hipLaunchKernelGGL(k_store_sqrt, dim3((batch + 63) / 64), dim3(64), 0, s, a.red_out, a.resid, a.resid_stride,
-                       batch);
     return hipGetLastError();
 }
 
@@ -217,22 +247,10 @@ __global__ void k_fill(float* __restrict__ p, size_t count, float v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
-__global__ void k_fill_u32(unsigned* __restrict__ p, size_t count, unsigned v) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-
 hipError_t launch_fill(float* p, size_t count, float v, hipStream_t s) {
     if (count == 0) return hipSuccess;
     const size_t blocks = (count + 255) / 256 < 4096 ? (count + 255) / 256 : 4096;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, p, count, v);
-    return hipGetLastError();
-}
-
-hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t s) {
-    if (count == 0) return hipSuccess;
-    const size_t blocks = (count + 255) / 256 < 4096 ? (count + 255) / 256 : 4096;
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, count, v);
     return hipGetLastError();
 }
 

@@ -50,10 +50,9 @@ hipError_t launch_pad(const KGeom& g, const float* x, PadBuf pad, int batch, hip
 }
 
 // ---------------------------------------------------------------------------- forward A
-// One thread per ray and up to BT images of the batch (the intercepts, weights
-// and addresses are shared; only the samples and sums are per image).
-//   y[b][v][k] = s * sum_{a=lo..hi} (1-f) L_a[j0] + f L_a[j0+1],
-//   t = fma(a - c0, m, tc) (float64), j0 = floor(t), f = (float)(t - j0),
+// One thread per ray.
+//   y[b][v][k] = s * sum_{a=lo..hi} (1-f) L_a[j] + f L_a[j+1],
+//   T = tc + (a - c0) m (fixed point), j = T >> kFrac, f = frac(T) as float32,
 // L_a the padded line a of image b.  Bins k in [n_bins, ds) are written as zero.
 // The driving index runs over the union of the wavefront's ranges, so at every
 // step all lanes of one axis read the same image line (coalesced gathers);
@@ -71,17 +70,25 @@ __device__ __forceinline__ int wave_max_i(int v) {
     return v;
 }
 
-template <int BT>
+// Sample index (high word) and fraction (low word) of a fixed-point intercept.
+static_assert(kFrac == 32 && kSlopeFrac == 31, "fixed-point layout");
+__device__ __forceinline__ int fx_index(int64_t t) { return (int)(t >> 32); }
+__device__ __forceinline__ float fx_frac(int64_t t) { return (float)(uint32_t)t * 0x1p-32f; }
+// intercept at driving index a: tc + (a - c0) * 2m
+__device__ __forceinline__ int64_t fx_at(const RayEntry& e, int a_minus_c0) {
+    return e.tc + ((int64_t)a_minus_c0 * (int64_t)e.m) * 2;
+}
+
+template <bool SCALED>
 __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __restrict__ pad,
                                                          float* __restrict__ y, int chunks, int batch) {
     const int v = blockIdx.x / chunks;
     const int k = (blockIdx.x - v * chunks) * kProjBlock + threadIdx.x;
-    const int b0 = blockIdx.y * BT;
+    const int b = blockIdx.y;
     const bool ray = k < g.n_bins;
     RayEntry e;
-    e.tc = 0.0;
-    e.m = 0.0;
-    e.s = 0.f;
+    e.tc = 0;
+    e.m = 0;
     e.meta = 0;
     if (ray) e = g.rays[(size_t)v * g.n_bins + k];
     const bool hits = ray && ray_hi(e.meta) >= ray_lo(e.meta);
@@ -91,35 +98,55 @@ __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __
     const int a_lo = __builtin_amdgcn_readfirstlane(wave_min_i(lo));
     const int a_hi = __builtin_amdgcn_readfirstlane(wave_max_i(hi));
     const int line = g.line;
-    const float* lines[BT];
-#pragma unroll
-    for (int q = 0; q < BT; q++)
-        lines[q] = pad + ((size_t)min(b0 + q, batch - 1) * 2 + axis) * g.n * line + kPad;
-    float acc[BT];
-#pragma unroll
-    for (int q = 0; q < BT; q++) acc[q] = 0.f;
-    double da = (double)(a_lo - g.c0);
-#pragma unroll 2
-    for (int a = a_lo; a <= a_hi; a++, da += 1.0) {
-        if (a >= lo && a <= hi) {
-            const double t = fma(da, e.m, e.tc);
-            const double fl = floor(t);
-            const float f = (float)(t - fl);
-            const float f1 = 1.f - f;
-            const size_t off = (size_t)a * line + (int)fl;
-#pragma unroll
-            for (int q = 0; q < BT; q++) {
-                acc[q] = fmaf(f1, lines[q][off], acc[q]);
-                acc[q] = fmaf(f, lines[q][off + 1], acc[q]);
-            }
-        }
+    const float* lines = pad + ((size_t)b * 2 + axis) * g.n * line;
+    float acc = 0.f;
+    int64_t t = fx_at(e, a_lo - g.c0);
+    const int64_t m = (int64_t)e.m * 2;
+    uint32_t row = (uint32_t)(a_lo * line);
+    // Branch-free steps (a lane outside its range reads element 0 of its image
+    // with zero weights), so that several gathers are in flight per wave.
+#pragma unroll 4
+    for (int a = a_lo; a <= a_hi; a++, t += m, row += line) {
+        const bool act = a >= lo && a <= hi;
+        const float f = fx_frac(t);
+        const float w1 = act ? f : 0.f;
+        const float w0 = act ? 1.f - f : 0.f;
+        const float* p = lines + (act ? row + (uint32_t)fx_index(t) : 0u);
+        acc = fmaf(w0, p[0], acc);
+        acc = fmaf(w1, p[1], acc);
     }
     if (k >= g.ds) return;
-#pragma unroll
-    for (int q = 0; q < BT; q++)
-        if (b0 + q < batch) y[((size_t)(b0 + q) * g.n_views + v) * g.ds + k] = ray ? acc[q] * e.s : 0.f;
+    float out = 0.f;
+    if (ray) out = SCALED ? acc * g.step[(size_t)v * g.ds + k] : acc;
+    y[((size_t)b * g.n_views + v) * g.ds + k] = out;
 }
 
+hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, bool scaled, hipStream_t s) {
+    const int chunks = (g.ds + kProjBlock - 1) / kProjBlock;
+    dim3 grid(g.n_views * chunks, batch);
+    if (scaled) hipLaunchKernelGGL(k_project<true>, grid, dim3(kProjBlock), 0, s, g, pad.base, y, chunks, batch);
+    else hipLaunchKernelGGL(k_project<false>, grid, dim3(kProjBlock), 0, s, g, pad.base, y, chunks, batch);
+    return hipGetLastError();
+}
+
+// out = y * step^power over internal rows (power 1: S y, power 2: S^2 y).
+__global__ __launch_bounds__(256) void k_scale(KGeom g, const float* __restrict__ y, float* __restrict__ out,
+                                               size_t count, int power) {
+    const size_t per_batch = (size_t)g.n_views * g.ds;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) {
+        const float sv = g.step[i % per_batch];          // [v][k] of this element
+        out[i] = power == 2 ? y[i] * sv * sv : y[i] * sv;
+    }
+}
+
+hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, int power, hipStream_t s) {
+    const size_t count = (size_t)batch * g.n_views * g.ds;
+    const size_t blocks = (count + 255) / 256 < 8192 ? (count + 255) / 256 : 8192;
+    hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, s, g, y, out, count, power);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- adjoint J^T
 // Images per backprojector thread.  The detector window and the table reads
 // (about two thirds of the per-candidate work) are shared by the tile, so a
 // group of BT images costs roughly (2 + BT) units: pick the tile that
@@ -136,23 +163,27 @@ static int batch_tile(int batch) {
     return best;
 }
 
-hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, hipStream_t s) {
-    const int chunks = (g.ds + kProjBlock - 1) / kProjBlock;
-    const int bt = 1;   // one image per thread: more waves in flight beat sharing the intercepts
-    dim3 grid(g.n_views * chunks, (batch + bt - 1) / bt);
-    hipLaunchKernelGGL(k_project<1>, grid, dim3(kProjBlock), 0, s, g, pad.base, y, chunks, batch);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------- adjoint A^T
 // One thread per pixel and up to BT images, 16x16 pixels per block.  For every
 // view the pixel finds the bins whose rays can give it a non-zero Joseph
 // weight: the detector interval covered by the diamond |dx| + |dy| <= pixel
 // around its centre (any sample that touches the pixel lies inside it),
 // widened by 0.01 bin.  For each candidate it re-evaluates the forward
-// projector's own intercept and float32 weight, so the result is the exact
-// transpose of k_project up to summation order.  Per view the (few) terms are
+// projector's own fixed-point intercept and float32 weight, so the result is
+// the exact transpose of k_project (unscaled) up to summation order.
+// Candidates are taken two at a time with predication, so that their table
+// and sinogram loads are in flight together.  Per view the (few) terms are
 // summed in float32, across views in float64.  No atomics.
+__device__ __forceinline__ float joseph_weight(const RayEntry& e, int i, int j, int c0) {
+    const int ax = ray_axis(e.meta);
+    const int da = ax ? j : i;      // driving index of this pixel for the ray
+    const int ob = ax ? i : j;      // interpolated index
+    const int64_t t = fx_at(e, da - c0);
+    const float f = fx_frac(t);
+    const int j0 = fx_index(t) - kPad;
+    const float w = (ob == j0) ? (1.f - f) : ((ob == j0 + 1) ? f : 0.f);
+    return (da >= ray_lo(e.meta) && da <= ray_hi(e.meta)) ? w : 0.f;
+}
+
 template <int MODE, bool REDUCE, int BT>
 __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __restrict__ y, BpArgs a, int batch) {
     __shared__ float tile[16][17];
@@ -200,20 +231,20 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
             float part[BT];
 #pragma unroll
             for (int q = 0; q < BT; q++) part[q] = 0.f;
-            for (int k = klo; k <= khi; k++) {
-                const RayEntry e = rv[k];
-                const int ax = ray_axis(e.meta);
-                const int da = ax ? j : i;      // driving index of this pixel for the ray
-                const int ob = ax ? i : j;      // interpolated index
-                if (da < ray_lo(e.meta) || da > ray_hi(e.meta)) continue;
-                const double t = fma((double)(da - g.c0), e.m, e.tc);
-                const double fl = floor(t);
-                const float f = (float)(t - fl);
-                const int j0r = (int)fl;
-                const float w = (ob == j0r) ? (1.f - f) : ((ob == j0r + 1) ? f : 0.f);
-                const float ws = w * e.s;
+            for (int k = klo; k <= khi; k += 2) {
+                const bool two = k + 1 <= khi;
+                const int k1 = two ? k + 1 : k;
+                const RayEntry e0 = rv[k], e1 = rv[k1];
+                float yv0[BT], yv1[BT];
 #pragma unroll
-                for (int q = 0; q < BT; q++) part[q] = fmaf(ws, yb[q][voff + k], part[q]);
+                for (int q = 0; q < BT; q++) {
+                    yv0[q] = yb[q][voff + k];
+                    yv1[q] = yb[q][voff + k1];
+                }
+                const float w0 = joseph_weight(e0, i, j, g.c0);
+                const float w1 = two ? joseph_weight(e1, i, j, g.c0) : 0.f;
+#pragma unroll
+                for (int q = 0; q < BT; q++) part[q] = fmaf(w1, yv1[q], fmaf(w0, yv0[q], part[q]));
             }
 #pragma unroll
             for (int q = 0; q < BT; q++) tot[q] += (double)part[q];
@@ -248,8 +279,7 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
             store_padded_tile(a.pad_out.base + (size_t)b * 2 * n * g.line, n, g.line, i0, j0, tx, ty, r, tile);
             __syncthreads();   // the tile is reused by the next batch item
         }
-        if (REDUCE)
-            block_reduce_last<256>(part, a.red_partial + (size_t)b * nblk, a.red_count + b, a.red_out + b, nblk, blk);
+        if (REDUCE) block_partial<256>(part, a.partial + (size_t)b * nblk + blk);
     }
 }
 
@@ -264,7 +294,7 @@ static void launch_bp_mode(const KGeom& g, const float* y, const BpArgs& a, int 
 }
 
 hipError_t launch_backproject(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s) {
-    const bool red = a.red_partial != nullptr;
+    const bool red = a.partial != nullptr;
     switch (a.mode) {
     case BP_PLAIN:
         launch_bp_mode<BP_PLAIN, false>(g, y, a, batch, s);
@@ -286,16 +316,20 @@ hipError_t launch_backproject(const KGeom& g, const float* y, const BpArgs& a, i
 __global__ __launch_bounds__(256) void k_repack(const float* __restrict__ src, int src_stride,
                                                 float* __restrict__ dst, int dst_stride, int rows, int cols,
                                                 int dst_cols) {
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    const int r = blockIdx.y;
-    if (r >= rows || c >= dst_cols) return;
-    dst[(size_t)r * dst_stride + c] = c < cols ? src[(size_t)r * src_stride + c] : 0.f;
+    const size_t count = (size_t)rows * dst_cols;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) {
+        const size_t r = i / dst_cols;
+        const int c = (int)(i - r * dst_cols);
+        dst[r * dst_stride + c] = c < cols ? src[r * src_stride + c] : 0.f;
+    }
 }
 
 hipError_t launch_repack(const float* src, int src_stride, float* dst, int dst_stride, int rows, int cols,
                          int dst_cols, hipStream_t s) {
-    dim3 grid((dst_cols + 255) / 256, rows);
-    hipLaunchKernelGGL(k_repack, grid, dim3(256), 0, s, src, src_stride, dst, dst_stride, rows, cols, dst_cols);
+    const size_t count = (size_t)rows * dst_cols;
+    const size_t blocks = (count + 255) / 256 < 8192 ? (count + 255) / 256 : 8192;
+    hipLaunchKernelGGL(k_repack, dim3((unsigned)blocks), dim3(256), 0, s, src, src_stride, dst, dst_stride, rows,
+                       cols, dst_cols);
     return hipGetLastError();
 }
 

@@ -22,8 +22,10 @@ typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 b8_t __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------------------- float32
+template <int SCALE>
 __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, float* __restrict__ yf,
-                                                  const float* __restrict__ taps, int rows, int ds) {
+                                                  const float* __restrict__ taps, const float* __restrict__ step,
+                                                  int n_views, int rows, int ds) {
     extern __shared__ float T[];   // [2 ds]: T[d + ds] = kappa r(|d|)
     for (int i = threadIdx.x; i < 2 * ds; i += 256) T[i] = taps[i];
     __syncthreads();
@@ -32,11 +34,20 @@ __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, f
     const int slot = lane >> 4;                              // k slot 0..3
     const int n0 = blockIdx.y * 32;
     const int ncol = n0 + (lane & 15);
-    const float* arow = y + (size_t)min(m, rows - 1) * ds;
+    const int mc = min(m, rows - 1);
+    const float* arow = y + (size_t)mc * ds;
+    const float* srow = step + (size_t)(mc % n_views) * ds;
     const bool mvalid = m < rows;
     f4_t acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < ds; k0 += 16) {
         float4 av = *reinterpret_cast<const float4*>(arow + k0 + 4 * slot);
+        if (SCALE & RAMP_PRE) {
+            const float4 sv = *reinterpret_cast<const float4*>(srow + k0 + 4 * slot);
+            av.x *= sv.x;
+            av.y *= sv.y;
+            av.z *= sv.z;
+            av.w *= sv.w;
+        }
         if (!mvalid) av = make_float4(0.f, 0.f, 0.f, 0.f);
         // MFMA #q uses actual k = k0 + 4 slot + q in this lane's slot
         const int d = k0 + 4 * slot - ncol + ds;
@@ -55,8 +66,14 @@ __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, f
     for (int r = 0; r < 4; r++) {
         const int row = rbase + r;
         if (row < rows) {
-            yf[(size_t)row * ds + ncol] = acc0[r];
-            yf[(size_t)row * ds + ncol + 16] = acc1[r];
+            float o0 = acc0[r], o1 = acc1[r];
+            if (SCALE & RAMP_POST) {
+                const float* so = step + (size_t)(row % n_views) * ds;
+                o0 *= so[ncol];
+                o1 *= so[ncol + 16];
+            }
+            yf[(size_t)row * ds + ncol] = o0;
+            yf[(size_t)row * ds + ncol + 16] = o1;
         }
     }
 }
@@ -64,19 +81,27 @@ __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, f
 // ---------------------------------------------------------------------------- 16-bit splits
 // Fragment f of a split term holds, for lane l, the 8 values T16(delta + 8 (l/16) + i - l%16),
 // i = 0..7, with delta = dmin + 16 f (delta = k0 - n0 of the tile).
-template <int PREC>
+template <int PREC, int SCALE>
 __global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y, float* __restrict__ yf,
                                                     RampTables t, int rows, int ds) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = blockIdx.x * 64 + w * 16 + (lane & 15);
     const int slot = lane >> 4;                 // k slots 8 slot .. 8 slot + 7
     const int n0 = blockIdx.y * 32;
-    const float* arow = y + (size_t)min(m, rows - 1) * ds;
+    const int mc = min(m, rows - 1);
+    const float* arow = y + (size_t)mc * ds;
+    const float* srow = t.step + (size_t)(mc % t.n_views) * ds;
     const bool mvalid = m < rows;
     f4_t accA0 = {0.f, 0.f, 0.f, 0.f}, accA1 = accA0, accB0 = accA0, accB1 = accA0;
     for (int k0 = 0; k0 < ds; k0 += 32) {
         float4 a0 = *reinterpret_cast<const float4*>(arow + k0 + 8 * slot);
         float4 a1 = *reinterpret_cast<const float4*>(arow + k0 + 8 * slot + 4);
+        if (SCALE & RAMP_PRE) {
+            const float4 s0 = *reinterpret_cast<const float4*>(srow + k0 + 8 * slot);
+            const float4 s1 = *reinterpret_cast<const float4*>(srow + k0 + 8 * slot + 4);
+            a0.x *= s0.x; a0.y *= s0.y; a0.z *= s0.z; a0.w *= s0.w;
+            a1.x *= s1.x; a1.y *= s1.y; a1.z *= s1.z; a1.w *= s1.w;
+        }
         if (!mvalid) {
             a0 = make_float4(0.f, 0.f, 0.f, 0.f);
             a1 = a0;
@@ -139,25 +164,44 @@ __global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y,
     for (int r = 0; r < 4; r++) {
         const int row = rbase + r;
         if (row < rows) {
-            yf[(size_t)row * ds + ncol] = t.out_scale * fmaf(accB0[r], cross, accA0[r]);
-            yf[(size_t)row * ds + ncol + 16] = t.out_scale * fmaf(accB1[r], cross, accA1[r]);
+            float o0 = t.out_scale * fmaf(accB0[r], cross, accA0[r]);
+            float o1 = t.out_scale * fmaf(accB1[r], cross, accA1[r]);
+            if (SCALE & RAMP_POST) {
+                const float* so = t.step + (size_t)(row % t.n_views) * ds;
+                o0 *= so[ncol];
+                o1 *= so[ncol + 16];
+            }
+            yf[(size_t)row * ds + ncol] = o0;
+            yf[(size_t)row * ds + ncol + 16] = o1;
         }
     }
 }
 
-hipError_t launch_ramp(int prec, const RampTables& t, const float* y, float* yf, int rows, int ds,
-                       hipStream_t s) {
+template <int SCALE>
+static hipError_t launch_ramp_scaled(int prec, const RampTables& t, const float* y, float* yf, int rows, int ds,
+                                     hipStream_t s) {
     dim3 grid((rows + 63) / 64, ds / 32), block(256);
     if (prec == AIR_FP32) {
-        hipLaunchKernelGGL(k_ramp_f32, grid, block, 2 * ds * sizeof(float), s, y, yf, t.taps32, rows, ds);
+        hipLaunchKernelGGL(k_ramp_f32<SCALE>, grid, block, 2 * ds * sizeof(float), s, y, yf, t.taps32, t.step,
+                           t.n_views, rows, ds);
     } else if (prec == AIR_MIXED_F16) {
-        hipLaunchKernelGGL(k_ramp_split<AIR_MIXED_F16>, grid, block, 0, s, y, yf, t, rows, ds);
+        hipLaunchKernelGGL((k_ramp_split<AIR_MIXED_F16, SCALE>), grid, block, 0, s, y, yf, t, rows, ds);
     } else if (prec == AIR_MIXED_BF16) {
-        hipLaunchKernelGGL(k_ramp_split<AIR_MIXED_BF16>, grid, block, 0, s, y, yf, t, rows, ds);
+        hipLaunchKernelGGL((k_ramp_split<AIR_MIXED_BF16, SCALE>), grid, block, 0, s, y, yf, t, rows, ds);
     } else {
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_ramp(int prec, const RampTables& t, const float* y, float* yf, int rows, int ds, int scale,
+                       hipStream_t s) {
+    switch (scale) {
+    case 0: return launch_ramp_scaled<0>(prec, t, y, yf, rows, ds, s);
+    case RAMP_POST: return launch_ramp_scaled<RAMP_POST>(prec, t, y, yf, rows, ds, s);
+    case RAMP_PRE | RAMP_POST: return launch_ramp_scaled<RAMP_PRE | RAMP_POST>(prec, t, y, yf, rows, ds, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace air
