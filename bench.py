@@ -28,6 +28,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "mixed_f16": 2500.0, "mixed_bf16": 2500.0}
+# VALU issue peak: 256 CUs x 4 SIMD x 16 lanes per clock x 2.4 GHz (non-packed lane operations)
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# essential VALU lane operations of one Joseph sample (ray-step): advance the
+# fixed-point intercept, convert its fraction, form the two weights, form the
+# sample address, two fused multiply-adds
+VALU_OPS_PER_SAMPLE = 7
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
 
 
@@ -36,7 +42,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2_25", "c5"])
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -46,6 +52,8 @@ def parse():
                     help="profiler runs only: Bregman iterations of the instrumented pass (0 = the workload's)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="profiler runs only: also run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into profiles/traffic_c2.json")
     return ap.parse_args()
 
 
@@ -95,8 +103,49 @@ def cpu_baseline(w, y0):
                       f"{w.geom.n}^2 x {w.geom.n_views}-view case in {dt:.2f} s, scaled x{w.n_outer // k}"}
 
 
+def summarize_pmc(fetch_dir: str, write_dir: str, batch: int):
+    """Per-dispatch HBM bytes of each kernel from FETCH_SIZE / WRITE_SIZE (KiB),
+    each scaled so that the calibration copy of 256 MiB reads/writes 256 MiB."""
+    import csv
+    import glob
+
+    def per_kernel(d):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        vals = {}
+        for f in files:
+            for r in csv.DictReader(open(f)):
+                name = r["Kernel_Name"]
+                vals.setdefault(name, []).append(float(r["Counter_Value"]))
+        return vals
+
+    fetch, write = per_kernel(fetch_dir), per_kernel(write_dir)
+    copy_bytes = 256 * 1024 * 1024
+    cf = max(fetch.get("__amd_rocclr_copyBuffer", [0.0]))
+    cw = max(write.get("__amd_rocclr_copyBuffer", [0.0]))
+    sf = copy_bytes / (cf * 1024.0) if cf else None
+    sw = copy_bytes / (cw * 1024.0) if cw else None
+    names = {"k_project": "air::k_project<false>", "k_backproject": "air::k_backproject<1, true",
+             "k_ramp_f32": "air::k_ramp_f32<3>"}
+    out = {"batch": batch, "source_hash": kernel_source_hash(), "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_scale": sf, "write_scale": sw, "kernels": {}}
+    for short, prefix in names.items():
+        fk = [v for k, vs in fetch.items() if k.startswith(prefix) or prefix in k for v in vs]
+        wk = [v for k, vs in write.items() if k.startswith(prefix) or prefix in k for v in vs]
+        if fk and wk and sf and sw:
+            fb = sum(fk) / len(fk) * 1024.0 * sf
+            wb = sum(wk) / len(wk) * 1024.0 * sw
+            out["kernels"][short] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
+                                     "dispatches": len(fk)}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    json.dump(out, open(TRAFFIC_FILE, "w"), indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def main():
     a = parse()
+    if a.summarize_pmc:
+        summarize_pmc(a.summarize_pmc[0], a.summarize_pmc[1], a.batch)
+        return
     if a.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {a.gpus} is not supported "
               "(independent reconstructions shard across GPUs with no communication)", file=sys.stderr)
@@ -151,8 +200,10 @@ def main():
     out["proj_grays_s"] = rays / t_proj / 1e9 if t_proj else None
     out["backproj_grays_s"] = rays / t_bp / 1e9 if t_bp else None
 
-    # roofline of the dominant kernel; projector bytes = the traffic of the explicit
-    # sparse matrix A (one 4-byte image sample per nonzero, 2 per ray-step) + the sinogram
+    # Roofline of the dominant kernel.  The projectors' HBM traffic is small
+    # (the images live in L2/MALL), so they are placed on the VALU issue
+    # roofline: algorithmic work = VALU_OPS_PER_SAMPLE lane operations per
+    # Joseph sample, ray-steps per image from the index tables.
     dom = max(("project", "backproject", "ramp"), key=lambda k: kernel_ms[k]["total_ms"])
     t_dom = kernel_ms[dom]["avg_ms"] * 1e-3
     if dom == "ramp":
@@ -161,23 +212,23 @@ def main():
         roof = {"kernel": "k_ramp_f32", "bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK_TFLOPS["fp32"],
                 "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK_TFLOPS["fp32"]}
     else:
-        if dom == "project":
-            bytes_alg = B * (8.0 * rsteps + 4.0 * g.n_views * g.n_bins)
-            kname = "k_project"
-        else:
-            bytes_alg = B * (8.0 * rsteps + 4.0 * g.n * g.n)
-            kname = "k_backproject"
-        achieved = bytes_alg / t_dom / 1e9
-        roof = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": bytes_alg, "avg_launch_ms": t_dom * 1e3,
+        ops = VALU_OPS_PER_SAMPLE * B * float(rsteps)
+        achieved = ops / t_dom / 1e12
+        roof = {"kernel": "k_project" if dom == "project" else "k_backproject", "bound": "alu",
+                "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (VALU lane ops)",
+                "frac": achieved / VALU_PEAK_TOPS, "ops_per_launch": ops, "avg_launch_ms": t_dom * 1e3,
                 "ray_steps_per_image": rsteps}
     roof["traffic"] = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
-        ent = tr.get(roof["kernel"])
-        if ent and ent.get("source_hash") == kernel_source_hash() and ent.get("batch") == B:
+        ent = tr.get("kernels", {}).get(roof["kernel"])
+        if ent and tr.get("source_hash") == kernel_source_hash() and tr.get("batch") == B:
             roof["traffic"] = ent["bytes_per_launch"]
     out["roofline"] = roof
+    # the same kernels measured as an explicit sparse matrix would be (4 bytes per nonzero)
+    out["sparse_equivalent_gbs"] = {
+        "project": B * (8.0 * rsteps + 4.0 * g.n_views * g.n_bins) / t_proj / 1e9 if t_proj else None,
+        "backproject": B * (8.0 * rsteps + 4.0 * g.n * g.n) / t_bp / 1e9 if t_bp else None}
     out["kernel_source_hash"] = kernel_source_hash()
 
     if a.calibrate_copy:

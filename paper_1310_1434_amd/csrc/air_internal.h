@@ -43,11 +43,16 @@ struct PadBuf {
 hipError_t launch_pad(const KGeom& g, const float* x, PadBuf pad, int batch, hipStream_t s);
 // y = J x (scaled = false: bare interpolation weights) or y = A x = S J x (scaled = true).
 hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, bool scaled, hipStream_t s);
-// y <- y * step^power, elementwise over internal rows [batch * n_views][ds] (power 1 or 2).
-hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, int power, hipStream_t s);
+// Backprojector input layout: batch-interleaved rows [n_views][ds][bs] with
+// bs = bp_batch_stride(batch) >= batch, so that the images a backprojector
+// thread serves are contiguous.
+int bp_batch_stride(int batch);
+// out (interleaved, stride bs) = y (rows [batch * n_views][ds]) * step^power (power 1 or 2).
+hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, int power, int bs, hipStream_t s);
 
 // Backprojection epilogue modes (per pixel, acc = (J^T y)_pixel, J the bare
-// interpolation weights; callers fold the path lengths into y):
+// interpolation weights; callers fold the path lengths into y, which is in the
+// batch-interleaved layout of stride bp_batch_stride(batch)):
 enum BpMode {
     BP_PLAIN = 0,     // out = acc
     BP_MATVEC = 1,    // out = acc + mu * p;  partial sums of p . out (float64)
@@ -81,10 +86,12 @@ struct RampTables {
     int dmin;
     float out_scale;           // kappa * 2^-12 for the 16-bit modes
 };
-// scale: 0 = C y;  RAMP_POST = S C y;  RAMP_PRE | RAMP_POST = S C S y  (S = diag(step))
+// scale: 0 = C y;  RAMP_POST = S C y;  RAMP_PRE | RAMP_POST = S C S y  (S = diag(step)).
+// Input rows [batch * n_views][ds].  Output: the same layout when bs == 0, else
+// batch-interleaved [n_views][ds][bs] (the backprojector's input).
 enum { RAMP_PRE = 1, RAMP_POST = 2 };
 hipError_t launch_ramp(int prec, const RampTables& t, const float* y, float* yf, int rows, int ds, int scale,
-                       hipStream_t s);
+                       int bs, hipStream_t s);
 
 // CG vector updates on 16x16 tiles (float32 vectors, float64 scalars).
 struct CgArgs {

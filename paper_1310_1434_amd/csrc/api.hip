@@ -341,7 +341,7 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
         const size_t mb = (size_t)max_batch;
         p->off_pad = c.take(mb * 2 * g.n * p->line * sizeof(float));
         p->off_s1 = c.take(mb * g.n_views * ds * sizeof(float));
-        p->off_s2 = c.take(mb * g.n_views * ds * sizeof(float));
+        p->off_s2 = c.take((mb + 7) / 8 * 8 * g.n_views * ds * sizeof(float));   // interleaved, stride <= roundup(batch, 8)
         p->total = c.off;
     } catch (const std::bad_alloc&) {
         delete p;
@@ -417,10 +417,10 @@ air_status air_ramp(air_plan p, const float* y, float* yf, int32_t batch, hipStr
     if (air_status st = stage_sino(p, y, batch, p->at<float>(p->off_s1), &src, s)) return st;
     const int rows = batch * p->g.n_views;
     if (p->direct(yf)) {
-        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, yf, rows, p->ds, 0, s));
+        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, yf, rows, p->ds, 0, 0, s));
     } else {
         float* s2 = p->at<float>(p->off_s2);
-        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, s2, rows, p->ds, 0, s));
+        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, s2, rows, p->ds, 0, 0, s));
         AIR_K(AIR_K_OTHER, launch_repack(s2, p->ds, yf, p->g.n_bins, rows, p->g.n_bins, p->g.n_bins, s));
     }
     return AIR_OK;
@@ -436,9 +436,10 @@ air_status air_filtered_backproject(air_plan p, const float* y, float* x, int32_
     const float* src = nullptr;
     if (air_status st = stage_sino(p, y, batch, p->at<float>(p->off_s1), &src, s)) return st;
     float* s2 = p->at<float>(p->off_s2);
+    const int bs = bp_batch_stride(batch);
     if (filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, s2, batch * p->g.n_views, p->ds,
-                                              RAMP_POST, s));
-    else AIR_K(AIR_K_OTHER, launch_scale(p->kgeom(), src, s2, batch, 1, s));
+                                              RAMP_POST, bs, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(p->kgeom(), src, s2, batch, 1, bs, s));
     BpArgs a{};
     a.mode = BP_PLAIN;
     a.out = x;
@@ -461,9 +462,10 @@ air_status air_normal_apply(air_plan p, const float* x, float* out, int32_t batc
     // A^T C A x = J^T (S C S) J x;  A^T A x = J^T S^2 J x
     AIR_K(AIR_K_OTHER, launch_pad(kg, x, pad, batch, s));
     AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, false, s));
+    const int bs = bp_batch_stride(batch);
     if (filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), s1, s2, batch * p->g.n_views, p->ds,
-                                              RAMP_PRE | RAMP_POST, s));
-    else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 2, s));
+                                              RAMP_PRE | RAMP_POST, bs, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 2, bs, s));
     const float* src = s2;
     BpArgs a{};
     a.mode = BP_MATVEC;
@@ -523,7 +525,7 @@ SolveLayout solve_layout(const air_plan_s* p, int batch) {
     SolveLayout L;
     L.pad = c.take(B * 2 * n * p->line * sizeof(float));
     L.s1 = c.take(B * p->g.n_views * p->ds * sizeof(float));
-    L.s2 = c.take(B * p->g.n_views * p->ds * sizeof(float));
+    L.s2 = c.take((B + 7) / 8 * 8 * p->g.n_views * p->ds * sizeof(float));   // interleaved backprojector input
     L.g = c.take(B * np * sizeof(float));
     L.r = c.take(B * np * sizeof(float));
     L.p = c.take(B * np * sizeof(float));
@@ -584,8 +586,9 @@ air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const 
     // (A = S J: the path lengths are applied in the ramp stage, or by a scaling pass for the IR arm)
     const float* src = nullptr;
     if (air_status st = stage_sino(p, Y, batch, s1, &src, s)) return st;
-    if (prm->filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, src, s2, rows, p->ds, RAMP_POST, s));
-    else AIR_K(AIR_K_OTHER, launch_scale(kg, src, s2, batch, 1, s));
+    const int bs = bp_batch_stride(batch);
+    if (prm->filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, src, s2, rows, p->ds, RAMP_POST, bs, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(kg, src, s2, batch, 1, bs, s));
     {
         BpArgs a{};
         a.mode = BP_PLAIN;
@@ -603,8 +606,8 @@ air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const 
         else AIR_HIP(hipMemcpyAsync(r, g, (size_t)batch * np * sizeof(float), hipMemcpyDeviceToDevice, s));
         // r = rhs - M X, p = r, rho = r.r
         AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, false, s));
-        if (prm->filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, s1, s2, rows, p->ds, RAMP_PRE | RAMP_POST, s));
-        else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 2, s));
+        if (prm->filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, s1, s2, rows, p->ds, RAMP_PRE | RAMP_POST, bs, s));
+        else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 2, bs, s));
         const float* bsrc = s2;
         {
             BpArgs a{};
@@ -620,8 +623,9 @@ air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const 
         }
         for (int it = 0; it < prm->n_cg; it++) {
             AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, false, s));
-            if (prm->filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, s1, s2, rows, p->ds, RAMP_PRE | RAMP_POST, s));
-            else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 2, s));
+            if (prm->filter)
+                AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, s1, s2, rows, p->ds, RAMP_PRE | RAMP_POST, bs, s));
+            else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 2, bs, s));
             BpArgs a{};
             a.mode = BP_MATVEC;
             a.mu = mu_op;

@@ -129,20 +129,21 @@ hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, bool 
     return hipGetLastError();
 }
 
-// out = y * step^power over internal rows (power 1: S y, power 2: S^2 y).
+// out[v][k][b] (stride bs) = y[b][v][k] * step[v][k]^power  (power 1: S y, power 2: S^2 y).
 __global__ __launch_bounds__(256) void k_scale(KGeom g, const float* __restrict__ y, float* __restrict__ out,
-                                               size_t count, int power) {
+                                               size_t count, int power, int bs) {
     const size_t per_batch = (size_t)g.n_views * g.ds;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) {
-        const float sv = g.step[i % per_batch];          // [v][k] of this element
-        out[i] = power == 2 ? y[i] * sv * sv : y[i] * sv;
+        const size_t b = i / per_batch, vk = i - b * per_batch;
+        const float sv = g.step[vk];
+        out[vk * bs + b] = power == 2 ? y[i] * sv * sv : y[i] * sv;
     }
 }
 
-hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, int power, hipStream_t s) {
+hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, int power, int bs, hipStream_t s) {
     const size_t count = (size_t)batch * g.n_views * g.ds;
     const size_t blocks = (count + 255) / 256 < 8192 ? (count + 255) / 256 : 8192;
-    hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, s, g, y, out, count, power);
+    hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, s, g, y, out, count, power, bs);
     return hipGetLastError();
 }
 
@@ -152,6 +153,7 @@ hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, i
 // group of BT images costs roughly (2 + BT) units: pick the tile that
 // minimises ceil(batch / BT) * (2 + BT).
 static int batch_tile(int batch) {
+    if (batch <= 1) return 1;
     int best = 1, best_cost = batch * 3;
     for (int bt : {2, 4, 8}) {
         const int cost = (batch + bt - 1) / bt * (2 + bt);
@@ -161,6 +163,11 @@ static int batch_tile(int batch) {
         }
     }
     return best;
+}
+
+int bp_batch_stride(int batch) {
+    const int bt = batch_tile(batch);
+    return (batch + bt - 1) / bt * bt;
 }
 
 // One thread per pixel and up to BT images, 16x16 pixels per block.  For every
@@ -184,6 +191,24 @@ __device__ __forceinline__ float joseph_weight(const RayEntry& e, int i, int j, 
     return (da >= ray_lo(e.meta) && da <= ray_hi(e.meta)) ? w : 0.f;
 }
 
+// BT contiguous floats, aligned to min(4 BT, 16) bytes.
+template <int BT>
+__device__ __forceinline__ void load_group(const float* p, float (&v)[BT]) {
+    if constexpr (BT % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < BT; q += 4) {
+            const float4 t = *reinterpret_cast<const float4*>(p + q);
+            v[q] = t.x; v[q + 1] = t.y; v[q + 2] = t.z; v[q + 3] = t.w;
+        }
+    } else if constexpr (BT == 2) {
+        const float2 t = *reinterpret_cast<const float2*>(p);
+        v[0] = t.x; v[1] = t.y;
+    } else {
+#pragma unroll
+        for (int q = 0; q < BT; q++) v[q] = p[q];
+    }
+}
+
 template <int MODE, bool REDUCE, int BT>
 __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __restrict__ y, BpArgs a, int batch) {
     __shared__ float tile[16][17];
@@ -195,9 +220,10 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     const bool valid = i < n && j < n;
     const float px = ((float)i - g.half_n) * g.pixel;
     const float py = ((float)j - g.half_n) * g.pixel;
-    const float* yb[BT];
-#pragma unroll
-    for (int q = 0; q < BT; q++) yb[q] = y + (size_t)min(b0 + q, batch - 1) * g.n_views * g.ds;
+    // batch-interleaved input [v][k][bs]: this thread's BT images are contiguous
+    // (bs is a multiple of BT, so the group is 4 * BT-byte aligned)
+    const int bs = (batch + BT - 1) / BT * BT;
+    const float* yb = y + b0;
     double tot[BT];
 #pragma unroll
     for (int q = 0; q < BT; q++) tot[q] = 0.0;
@@ -227,7 +253,7 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
             const int klo = max(0, (int)ceilf(fmaxf(kmin, -1.f)));
             const int khi = min(g.n_bins - 1, (int)floorf(fminf(kmax, (float)g.n_bins)));
             const RayEntry* rv = g.rays + (size_t)v * g.n_bins;
-            const size_t voff = (size_t)v * g.ds;
+            const float* yv = yb + (size_t)v * g.ds * bs;
             float part[BT];
 #pragma unroll
             for (int q = 0; q < BT; q++) part[q] = 0.f;
@@ -236,11 +262,8 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                 const int k1 = two ? k + 1 : k;
                 const RayEntry e0 = rv[k], e1 = rv[k1];
                 float yv0[BT], yv1[BT];
-#pragma unroll
-                for (int q = 0; q < BT; q++) {
-                    yv0[q] = yb[q][voff + k];
-                    yv1[q] = yb[q][voff + k1];
-                }
+                load_group<BT>(yv + (size_t)k * bs, yv0);
+                load_group<BT>(yv + (size_t)k1 * bs, yv1);
                 const float w0 = joseph_weight(e0, i, j, g.c0);
                 const float w1 = two ? joseph_weight(e1, i, j, g.c0) : 0.f;
 #pragma unroll
