@@ -168,6 +168,52 @@ air_status air_solve_workspace_size(air_plan plan, int32_t batch, size_t* bytes)
 air_status air_solve(air_plan plan, const float* Y, float* X, int32_t batch, const air_solve_params* p,
                      double* resid, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------------
+ * Solve slots (continuous batching).  A state holds up to `capacity` split-Bregman
+ * reconstructions of one plan's geometry, each with its own sinogram, start image
+ * and Bregman iteration count, and all sharing lambda, mu, n_cg and filter.  Every
+ * slot keeps X, g = A'^T Y, the Bregman variables b and d - b, its residual
+ * history and its counter resident on the device; the CG state is rebuilt every
+ * outer iteration.  air_state_step advances all active slots together with the
+ * batched kernels; slots can be admitted and retired between steps, so requests
+ * that arrive while others run join the next step.  A slot's result is the same
+ * bits whatever else is in the state (each image's arithmetic is independent).
+ * Steps on a non-default stream replay one HIP graph per number of active slots.
+ * The state object lives on the host; its device memory is the caller's `ws`.
+ * Calls on one state must be ordered on one stream.
+ * --------------------------------------------------------------------------------- */
+typedef struct air_state_s* air_state;
+
+/* Device bytes for a state of `capacity` slots; p->reg must be 0 and p->n_outer
+ * is the largest Bregman iteration count a slot may ask for. */
+air_status air_state_workspace_size(air_plan plan, int32_t capacity, const air_solve_params* p, size_t* bytes);
+air_status air_state_create(air_plan plan, int32_t capacity, const air_solve_params* p, void* ws, size_t ws_bytes,
+                            air_state* out);
+void air_state_destroy(air_state state);
+/* Start a reconstruction in a free slot: g = A'^T Y, b = d = 0, X = X0 (device
+ * [n][n]) or zeros when X0 is NULL.  Y: device [V][D].  n_outer in [1, the
+ * state's n_outer].  *slot receives the slot id.  AIR_E_NOMEM if all slots are busy. */
+air_status air_state_admit(air_state state, const float* Y, const float* X0, int32_t n_outer, hipStream_t stream,
+                           int32_t* slot);
+/* Advance every active slot by k = min(max_iters, the fewest iterations any
+ * active slot still needs) Bregman iterations; *done_iters (may be NULL) = k. */
+air_status air_state_step(air_state state, int32_t max_iters, hipStream_t stream, int32_t* done_iters);
+/* Host-side bookkeeping, no GPU call. */
+air_status air_state_query(air_state state, int32_t slot, int32_t* iters_done, int32_t* n_outer);
+air_status air_state_active(air_state state, int32_t* count);
+/* Copy the slot's image (device [n][n], may be NULL) and residual history
+ * (device [n_outer] float64 ||W X - d||, may be NULL) out, then free the slot. */
+air_status air_state_retire(air_state state, int32_t slot, float* X_out, double* resid_out, hipStream_t stream);
+/* Checkpoint: the slot's whole continuation state (X, g, b, d - b, residual
+ * history, iteration count) to a host buffer of air_state_snapshot_size bytes.
+ * The copy is asynchronous: synchronise `stream` before reading the buffer.
+ * Restore admits it into a free slot of a state with the same geometry and
+ * solver parameters (it synchronises `stream` before returning); continuing
+ * gives the same bits as never having stopped. */
+air_status air_state_snapshot_size(air_state state, size_t* bytes);
+air_status air_state_snapshot(air_state state, int32_t slot, void* host_buf, hipStream_t stream);
+air_status air_state_restore(air_state state, const void* host_buf, hipStream_t stream, int32_t* slot);
+
 /* Per-kernel timing (measurement support).  While enabled on a plan, every
  * kernel launch that plan makes (operators and air_solve) is bracketed by a
  * pair of HIP events on the launch stream.  air_kernel_timing_collect waits

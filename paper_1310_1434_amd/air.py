@@ -61,6 +61,17 @@ SIGNATURES = {
     "air_framelet": ([_P, _P, _P, _I, _I, _P], ctypes.c_int),
     "air_solve_workspace_size": ([_P, _I, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "air_solve": ([_P, _P, _P, _I, ctypes.POINTER(_SolveParams), _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "air_state_workspace_size": ([_P, _I, ctypes.POINTER(_SolveParams), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "air_state_create": ([_P, _I, ctypes.POINTER(_SolveParams), _P, ctypes.c_size_t, ctypes.POINTER(_P)], ctypes.c_int),
+    "air_state_destroy": ([_P], None),
+    "air_state_admit": ([_P, _P, _P, _I, _P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "air_state_step": ([_P, _I, _P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "air_state_query": ([_P, _I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "air_state_active": ([_P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "air_state_retire": ([_P, _I, _P, _P, _P], ctypes.c_int),
+    "air_state_snapshot_size": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "air_state_snapshot": ([_P, _I, _P, _P], ctypes.c_int),
+    "air_state_restore": ([_P, _P, _P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "air_kernel_timing_enable": ([_P, _I], ctypes.c_int),
     "air_kernel_timing_collect": ([_P, ctypes.POINTER(_KernelStats)], ctypes.c_int),
     "air_last_error": ([], ctypes.c_char_p),
@@ -251,3 +262,102 @@ class Plan:
         if resid is not None:
             resid = resid[:, :n_outer]
         return x, resid
+
+
+class State:
+    """Device-resident solve slots of one plan (continuous batching, see air_state_* in air.h).
+
+    All calls are queued on ``stream`` (a torch.cuda.Stream; the current stream if
+    None).  Steps on a non-default stream replay a captured HIP graph."""
+
+    def __init__(self, plan: Plan, capacity: int, lam: float, mu: float, n_cg: int, max_outer: int,
+                 filter: int = 1, stream=None):
+        self.plan = plan
+        self.stream = stream
+        self.capacity = int(capacity)
+        self.max_outer = int(max_outer)
+        self._params = _SolveParams(float(lam), float(mu), int(max_outer), int(n_cg), 0, int(filter))
+        size = ctypes.c_size_t()
+        _check(lib.air_state_workspace_size(plan._h, self.capacity, ctypes.byref(self._params), ctypes.byref(size)),
+               "air_state_workspace_size")
+        self.workspace_bytes = int(size.value)
+        with torch.cuda.stream(self._torch_stream()):
+            self._ws = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=plan.device)
+        h = ctypes.c_void_p()
+        _check(lib.air_state_create(plan._h, self.capacity, ctypes.byref(self._params),
+                                    ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel(), ctypes.byref(h)),
+               "air_state_create")
+        self._h = h
+        self._inputs = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.air_state_destroy(h)
+            self._h = None
+
+    def _torch_stream(self):
+        return self.stream if self.stream is not None else torch.cuda.current_stream(self.plan.device)
+
+    def _s(self):
+        return ctypes.c_void_p(self._torch_stream().cuda_stream)
+
+    @property
+    def active(self) -> int:
+        c = ctypes.c_int32()
+        _check(lib.air_state_active(self._h, ctypes.byref(c)), "air_state_active")
+        return int(c.value)
+
+    def admit(self, y: torch.Tensor, x0: torch.Tensor | None = None, n_outer: int | None = None) -> int:
+        """Start a reconstruction of sinogram y [V, D] (device); returns its slot id."""
+        p = self.plan
+        _dev_f32(y, p.device, (p.n_views, p.n_bins), "y")
+        if x0 is not None:
+            _dev_f32(x0, p.device, (p.n, p.n), "x0")
+        slot = ctypes.c_int32()
+        _check(lib.air_state_admit(self._h, ctypes.c_void_p(y.data_ptr()),
+                                   ctypes.c_void_p(x0.data_ptr()) if x0 is not None else None,
+                                   int(n_outer if n_outer is not None else self.max_outer), self._s(),
+                                   ctypes.byref(slot)), "air_state_admit")
+        st = self._torch_stream()
+        y.record_stream(st)
+        if x0 is not None:
+            x0.record_stream(st)
+        return int(slot.value)
+
+    def step(self, max_iters: int = 1) -> int:
+        done = ctypes.c_int32()
+        _check(lib.air_state_step(self._h, int(max_iters), self._s(), ctypes.byref(done)), "air_state_step")
+        return int(done.value)
+
+    def query(self, slot: int):
+        it, no = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.air_state_query(self._h, int(slot), ctypes.byref(it), ctypes.byref(no)), "air_state_query")
+        return int(it.value), int(no.value)
+
+    def retire(self, slot: int):
+        """Copy out (X [n, n], resid [n_outer] float64) and free the slot (asynchronous)."""
+        _, n_outer = self.query(slot)
+        p = self.plan
+        with torch.cuda.stream(self._torch_stream()):
+            x = torch.empty((p.n, p.n), device=p.device)
+            r = torch.empty((n_outer,), dtype=torch.float64, device=p.device)
+        _check(lib.air_state_retire(self._h, int(slot), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(r.data_ptr()),
+                                    self._s()), "air_state_retire")
+        return x, r
+
+    def snapshot(self, slot: int) -> np.ndarray:
+        size = ctypes.c_size_t()
+        _check(lib.air_state_snapshot_size(self._h, ctypes.byref(size)), "air_state_snapshot_size")
+        buf = np.empty(int(size.value), np.uint8)
+        _check(lib.air_state_snapshot(self._h, int(slot), ctypes.c_void_p(buf.ctypes.data), self._s()),
+               "air_state_snapshot")
+        self._torch_stream().synchronize()
+        return buf
+
+    def restore(self, buf: np.ndarray) -> int:
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        slot = ctypes.c_int32()
+        _check(lib.air_state_restore(self._h, ctypes.c_void_p(buf.ctypes.data), self._s(), ctypes.byref(slot)),
+               "air_state_restore")
+        return int(slot.value)

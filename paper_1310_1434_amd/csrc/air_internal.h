@@ -110,10 +110,10 @@ enum FinalizeMode {
     FIN_RHO = 0,    // rho[b] = sum                                    (initial residual)
     FIN_ALPHA = 1,  // pq = sum; alpha[b] = rho / pq (0 if either is 0)
     FIN_BETA = 2,   // rho' = sum; beta[b] = rho' / rho (0 if rho is 0); rho[b] = rho'
-    FIN_RESID = 3,  // out[b * stride] = sqrt(sum)                     (Bregman residual)
+    FIN_RESID = 3,  // out[b * stride + k] = sqrt(sum), k = iters[b]++ (k = 0 if iters is null)
 };
 hipError_t launch_finalize(int mode, const double* partial, int nblk, int batch, double* rho, double* coef,
-                           double* out, int stride, hipStream_t s);
+                           double* out, int stride, int* iters, hipStream_t s);
 
 // Framelet kernels.
 hipError_t launch_framelet_fwd(int n, const float* x, float* z, int batch, hipStream_t s);

@@ -1,15 +1,10 @@
 // C ABI of the AIR library: plans, operator entry points and the split
 // Bregman solver.  Host code; all arithmetic runs in the kernels.
-#include <cmath>
-#include <cstring>
 #include <new>
-#include <string>
 
-#include "air_internal.h"
+#include "plan.h"
 
-using namespace air;
-
-namespace {
+namespace air {
 
 thread_local std::string g_err;
 
@@ -18,22 +13,9 @@ air_status fail(air_status st, const std::string& msg) {
     return st;
 }
 
-#define AIR_HIP(expr)                                                                         \
-    do {                                                                                      \
-        hipError_t e_ = (expr);                                                               \
-        if (e_ != hipSuccess) return fail(AIR_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
+}  // namespace air
 
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-struct Carver {
-    size_t off = 0;
-    size_t take(size_t bytes) {
-        const size_t o = off;
-        off = align256(off + bytes);
-        return o;
-    }
-};
+namespace {
 
 // float -> IEEE half, round to nearest even (host side, for the filter fragments)
 uint16_t f32_to_f16(float f) {
@@ -90,140 +72,6 @@ float bf16_to_f32(uint16_t h) {
     return v;
 }
 
-}  // namespace
-
-struct air_plan_s {
-    GeomHost g;
-    int max_batch = 1;
-    air_precision prec = AIR_FP32;
-    int ds = 0, line = 0, c0 = 0;
-    double kappa = 0.0;
-    std::vector<RayEntry> rays;
-    std::vector<float> step;       // [n_views][ds] path length per driving step, 0 in the padding
-    std::vector<int8_t> axis;
-    std::vector<int32_t> lo, hi;
-    std::vector<float> views;      // interleaved (cos, sin) as float
-    std::vector<float> taps32;     // [2 ds]
-    std::vector<uint16_t> frag[3];
-    int n_terms = 0, n_frag = 0, dmin = 0;
-    // workspace layout (bytes)
-    size_t off_rays = 0, off_step = 0, off_views = 0, off_taps = 0, off_frag[3] = {0, 0, 0};
-    size_t off_pad = 0, off_s1 = 0, off_s2 = 0, total = 0;
-    char* ws = nullptr;
-    // per-kernel event timing (air_kernel_timing_enable)
-    struct Timed {
-        int kind;
-        hipEvent_t a, b;
-    };
-    bool timing = false;
-    std::vector<Timed> pending;
-    std::vector<hipEvent_t> pool;
-
-    ~air_plan_s() {
-        for (const Timed& t : pending) {
-            (void)hipEventDestroy(t.a);
-            (void)hipEventDestroy(t.b);
-        }
-        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-    }
-    hipEvent_t take_event() {
-        if (!pool.empty()) {
-            hipEvent_t e = pool.back();
-            pool.pop_back();
-            return e;
-        }
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        return e;
-    }
-
-    KGeom kgeom() const {
-        KGeom k;
-        k.n = g.n;
-        k.n_views = g.n_views;
-        k.n_bins = g.n_bins;
-        k.ds = ds;
-        k.line = line;
-        k.c0 = c0;
-        k.beam = g.beam;
-        k.pixel = (float)g.pixel;
-        k.half_n = (float)(0.5 * (g.n - 1));
-        k.inv_bin = (float)(1.0 / g.bin);
-        k.half_d = (float)(0.5 * (g.n_bins - 1));
-        k.sod = (float)g.sod;
-        k.sdd = (float)g.sdd;
-        k.rays = reinterpret_cast<const RayEntry*>(ws + off_rays);
-        k.step = reinterpret_cast<const float*>(ws + off_step);
-        k.views = reinterpret_cast<const float2*>(ws + off_views);
-        return k;
-    }
-    RampTables ramp_tables() const {
-        RampTables t;
-        t.taps32 = reinterpret_cast<const float*>(ws + off_taps);
-        t.step = reinterpret_cast<const float*>(ws + off_step);
-        t.n_views = g.n_views;
-        t.frag_a = n_terms > 0 ? reinterpret_cast<const uint4*>(ws + off_frag[0]) : nullptr;
-        t.frag_b = n_terms > 1 ? reinterpret_cast<const uint4*>(ws + off_frag[1]) : nullptr;
-        t.frag_c = n_terms > 2 ? reinterpret_cast<const uint4*>(ws + off_frag[2]) : nullptr;
-        t.n_frag = n_frag;
-        t.dmin = dmin;
-        t.out_scale = (float)(kappa / 4096.0);
-        return t;
-    }
-    template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
-    bool direct(const void* p) const { return g.n_bins == ds && (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
-};
-
-namespace {
-
-// Brackets one kernel launch with events when timing is enabled on the plan.
-struct KTimer {
-    air_plan_s* p;
-    int kind;
-    hipStream_t s;
-    hipEvent_t a = nullptr, b = nullptr;
-    KTimer(air_plan_s* p_, int kind_, hipStream_t s_) : p(p_), kind(kind_), s(s_) {
-        if (p->timing) {
-            a = p->take_event();
-            b = p->take_event();
-            if (a && b && hipEventRecord(a, s) != hipSuccess) a = nullptr;
-        }
-    }
-    void done() {
-        if (a && b && hipEventRecord(b, s) == hipSuccess) p->pending.push_back({kind, a, b});
-    }
-};
-
-#define AIR_K(kind, expr)             \
-    do {                              \
-        KTimer t_(p, kind, s);        \
-        AIR_HIP(expr);                \
-        t_.done();                    \
-    } while (0)
-
-air_status check_plan(air_plan p, bool need_ws) {
-    if (!p) return fail(AIR_E_INVALID, "plan is null");
-    if (need_ws && !p->ws) return fail(AIR_E_INVALID, "plan has no workspace bound");
-    return AIR_OK;
-}
-
-air_status check_batch(air_plan p, int32_t batch, bool bounded) {
-    if (batch < 1) return fail(AIR_E_INVALID, "batch must be >= 1");
-    if (bounded && batch > p->max_batch) return fail(AIR_E_INVALID, "batch exceeds the plan's max_batch");
-    return AIR_OK;
-}
-
-// y (public stride n_bins) -> internal rows of stride ds, unless it can be read in place.
-air_status stage_sino(air_plan p, const float* y, int32_t batch, float* scratch, const float** out, hipStream_t s) {
-    if (p->direct(y)) {
-        *out = y;
-        return AIR_OK;
-    }
-    const int rows = batch * p->g.n_views;
-    AIR_K(AIR_K_OTHER, launch_repack(y, p->g.n_bins, scratch, p->ds, rows, p->g.n_bins, p->ds, s));
-    *out = scratch;
-    return AIR_OK;
-}
 
 }  // namespace
 
@@ -513,33 +361,6 @@ air_status air_framelet(air_plan p, const float* in, float* out, int32_t batch, 
 
 }  // extern "C"
 
-namespace {
-
-struct SolveLayout {
-    size_t pad, s1, s2, g, r, p, q, bb, e, part, scal, total;
-};
-
-SolveLayout solve_layout(const air_plan_s* p, int batch) {
-    const size_t B = (size_t)batch, n = (size_t)p->g.n, np = n * n;
-    Carver c;
-    SolveLayout L;
-    L.pad = c.take(B * 2 * n * p->line * sizeof(float));
-    L.s1 = c.take(B * p->g.n_views * p->ds * sizeof(float));
-    L.s2 = c.take((B + 7) / 8 * 8 * p->g.n_views * p->ds * sizeof(float));   // interleaved backprojector input
-    L.g = c.take(B * np * sizeof(float));
-    L.r = c.take(B * np * sizeof(float));
-    L.p = c.take(B * np * sizeof(float));
-    L.q = c.take(B * np * sizeof(float));
-    L.bb = c.take(B * 8 * np * sizeof(float));
-    L.e = c.take(B * 9 * np * sizeof(float));
-    L.part = c.take(B * tiles16((int)n) * sizeof(double));
-    L.scal = c.take(B * 4 * sizeof(double));
-    L.total = c.off;
-    return L;
-}
-
-}  // namespace
-
 extern "C" {
 
 air_status air_solve_workspace_size(air_plan p, int32_t batch, size_t* bytes) {
@@ -563,108 +384,18 @@ air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const 
     if (prm->n_outer < 0 || prm->n_cg < 0) return fail(AIR_E_INVALID, "iteration counts must be >= 0");
     const SolveLayout L = solve_layout(p, batch);
     if (ws_bytes < L.total) return fail(AIR_E_NOMEM, "workspace smaller than air_solve_workspace_size");
-
-    char* w = static_cast<char*>(ws);
-    auto F = [&](size_t off) { return reinterpret_cast<float*>(w + off); };
-    const KGeom kg = p->kgeom();
-    const RampTables rt = p->ramp_tables();
-    const int n = p->g.n, rows = batch * p->g.n_views, nblk = tiles16(n);
-    const size_t np = (size_t)n * n;
-    PadBuf pad{F(L.pad)};
-    float *s1 = F(L.s1), *s2 = F(L.s2), *g = F(L.g), *r = F(L.r), *pv = F(L.p), *q = F(L.q);
-    float *bb = F(L.bb), *e = F(L.e);
-    double* part = reinterpret_cast<double*>(w + L.part);
-    double* scal = reinterpret_cast<double*>(w + L.scal);
-    double* rho = scal;                 // [batch] current r . r
-    double* alpha = scal + batch;       // [batch]
-    double* beta = scal + 2 * batch;    // [batch]
-    double* junk = scal + 3 * batch;    // [batch] residual norms when the caller wants none
-    const bool tf = prm->reg == 0;
-    const float mu_op = (float)(tf ? prm->mu : prm->lambda);
-
-    // g = A'^T Y (or A^T Y)
-    // (A = S J: the path lengths are applied in the ramp stage, or by a scaling pass for the IR arm)
-    const float* src = nullptr;
-    if (air_status st = stage_sino(p, Y, batch, s1, &src, s)) return st;
-    const int bs = bp_batch_stride(batch);
-    if (prm->filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, src, s2, rows, p->ds, RAMP_POST, bs, s));
-    else AIR_K(AIR_K_OTHER, launch_scale(kg, src, s2, batch, 1, bs, s));
-    {
-        BpArgs a{};
-        a.mode = BP_PLAIN;
-        a.out = g;
-        AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, s2, a, batch, s));
+    SolveBufs B = solve_bufs(p, L, static_cast<char*>(ws), X, batch);
+    if (resid) {
+        B.resid = resid;
+        B.resid_stride = prm->n_outer;
+    } else {
+        B.iters = nullptr;          // residual norms go to scratch, one slot per image
     }
-    if (tf) {
-        AIR_K(AIR_K_OTHER, launch_fill(bb, (size_t)batch * 8 * np, 0.f, s));
-        AIR_K(AIR_K_OTHER, launch_fill(e, (size_t)batch * 9 * np, 0.f, s));
-    }
-    AIR_K(AIR_K_OTHER, launch_pad(kg, X, pad, batch, s));
-    const int n_out = tf ? prm->n_outer : 1;
-    for (int k = 0; k < n_out; k++) {
-        if (tf) AIR_K(AIR_K_FRAMELET, launch_tf_rhs(n, g, e, (float)prm->mu, r, batch, s));
-        else AIR_HIP(hipMemcpyAsync(r, g, (size_t)batch * np * sizeof(float), hipMemcpyDeviceToDevice, s));
-        // r = rhs - M X, p = r, rho = r.r
-        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, false, s));
-        if (prm->filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, s1, s2, rows, p->ds, RAMP_PRE | RAMP_POST, bs, s));
-        else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 2, bs, s));
-        const float* bsrc = s2;
-        {
-            BpArgs a{};
-            a.mode = BP_RESIDUAL;
-            a.mu = mu_op;
-            a.aux = X;
-            a.out = r;
-            a.p_out = pv;
-            a.pad_out = pad;
-            a.partial = part;
-            AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, bsrc, a, batch, s));
-            AIR_K(AIR_K_CG, launch_finalize(FIN_RHO, part, nblk, batch, rho, nullptr, nullptr, 0, s));
-        }
-        for (int it = 0; it < prm->n_cg; it++) {
-            AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, false, s));
-            if (prm->filter)
-                AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, s1, s2, rows, p->ds, RAMP_PRE | RAMP_POST, bs, s));
-            else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 2, bs, s));
-            BpArgs a{};
-            a.mode = BP_MATVEC;
-            a.mu = mu_op;
-            a.aux = pv;
-            a.out = q;
-            a.partial = part;
-            AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, s2, a, batch, s));
-            AIR_K(AIR_K_CG, launch_finalize(FIN_ALPHA, part, nblk, batch, rho, alpha, nullptr, 0, s));
-            CgArgs cg{};
-            cg.n = n;
-            cg.x = X;
-            cg.r = r;
-            cg.p = pv;
-            cg.q = q;
-            cg.pad.base = it == prm->n_cg - 1 ? pad.base : nullptr;
-            cg.alpha = alpha;
-            cg.beta = beta;
-            cg.partial = part;
-            AIR_K(AIR_K_CG, launch_cg_update_xr(cg, batch, s));
-            if (it < prm->n_cg - 1) {
-                AIR_K(AIR_K_CG, launch_finalize(FIN_BETA, part, nblk, batch, rho, beta, nullptr, 0, s));
-                cg.pad = pad;
-                AIR_K(AIR_K_CG, launch_cg_update_p(cg, batch, s));
-            }
-        }
-        if (prm->n_cg == 0) AIR_K(AIR_K_OTHER, launch_pad(kg, X, pad, batch, s));
-        if (tf) {
-            TfArgs t{};
-            t.n = n;
-            t.x = X;
-            t.bb = bb;
-            t.e = e;
-            t.thr = (float)(prm->lambda / (2.0 * prm->mu));
-            t.partial = part;
-            AIR_K(AIR_K_FRAMELET, launch_tf_shrink(t, batch, s));
-            AIR_K(AIR_K_FRAMELET, launch_finalize(FIN_RESID, part, nblk, batch, nullptr, nullptr,
-                                                  resid ? resid + k : junk, resid ? prm->n_outer : 1, s));
-        }
-    }
+    const SolveSetup setup{prm->reg, prm->filter, prm->lambda, prm->mu, prm->n_cg};
+    if (air_status st = solve_init(p, B, Y, batch, setup, s)) return st;
+    const int n_out = prm->reg == 0 ? prm->n_outer : 1;
+    for (int k = 0; k < n_out; k++)
+        if (air_status st = solve_outer(p, B, batch, setup, s)) return st;
     return AIR_OK;
 }
 

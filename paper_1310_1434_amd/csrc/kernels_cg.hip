@@ -72,7 +72,7 @@ hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s) {
 // thread a fixed stride, then a fixed tree) and derive the CG scalar.
 __global__ __launch_bounds__(256) void k_finalize(int mode, const double* __restrict__ partial, int nblk,
                                                   double* __restrict__ rho, double* __restrict__ coef,
-                                                  double* __restrict__ out, int stride) {
+                                                  double* __restrict__ out, int stride, int* __restrict__ iters) {
     __shared__ double sh[4];
     const int b = blockIdx.x, tid = threadIdx.x;
     const double* pb = partial + (size_t)b * nblk;
@@ -98,14 +98,17 @@ __global__ __launch_bounds__(256) void k_finalize(int mode, const double* __rest
         rho[b] = sum;
         break;
     }
-    default:
-        out[(size_t)b * stride] = sqrt(sum);
+    default: {
+        const int k = iters ? iters[b] : 0;
+        out[(size_t)b * stride + k] = sqrt(sum);
+        if (iters) iters[b] = k + 1;
+    }
     }
 }
 
 hipError_t launch_finalize(int mode, const double* partial, int nblk, int batch, double* rho, double* coef,
-                           double* out, int stride, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(256), 0, s, mode, partial, nblk, rho, coef, out, stride);
+                           double* out, int stride, int* iters, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(256), 0, s, mode, partial, nblk, rho, coef, out, stride, iters);
     return hipGetLastError();
 }
 

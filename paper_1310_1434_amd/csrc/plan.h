@@ -1,0 +1,212 @@
+// Internal: the plan object, launch bracketing, argument checks and the
+// split-Bregman iteration shared by air_solve and the solve slots.
+#pragma once
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "air_internal.h"
+
+namespace air {
+
+air_status fail(air_status st, const std::string& msg);
+
+#define AIR_HIP(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return air::fail(AIR_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    }
+};
+
+}  // namespace air
+
+using namespace air;
+
+struct air_plan_s {
+    GeomHost g;
+    int max_batch = 1;
+    air_precision prec = AIR_FP32;
+    int ds = 0, line = 0, c0 = 0;
+    double kappa = 0.0;
+    std::vector<RayEntry> rays;
+    std::vector<float> step;       // [n_views][ds] path length per driving step, 0 in the padding
+    std::vector<int8_t> axis;
+    std::vector<int32_t> lo, hi;
+    std::vector<float> views;      // interleaved (cos, sin) as float
+    std::vector<float> taps32;     // [2 ds]
+    std::vector<uint16_t> frag[3];
+    int n_terms = 0, n_frag = 0, dmin = 0;
+    // workspace layout (bytes)
+    size_t off_rays = 0, off_step = 0, off_views = 0, off_taps = 0, off_frag[3] = {0, 0, 0};
+    size_t off_pad = 0, off_s1 = 0, off_s2 = 0, total = 0;
+    char* ws = nullptr;
+    // per-kernel event timing (air_kernel_timing_enable)
+    struct Timed {
+        int kind;
+        hipEvent_t a, b;
+    };
+    bool timing = false;
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> pool;
+
+    ~air_plan_s() {
+        for (const Timed& t : pending) {
+            (void)hipEventDestroy(t.a);
+            (void)hipEventDestroy(t.b);
+        }
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+    hipEvent_t take_event() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+
+    KGeom kgeom() const {
+        KGeom k;
+        k.n = g.n;
+        k.n_views = g.n_views;
+        k.n_bins = g.n_bins;
+        k.ds = ds;
+        k.line = line;
+        k.c0 = c0;
+        k.beam = g.beam;
+        k.pixel = (float)g.pixel;
+        k.half_n = (float)(0.5 * (g.n - 1));
+        k.inv_bin = (float)(1.0 / g.bin);
+        k.half_d = (float)(0.5 * (g.n_bins - 1));
+        k.sod = (float)g.sod;
+        k.sdd = (float)g.sdd;
+        k.rays = reinterpret_cast<const RayEntry*>(ws + off_rays);
+        k.step = reinterpret_cast<const float*>(ws + off_step);
+        k.views = reinterpret_cast<const float2*>(ws + off_views);
+        return k;
+    }
+    RampTables ramp_tables() const {
+        RampTables t;
+        t.taps32 = reinterpret_cast<const float*>(ws + off_taps);
+        t.step = reinterpret_cast<const float*>(ws + off_step);
+        t.n_views = g.n_views;
+        t.frag_a = n_terms > 0 ? reinterpret_cast<const uint4*>(ws + off_frag[0]) : nullptr;
+        t.frag_b = n_terms > 1 ? reinterpret_cast<const uint4*>(ws + off_frag[1]) : nullptr;
+        t.frag_c = n_terms > 2 ? reinterpret_cast<const uint4*>(ws + off_frag[2]) : nullptr;
+        t.n_frag = n_frag;
+        t.dmin = dmin;
+        t.out_scale = (float)(kappa / 4096.0);
+        return t;
+    }
+    template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+    bool direct(const void* p) const { return g.n_bins == ds && (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+};
+
+namespace air {
+
+// Brackets one kernel launch with events when timing is enabled on the plan.
+struct KTimer {
+    air_plan_s* p;
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    KTimer(air_plan_s* p_, int kind_, hipStream_t s_) : p(p_), kind(kind_), s(s_) {
+        if (p->timing) {
+            a = p->take_event();
+            b = p->take_event();
+            if (a && b && hipEventRecord(a, s) != hipSuccess) a = nullptr;
+        }
+    }
+    void done() {
+        if (a && b && hipEventRecord(b, s) == hipSuccess) p->pending.push_back({kind, a, b});
+    }
+};
+
+#define AIR_K(kind, expr)             \
+    do {                              \
+        KTimer t_(p, kind, s);        \
+        AIR_HIP(expr);                \
+        t_.done();                    \
+    } while (0)
+
+inline air_status check_plan(air_plan p, bool need_ws) {
+    if (!p) return fail(AIR_E_INVALID, "plan is null");
+    if (need_ws && !p->ws) return fail(AIR_E_INVALID, "plan has no workspace bound");
+    return AIR_OK;
+}
+
+inline air_status check_batch(air_plan p, int32_t batch, bool bounded) {
+    if (batch < 1) return fail(AIR_E_INVALID, "batch must be >= 1");
+    if (bounded && batch > p->max_batch) return fail(AIR_E_INVALID, "batch exceeds the plan's max_batch");
+    return AIR_OK;
+}
+
+// y (public stride n_bins) -> internal rows of stride ds, unless it can be read in place.
+inline air_status stage_sino(air_plan p, const float* y, int32_t batch, float* scratch, const float** out, hipStream_t s) {
+    if (p->direct(y)) {
+        *out = y;
+        return AIR_OK;
+    }
+    const int rows = batch * p->g.n_views;
+    AIR_K(AIR_K_OTHER, launch_repack(y, p->g.n_bins, scratch, p->ds, rows, p->g.n_bins, p->ds, s));
+    *out = scratch;
+    return AIR_OK;
+}
+
+
+// Device buffers of a batch of reconstructions in the split-Bregman loop
+// (images at positions [0, batch); per-image buffers are contiguous per image).
+struct SolveBufs {
+    float* X;       // [batch][n][n] current image
+    float* pad;     // [batch][2][n][line] padded copies of X or p
+    float* s1;      // [batch][n_views][ds] projections
+    float* s2;      // interleaved backprojector input, stride bp_batch_stride(batch)
+    float* g;       // [batch][n][n]  A'^T Y
+    float* r;       // [batch][n][n]  right-hand side, then CG residual
+    float* p;       // [batch][n][n]
+    float* q;       // [batch][n][n]
+    float* bb;      // [batch][8][n][n] Bregman b (bands 1..8)
+    float* e;       // [batch][9][n][n] d - b
+    double* part;   // [batch][tiles16(n)] block partial sums
+    double* rho;    // [batch]
+    double* alpha;  // [batch]
+    double* beta;   // [batch]
+    double* resid;  // residual history, resid[b * resid_stride + iters[b]]
+    int resid_stride;
+    int* iters;     // [batch] per-image Bregman iteration counters, or null (then resid[b * stride])
+};
+
+struct SolveSetup {
+    int reg;        // 0 split Bregman, 1 L2
+    int filter;     // 1 AIR, 0 IR
+    double lambda, mu;
+    int n_cg;
+};
+
+// Bytes of the per-image buffers of SolveBufs (excluding the sinogram scratch).
+struct SolveLayout {
+    size_t pad, s1, s2, g, r, p, q, bb, e, part, scal, iters, total;
+};
+SolveLayout solve_layout(const air_plan_s* p, int batch);
+SolveBufs solve_bufs(const air_plan_s* p, const SolveLayout& L, char* ws, float* X, int batch);
+
+// g = A'^T Y (or A^T Y); zero b and e; padded copies of X.  Y: [batch][V][D] (public layout).
+air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch, const SolveSetup& st, hipStream_t s);
+// One outer iteration (split Bregman) or the whole CG run (L2) for images [0, batch).
+air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSetup& st, hipStream_t s);
+
+}  // namespace air

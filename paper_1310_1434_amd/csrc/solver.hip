@@ -1,0 +1,154 @@
+// The split-Bregman iteration (and the L2 solve of Eq. (5)) as sequences of
+// kernel launches on one stream.  Shared by air_solve and the solve slots of
+// air_state; an outer iteration has fixed launch parameters, so it can be
+// captured once in a HIP graph and replayed.
+#include "plan.h"
+
+namespace air {
+
+SolveLayout solve_layout(const air_plan_s* p, int batch) {
+    const size_t B = (size_t)batch, n = (size_t)p->g.n, np = n * n;
+    Carver c;
+    SolveLayout L;
+    L.pad = c.take(B * 2 * n * p->line * sizeof(float));
+    L.s1 = c.take(B * p->g.n_views * p->ds * sizeof(float));
+    L.s2 = c.take((B + 7) / 8 * 8 * p->g.n_views * p->ds * sizeof(float));   // interleaved backprojector input
+    L.g = c.take(B * np * sizeof(float));
+    L.r = c.take(B * np * sizeof(float));
+    L.p = c.take(B * np * sizeof(float));
+    L.q = c.take(B * np * sizeof(float));
+    L.bb = c.take(B * 8 * np * sizeof(float));
+    L.e = c.take(B * 9 * np * sizeof(float));
+    L.part = c.take(B * tiles16((int)n) * sizeof(double));
+    L.scal = c.take(B * 4 * sizeof(double));
+    L.iters = c.take(B * sizeof(int));
+    L.total = c.off;
+    return L;
+}
+
+SolveBufs solve_bufs(const air_plan_s* p, const SolveLayout& L, char* w, float* X, int batch) {
+    (void)p;
+    auto F = [&](size_t off) { return reinterpret_cast<float*>(w + off); };
+    SolveBufs B;
+    B.X = X;
+    B.pad = F(L.pad);
+    B.s1 = F(L.s1);
+    B.s2 = F(L.s2);
+    B.g = F(L.g);
+    B.r = F(L.r);
+    B.p = F(L.p);
+    B.q = F(L.q);
+    B.bb = F(L.bb);
+    B.e = F(L.e);
+    B.part = reinterpret_cast<double*>(w + L.part);
+    double* scal = reinterpret_cast<double*>(w + L.scal);
+    B.rho = scal;
+    B.alpha = scal + batch;
+    B.beta = scal + 2 * batch;
+    B.resid = scal + 3 * batch;     // scratch: one norm per image (stride 1, no counters)
+    B.resid_stride = 1;
+    B.iters = reinterpret_cast<int*>(w + L.iters);
+    return B;
+}
+
+air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch, const SolveSetup& st, hipStream_t s) {
+    const KGeom kg = p->kgeom();
+    const int rows = batch * p->g.n_views;
+    const size_t np = (size_t)p->g.n * p->g.n;
+    // g = A'^T Y = J^T (S C Y), or A^T Y = J^T (S Y) for the IR arm
+    const float* src = nullptr;
+    if (air_status e = stage_sino(p, Y, batch, B.s1, &src, s)) return e;
+    const int bs = bp_batch_stride(batch);
+    if (st.filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, B.s2, rows, p->ds, RAMP_POST, bs, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(kg, src, B.s2, batch, 1, bs, s));
+    BpArgs a{};
+    a.mode = BP_PLAIN;
+    a.out = B.g;
+    AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, B.s2, a, batch, s));
+    if (st.reg == 0) {
+        AIR_K(AIR_K_OTHER, launch_fill(B.bb, (size_t)batch * 8 * np, 0.f, s));
+        AIR_K(AIR_K_OTHER, launch_fill(B.e, (size_t)batch * 9 * np, 0.f, s));
+    }
+    if (B.iters) AIR_K(AIR_K_OTHER, launch_fill(reinterpret_cast<float*>(B.iters), (size_t)batch, 0.f, s));
+    AIR_K(AIR_K_OTHER, launch_pad(kg, B.X, PadBuf{B.pad}, batch, s));
+    return AIR_OK;
+}
+
+air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSetup& st, hipStream_t s) {
+    const KGeom kg = p->kgeom();
+    const RampTables rt = p->ramp_tables();
+    const int n = p->g.n, rows = batch * p->g.n_views, nblk = tiles16(n);
+    const size_t np = (size_t)n * n;
+    const int bs = bp_batch_stride(batch);
+    const bool tf = st.reg == 0;
+    const float mu_op = (float)(tf ? st.mu : st.lambda);
+    const PadBuf pad{B.pad};
+    // operator A'^T A + mu I = J^T (S C S) J + mu I (IR arm: J^T S^2 J + mu I)
+    auto filtered = [&]() -> air_status {
+        if (st.filter)
+            AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, B.s1, B.s2, rows, p->ds, RAMP_PRE | RAMP_POST, bs, s));
+        else AIR_K(AIR_K_OTHER, launch_scale(kg, B.s1, B.s2, batch, 2, bs, s));
+        return AIR_OK;
+    };
+    if (tf) AIR_K(AIR_K_FRAMELET, launch_tf_rhs(n, B.g, B.e, (float)st.mu, B.r, batch, s));
+    else AIR_HIP(hipMemcpyAsync(B.r, B.g, (size_t)batch * np * sizeof(float), hipMemcpyDeviceToDevice, s));
+    // r = rhs - M X, p = r, rho = r.r
+    AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, false, s));
+    if (air_status e = filtered()) return e;
+    {
+        BpArgs a{};
+        a.mode = BP_RESIDUAL;
+        a.mu = mu_op;
+        a.aux = B.X;
+        a.out = B.r;
+        a.p_out = B.p;
+        a.pad_out = pad;
+        a.partial = B.part;
+        AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, B.s2, a, batch, s));
+        AIR_K(AIR_K_CG, launch_finalize(FIN_RHO, B.part, nblk, batch, B.rho, nullptr, nullptr, 0, nullptr, s));
+    }
+    for (int it = 0; it < st.n_cg; it++) {
+        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, false, s));
+        if (air_status e = filtered()) return e;
+        BpArgs a{};
+        a.mode = BP_MATVEC;
+        a.mu = mu_op;
+        a.aux = B.p;
+        a.out = B.q;
+        a.partial = B.part;
+        AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, B.s2, a, batch, s));
+        AIR_K(AIR_K_CG, launch_finalize(FIN_ALPHA, B.part, nblk, batch, B.rho, B.alpha, nullptr, 0, nullptr, s));
+        CgArgs cg{};
+        cg.n = n;
+        cg.x = B.X;
+        cg.r = B.r;
+        cg.p = B.p;
+        cg.q = B.q;
+        cg.pad.base = it == st.n_cg - 1 ? B.pad : nullptr;
+        cg.alpha = B.alpha;
+        cg.beta = B.beta;
+        cg.partial = B.part;
+        AIR_K(AIR_K_CG, launch_cg_update_xr(cg, batch, s));
+        if (it < st.n_cg - 1) {
+            AIR_K(AIR_K_CG, launch_finalize(FIN_BETA, B.part, nblk, batch, B.rho, B.beta, nullptr, 0, nullptr, s));
+            cg.pad = pad;
+            AIR_K(AIR_K_CG, launch_cg_update_p(cg, batch, s));
+        }
+    }
+    if (st.n_cg == 0) AIR_K(AIR_K_OTHER, launch_pad(kg, B.X, pad, batch, s));
+    if (tf) {
+        TfArgs t{};
+        t.n = n;
+        t.x = B.X;
+        t.bb = B.bb;
+        t.e = B.e;
+        t.thr = (float)(st.lambda / (2.0 * st.mu));
+        t.partial = B.part;
+        AIR_K(AIR_K_FRAMELET, launch_tf_shrink(t, batch, s));
+        AIR_K(AIR_K_FRAMELET, launch_finalize(FIN_RESID, B.part, nblk, batch, nullptr, nullptr, B.resid,
+                                              B.resid_stride, B.iters, s));
+    }
+    return AIR_OK;
+}
+
+}  // namespace air

@@ -18,15 +18,16 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 
 CASES = {
-    # name: (workload, seed)
-    "c2_fan_512_720_seed0": ("c2", 0),
-    "c2_fan_512_180_seed0": ("c2_25", 0),
+    # name: (workload, seed, Bregman iterations or None for the workload's own)
+    "c2_fan_512_720_seed0": ("c2", 0, None),
+    "c2_fan_512_180_seed0": ("c2_25", 0, None),
+    "c5_fan_1024_2304_seed0_outer2": ("c5", 0, 2),
 }
 
 
 def make(name: str):
-    wname, seed = CASES[name]
-    w = synth.workload(wname)
+    wname, seed, n_outer = CASES[name]
+    w = synth.workload(wname) if n_outer is None else synth.workload(wname, n_outer=n_outer)
     case = synth.make_case(w, seed)
     y32 = case["y"].astype(np.float32)
     g = oracle.Geom(w.geom)

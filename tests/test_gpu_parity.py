@@ -272,3 +272,72 @@ def test_solve_parity_c2_full_size(air, torch_mod, record, case, wname):
     record("rel_l2_final", rel(host(x)[0], ref["x"]))
     assert rel(host(x)[0], ref["x"]) < 1e-4
     np.testing.assert_allclose(host(resid)[0], ref["resid"], rtol=1e-2)
+
+
+# ----------------------------------------------------------------------------- C3 and C5
+
+def test_c3_batch64_precision_modes(air, torch_mod, orc, record):
+    """64 seeded phantoms on the 128^2 parallel geometry in one batch: the ramp and
+    A'^T per image in each precision mode, and final images of a subset."""
+    from synth.phantom import batch_cases
+    w = synth.workload("c3")
+    _, ys = batch_cases(w, range(w.batch))
+    ys = ys.astype(np.float32)
+    G = orc.Geom(w.geom)
+    ref_c = [orc.ramp(G, y.astype(np.float64)) for y in ys]
+    ref_atc = [orc.filtered_backproject(G, y.astype(np.float64), 1) for y in ys]
+    sub = range(0, 64, 8)
+    ref_x = {i: orc.solve(G, ys[i].astype(np.float64), w.lam, w.mu, w.n_outer, w.n_cg)[0] for i in sub}
+    Y = dev(torch_mod, ys)
+    for prec, op_tol, final_tol in [("fp32", 1e-5, 1e-4), ("mixed_f16", 1e-5, 1e-3), ("mixed_bf16", 1e-5, 1e-3)]:
+        plan = air.Plan(w.geom, max_batch=64, precision=prec)
+        yf = host(plan.ramp(Y))
+        xf = host(plan.filtered_backproject(Y, 1))
+        ec = max(rel(yf[i], ref_c[i]) for i in range(64))
+        ea = max(rel(xf[i], ref_atc[i]) for i in range(64))
+        record(f"max_rel_l2_C_{prec}", ec)
+        record(f"max_rel_l2_AtC_{prec}", ea)
+        assert ec < op_tol and ea < op_tol, (prec, ec, ea)
+        x, _ = plan.solve(Y, w.lam, w.mu, w.n_outer, w.n_cg, with_resid=False)
+        x = host(x)
+        ef = max(rel(x[i], ref_x[i]) for i in sub)
+        record(f"max_rel_l2_final_{prec}", ef)
+        assert ef < final_tol, (prec, ef)
+
+
+@pytest.fixture(scope="module")
+def c5_case():
+    w = synth.workload("c5")
+    return w, synth.make_case(w, 0)
+
+
+def test_c5_operators_full_size(air, torch_mod, orc, record, c5_case):
+    """1024^2 fan beam, 2304 views x 1536 bins: A and A'^T of one phantom."""
+    w, case = c5_case
+    g = w.geom
+    plan = air.Plan(g, max_batch=1)
+    G = orc.Geom(g)
+    x = case["x_true"].astype(np.float32)
+    y = host(plan.project(dev(torch_mod, x[None])))[0]
+    e1 = rel(y, orc.project(G, x.astype(np.float64)))
+    y32 = case["y"].astype(np.float32)
+    xb = host(plan.filtered_backproject(dev(torch_mod, y32[None]), 1))[0]
+    e2 = rel(xb, orc.filtered_backproject(G, y32.astype(np.float64), 1))
+    record("rel_l2_A", e1)
+    record("rel_l2_AtC", e2)
+    assert e1 < 1e-5 and e2 < 1e-5, (e1, e2)
+
+
+def test_c5_solve_against_stored_oracle(air, torch_mod, record, c5_case):
+    """Two Bregman iterations (x 5 CG) of the 1024^2 case in a batch of two
+    against the oracle's reconstruction stored by tests/golden/make_refs.py."""
+    w, case = c5_case
+    ref = np.load(os.path.join(HERE, "golden", "c5_fan_1024_2304_seed0_outer2.npz"))
+    y = case["y"].astype(np.float32)
+    plan = air.Plan(w.geom)
+    Y = dev(torch_mod, np.stack([y, y[::-1].copy()]))
+    x, resid = plan.solve(Y, w.lam, w.mu, 2, w.n_cg)
+    e = rel(host(x)[0], ref["x"])
+    record("rel_l2_final", e)
+    assert e < 1e-4
+    np.testing.assert_allclose(host(resid)[0], ref["resid"], rtol=1e-2)

@@ -129,7 +129,7 @@ def test_calls_on_an_unbound_plan_fail_without_touching_the_gpu(air):
         s1, s3 = ctypes.c_size_t(), ctypes.c_size_t()
         assert air.lib.air_solve_workspace_size(h, 1, ctypes.byref(s1)) == air.AIR_OK
         assert air.lib.air_solve_workspace_size(h, 3, ctypes.byref(s3)) == air.AIR_OK
-        assert 2.9 * s1.value < s3.value < 3.1 * s1.value
+        assert s1.value < s3.value <= 3 * s1.value
         assert air.lib.air_solve_workspace_size(h, 0, ctypes.byref(s1)) == air.AIR_E_INVALID
     finally:
         air.lib.air_plan_destroy(h)
