@@ -52,6 +52,12 @@ def parse():
                     help="profiler runs only: Bregman iterations of the instrumented pass (0 = the workload's)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="profiler runs only: also run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--serve", action="store_true",
+                    help="run the continuous-batching serving benchmark instead (Poisson arrivals, mixed geometries)")
+    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-rate", type=float, default=40.0, help="offered load, requests per second")
+    ap.add_argument("--serve-capacity", type=int, default=8, help="slots per geometry group")
+    ap.add_argument("--serve-precision", default="mixed_f16", choices=["fp32", "mixed_f16", "mixed_bf16"])
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into profiles/traffic_c2.json")
     return ap.parse_args()
@@ -141,8 +147,71 @@ def summarize_pmc(fetch_dir: str, write_dir: str, batch: int):
     print(json.dumps(out, indent=1))
 
 
+def serving_workload(n_requests: int, rate: float, seed: int = 0):
+    """The serving mix: image size uniform over {256, 512, 768} (0.78 mm pixels,
+    1.4375 n bins of 1.2 mm), views uniform over {180, 360, 720, 1440} over 2 pi,
+    100% or 25% of them, I0 ~ U[1e4, 1e5], Bregman iterations uniform in [20, 50],
+    Poisson arrivals.  One 20-ellipse phantom per (size, views) scan (its exact
+    line integrals computed once); each request draws its own Poisson noise."""
+    import synth
+    from synth.configs import Workload, serving_geometry
+    from synth.phantom import draw_phantom, line_integrals
+    from paper_1310_1434_amd.serve import Request, poisson_arrivals
+
+    rng = np.random.default_rng(seed)
+    arrivals = poisson_arrivals(rate, n_requests, seed)
+    scans = {}
+    reqs = []
+    for i in range(n_requests):
+        n = int(rng.choice([256, 512, 768]))
+        views = int(rng.choice([180, 360, 720, 1440]))
+        step = int(rng.choice([1, 4]))
+        i0 = float(rng.uniform(1e4, 1e5))
+        n_outer = int(rng.integers(20, 51))
+        if (n, views) not in scans:
+            full = serving_geometry(n, views)
+            w = Workload(f"serve_{n}_{views}", full, disk_radius=190.0 * n / 512.0, n_ellipses=20, i0=i0)
+            ell = draw_phantom(np.random.default_rng(1000 + len(scans)), w)
+            scans[(n, views)] = line_integrals(ell, full)
+        p = scans[(n, views)][::step]
+        y = synth.noisy_sinogram(rng, p, i0).astype(np.float32)
+        reqs.append(Request(i, serving_geometry(n, views, step), np.ascontiguousarray(y), n_outer,
+                            arrival=float(arrivals[i])))
+    return reqs
+
+
+def serve_bench(a):
+    import torch
+    from paper_1310_1434_amd.serve import GpuExecutor, Server, geometry_key, latency_stats
+
+    reqs = serving_workload(a.serve_requests, a.serve_rate)
+    ex = GpuExecutor(lam=0.005, mu=1.0, n_cg=5, max_outer=50, capacity=a.serve_capacity,
+                     precision=a.serve_precision)
+    for r in reqs:                    # ray tables are built before the clock starts
+        ex.plan(geometry_key(r.geom), r.geom)
+    free, _ = torch.cuda.mem_get_info()
+    srv = Server(ex, int(0.8 * free), a.serve_capacity)
+    t = time.perf_counter()
+    done = srv.run(reqs)
+    wall = time.perf_counter() - t
+    ok = [r for r in done if r.error is None]
+    st = latency_stats(done)
+    return {"requests": len(reqs), "offered_rate_per_s": a.serve_rate, "completed": len(ok),
+            "failed": len(done) - len(ok), "recon_per_s": len(ok) / wall, "wall_s": wall,
+            "p50_latency_s": st.get("p50_s"), "p99_latency_s": st.get("p99_s"), "max_latency_s": st.get("max_s"),
+            "geometry_groups": len({geometry_key(r.geom) for r in reqs}), "slots_per_group": a.serve_capacity,
+            "precision": a.serve_precision, "steps": srv.steps,
+            "mean_bregman_iterations": float(np.mean([r.n_outer for r in reqs]))}
+
+
 def main():
     a = parse()
+    if a.serve:
+        if a.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({"serving": serve_bench(a)}), flush=True)
+        return
     if a.summarize_pmc:
         summarize_pmc(a.summarize_pmc[0], a.summarize_pmc[1], a.batch)
         return

@@ -206,6 +206,10 @@ air_status air_state_admit(air_state st, const float* Y, const float* X0, int32_
         const hipError_t h = launch_fill(b.X, n, 0.f, s);
         if (h != hipSuccess) e = fail(AIR_E_HIP, std::string("admit: ") + hipGetErrorString(h));
     }
+    if (e == AIR_OK) {   // residual history starts at zero (deterministic snapshots)
+        const hipError_t h = launch_fill(reinterpret_cast<float*>(b.resid), 2 * (size_t)st->max_outer, 0.f, s);
+        if (h != hipSuccess) e = fail(AIR_E_HIP, std::string("admit: ") + hipGetErrorString(h));
+    }
     if (e == AIR_OK) e = solve_init(p, b, Y, 1, st->setup, s);
     if (e != AIR_OK) {     // give the position back
         st->pos_of[slot] = -1;

@@ -1,0 +1,293 @@
+"""Continuous-batching reconstruction server over the solve slots.
+
+Requests (a sinogram, its scan geometry and a Bregman iteration count) are
+grouped by geometry; each group owns one plan, one slot state and one HIP
+stream, so groups run concurrently on the device.  The loop, repeated until
+every request is done:
+
+  1. retire: in every group whose last step has completed, slots that reached
+     their iteration count are copied out and freed;
+  2. admit: pending requests that have arrived are admitted first come, first
+     served into a free slot of their group; a group is opened when the HBM
+     budget allows (idle empty groups are closed to make room); a request whose
+     group could never fit the budget is rejected;
+  3. step: every group with active slots whose previous step has completed
+     advances one Bregman iteration (one replay of its captured graph).
+
+So a request that arrives while others are on the GPU joins at the next step
+of its group, and finished ones leave without waiting for the rest.  The
+executor abstraction lets the same scheduler run on the GPU (GpuExecutor) or
+on a simulated clock (tests).
+"""
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+import time
+from collections import deque
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    geom: object                  # scan geometry (beam, n, pixel, n_views, n_bins, bin, sod, sdd, view_cos, view_sin)
+    y: np.ndarray                 # [n_views, n_bins] float32 sinogram (host)
+    n_outer: int
+    arrival: float = 0.0          # seconds from the start of the run
+    admitted: float | None = None
+    finished: float | None = None
+    x: np.ndarray | None = None   # result image (GpuExecutor)
+    resid: np.ndarray | None = None
+    error: str | None = None
+
+    @property
+    def latency(self) -> float | None:
+        return None if self.finished is None else self.finished - self.arrival
+
+
+def geometry_key(g) -> tuple:
+    angles = np.concatenate([np.asarray(g.view_cos, np.float64), np.asarray(g.view_sin, np.float64)])
+    return (g.beam, int(g.n), float(g.pixel), int(g.n_views), int(g.n_bins), float(g.bin),
+            float(getattr(g, "sod", 0.0)), float(getattr(g, "sdd", 0.0)),
+            hashlib.sha1(angles.tobytes()).hexdigest())
+
+
+class Group:
+    def __init__(self, key, geom, capacity: int, nbytes: int):
+        self.key = key
+        self.geom = geom
+        self.capacity = capacity
+        self.nbytes = nbytes
+        self.slots: dict[int, Request] = {}     # slot -> request
+        self.impl = None                        # executor-specific
+
+
+class GpuExecutor:
+    """Groups on the GPU: a Plan, a State of `capacity` slots and a stream each."""
+
+    def __init__(self, lam: float, mu: float, n_cg: int, max_outer: int, capacity: int,
+                 precision: str = "fp32", device: str = "cuda:0"):
+        import torch
+        from . import air
+        self.torch, self.air = torch, air
+        self.lam, self.mu, self.n_cg, self.max_outer = lam, mu, n_cg, max_outer
+        self.capacity, self.precision, self.device = capacity, precision, device
+        self._plans = {}
+
+    def plan(self, key, geom):
+        if key not in self._plans:
+            self._plans[key] = self.air.Plan(geom, max_batch=1, precision=self.precision, device=self.device)
+        return self._plans[key]
+
+    def group_bytes(self, key, geom) -> int:
+        """Device bytes of a group: its slot state plus its plan's tables and scratch."""
+        import ctypes
+        p = self.plan(key, geom)
+        prm = self.air._SolveParams(self.lam, self.mu, self.max_outer, self.n_cg, 0, 1)
+        size = ctypes.c_size_t()
+        self.air._check(self.air.lib.air_state_workspace_size(p._h, self.capacity, ctypes.byref(prm),
+                                                               ctypes.byref(size)), "air_state_workspace_size")
+        return int(size.value) + p._ws.numel()
+
+    def open(self, group: Group):
+        stream = self.torch.cuda.Stream(device=self.device)
+        state = self.air.State(self.plan(group.key, group.geom), self.capacity, self.lam, self.mu, self.n_cg,
+                               self.max_outer, stream=stream)
+        group.impl = {"state": state, "stream": stream, "event": None}
+
+    def close(self, group: Group):
+        group.impl["stream"].synchronize()
+        group.impl = None
+
+    def admit(self, group: Group, req: Request) -> int:
+        st = group.impl["state"]
+        with self.torch.cuda.stream(group.impl["stream"]):
+            y = self.torch.from_numpy(np.ascontiguousarray(req.y, np.float32)).to(self.device, non_blocking=False)
+            return st.admit(y, n_outer=req.n_outer)
+
+    def idle(self, group: Group) -> bool:
+        ev = group.impl["event"]
+        return ev is None or ev.query()
+
+    def step(self, group: Group) -> int:
+        k = group.impl["state"].step(1)
+        ev = self.torch.cuda.Event()
+        ev.record(group.impl["stream"])
+        group.impl["event"] = ev
+        return k
+
+    def progress(self, group: Group, slot: int) -> tuple[int, int]:
+        return group.impl["state"].query(slot)
+
+    def retire(self, group: Group, slot: int, req: Request):
+        x, r = group.impl["state"].retire(slot)
+        group.impl["stream"].synchronize()
+        req.x = x.cpu().numpy()
+        req.resid = r.cpu().numpy()
+        if not np.isfinite(req.resid).all():
+            req.error = "non-finite residual"
+
+
+class Server:
+    def __init__(self, executor, hbm_budget: int, capacity: int, clock=time.perf_counter, sleep=time.sleep):
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.capacity = capacity
+        self.clock, self.sleep = clock, sleep
+        self.groups: dict[tuple, Group] = {}
+        self.pending: deque[Request] = deque()
+        self.done: list[Request] = []
+        self.used = 0
+        self.steps = 0
+
+    # ---------------------------------------------------------------- helpers
+    def _open(self, key, geom) -> Group | None:
+        nbytes = self.ex.group_bytes(key, geom)
+        if nbytes > self.budget:
+            return None
+        while self.used + nbytes > self.budget:
+            idle = [g for g in self.groups.values() if not g.slots and self.ex.idle(g)]
+            if not idle:
+                return None
+            self._close(idle[0])
+        g = Group(key, geom, self.capacity, nbytes)
+        self.ex.open(g)
+        self.groups[key] = g
+        self.used += nbytes
+        return g
+
+    def _close(self, g: Group):
+        self.ex.close(g)
+        self.used -= g.nbytes
+        del self.groups[g.key]
+
+    # ---------------------------------------------------------------- one pass
+    def poll(self, now: float) -> bool:
+        busy = False
+        # 1. retire finished slots of groups whose last step completed
+        for g in list(self.groups.values()):
+            if not g.slots or not self.ex.idle(g):
+                continue
+            for slot, req in list(g.slots.items()):
+                it, n_outer = self.ex.progress(g, slot)
+                if it >= n_outer:
+                    self.ex.retire(g, slot, req)
+                    req.finished = self.clock() - self._t0
+                    del g.slots[slot]
+                    self.done.append(req)
+                    busy = True
+        # 2. admit arrived requests, first come first served within each group
+        blocked = set()
+        for req in list(self.pending):
+            if req.arrival > now:
+                break
+            key = geometry_key(req.geom)
+            if key in blocked:
+                continue
+            g = self.groups.get(key)
+            if g is None:
+                if self.ex.group_bytes(key, req.geom) > self.budget:
+                    req.error = "does not fit the HBM budget"
+                    self.pending.remove(req)
+                    self.done.append(req)
+                    continue
+                g = self._open(key, req.geom)
+                if g is None:
+                    blocked.add(key)
+                    continue
+            if len(g.slots) >= g.capacity:
+                blocked.add(key)
+                continue
+            slot = self.ex.admit(g, req)
+            req.admitted = now
+            g.slots[slot] = req
+            self.pending.remove(req)
+            busy = True
+        # 3. step every group with work whose previous step completed
+        for g in self.groups.values():
+            if g.slots and self.ex.idle(g):
+                self.ex.step(g)
+                self.steps += 1
+                busy = True
+        return busy
+
+    def run(self, requests: list[Request], idle_sleep: float = 2e-4) -> list[Request]:
+        """Serve `requests` (arrival times relative to the start); returns them when all are done."""
+        self.pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+        self.done = []
+        self._t0 = self.clock()
+        total = len(requests)
+        while len(self.done) < total:
+            now = self.clock() - self._t0
+            if not self.poll(now):
+                self.sleep(idle_sleep)
+        return sorted(self.done, key=lambda r: r.rid)
+
+
+class FakeExecutor:
+    """Simulated executor for scheduler tests: a step of a group with k active
+    slots takes step_cost(group, k) seconds of a simulated clock."""
+
+    def __init__(self, bytes_per_group, step_cost):
+        self.bytes_per_group = bytes_per_group
+        self.step_cost = step_cost
+        self.now = 0.0
+        self.opened = []
+        self.log = []
+
+    def clock(self):
+        return self.now
+
+    def sleep(self, dt):
+        self.now += dt
+
+    def group_bytes(self, key, geom):
+        return self.bytes_per_group(geom)
+
+    def open(self, g):
+        g.impl = {"busy_until": 0.0, "iters": {}, "next": 0}
+        self.opened.append(g.key)
+
+    def close(self, g):
+        self.log.append(("close", g.key))
+        g.impl = None
+
+    def admit(self, g, req):
+        slot = g.impl["next"]
+        g.impl["next"] += 1
+        g.impl["iters"][slot] = [0, req.n_outer]
+        self.log.append(("admit", req.rid, self.now))
+        return slot
+
+    def idle(self, g):
+        return self.now >= g.impl["busy_until"]
+
+    def step(self, g):
+        k = len(g.slots)
+        for slot in g.slots:
+            g.impl["iters"][slot][0] += 1
+        g.impl["busy_until"] = self.now + self.step_cost(g, k)
+        return 1
+
+    def progress(self, g, slot):
+        return tuple(g.impl["iters"][slot])
+
+    def retire(self, g, slot, req):
+        self.log.append(("retire", req.rid, self.now))
+        del g.impl["iters"][slot]
+
+
+def poisson_arrivals(rate: float, count: int, seed: int = 0) -> np.ndarray:
+    """Arrival times (s) of a seeded Poisson process of `rate` requests per second."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
+def latency_stats(reqs: list[Request]) -> dict:
+    lat = np.array([r.latency for r in reqs if r.latency is not None and r.error is None])
+    if lat.size == 0:
+        return {"count": 0}
+    return {"count": int(lat.size), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "max_s": float(lat.max())}
