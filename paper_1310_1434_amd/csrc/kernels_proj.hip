@@ -55,8 +55,8 @@ hipError_t launch_pad(const KGeom& g, const float* x, PadBuf pad, int batch, hip
 //   T = tc + (a - c0) m (fixed point), j = T >> kFrac, f = frac(T) as float32,
 // L_a the padded line a of image b.  Bins k in [n_bins, ds) are written as zero.
 // The driving index runs over the union of the wavefront's ranges, so at every
-// step all lanes of one axis read the same image line (coalesced gathers);
-// lanes outside their own [lo, hi] sit the step out.
+// step all lanes of one axis read the same image line (coalesced gathers); a
+// lane outside its own range samples the zero padding.
 constexpr int kProjBlock = 256;
 
 __device__ __forceinline__ int wave_min_i(int v) {
@@ -74,10 +74,17 @@ __device__ __forceinline__ int wave_max_i(int v) {
 static_assert(kFrac == 32 && kSlopeFrac == 31, "fixed-point layout");
 __device__ __forceinline__ int fx_index(int64_t t) { return (int)(t >> 32); }
 __device__ __forceinline__ float fx_frac(int64_t t) { return (float)(uint32_t)t * 0x1p-32f; }
-// intercept at driving index a: tc + (a - c0) * 2m
+// intercept at driving index a: tc + 2 (a - c0) m, as one 32x32->64 multiply and one shift-add
 __device__ __forceinline__ int64_t fx_at(const RayEntry& e, int a_minus_c0) {
-    return e.tc + ((int64_t)a_minus_c0 * (int64_t)e.m) * 2;
+    int64_t prod = (int64_t)a_minus_c0 * (int64_t)e.m;
+    asm volatile("" : "+v"(prod));      // keep the product 32x32 (no reassociation with the shift)
+    return e.tc + prod * 2;
 }
+
+// Index of the first of the two samples in a padded line of n + 4: clamping
+// into [0, n + 2] only ever moves samples onto the zero padding, so an
+// out-of-range step contributes exactly zero (no range test needed).
+__device__ __forceinline__ int fx_clamped_index(int64_t t, int n) { return min(max(fx_index(t), 0), n + 2); }
 
 template <bool SCALED>
 __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __restrict__ pad,
@@ -95,25 +102,22 @@ __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __
     const int lo = hits ? ray_lo(e.meta) : 0x7fffffff;    // misses do not widen the wave's range
     const int hi = hits ? ray_hi(e.meta) : -1;
     const int axis = ray_axis(e.meta);
-    const int a_lo = __builtin_amdgcn_readfirstlane(wave_min_i(lo));
-    const int a_hi = __builtin_amdgcn_readfirstlane(wave_max_i(hi));
+    // The union of the wave's ranges, one step wider on each side (the float64
+    // range test and the fixed-point intercept may disagree at the very edge).
+    const int a_lo = max(0, __builtin_amdgcn_readfirstlane(wave_min_i(lo)) - 1);
+    const int a_hi = min(g.n - 1, __builtin_amdgcn_readfirstlane(wave_max_i(hi)) + 1);
     const int line = g.line;
     const float* lines = pad + ((size_t)b * 2 + axis) * g.n * line;
     float acc = 0.f;
     int64_t t = fx_at(e, a_lo - g.c0);
     const int64_t m = (int64_t)e.m * 2;
     uint32_t row = (uint32_t)(a_lo * line);
-    // Branch-free steps (a lane outside its range reads element 0 of its image
-    // with zero weights), so that several gathers are in flight per wave.
 #pragma unroll 4
     for (int a = a_lo; a <= a_hi; a++, t += m, row += line) {
-        const bool act = a >= lo && a <= hi;
         const float f = fx_frac(t);
-        const float w1 = act ? f : 0.f;
-        const float w0 = act ? 1.f - f : 0.f;
-        const float* p = lines + (act ? row + (uint32_t)fx_index(t) : 0u);
-        acc = fmaf(w0, p[0], acc);
-        acc = fmaf(w1, p[1], acc);
+        const float* p = lines + row + fx_clamped_index(t, g.n);
+        acc = fmaf(1.f - f, p[0], acc);
+        acc = fmaf(f, p[1], acc);
     }
     if (k >= g.ds) return;
     float out = 0.f;
@@ -187,8 +191,9 @@ __device__ __forceinline__ float joseph_weight(const RayEntry& e, int i, int j, 
     const int64_t t = fx_at(e, da - c0);
     const float f = fx_frac(t);
     const int j0 = fx_index(t) - kPad;
-    const float w = (ob == j0) ? (1.f - f) : ((ob == j0 + 1) ? f : 0.f);
-    return (da >= ray_lo(e.meta) && da <= ray_hi(e.meta)) ? w : 0.f;
+    // ob in {j0, j0 + 1} implies -1 <= t < n: exactly the samples the forward
+    // projector takes with non-zero weight, so no range test is needed
+    return (ob == j0) ? (1.f - f) : ((ob == j0 + 1) ? f : 0.f);
 }
 
 // BT contiguous floats, aligned to min(4 BT, 16) bytes.
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                 load_group<BT>(yv + (size_t)k * bs, yv0);
                 load_group<BT>(yv + (size_t)k1 * bs, yv1);
                 const float w0 = joseph_weight(e0, i, j, g.c0);
-                const float w1 = two ? joseph_weight(e1, i, j, g.c0) : 0.f;
+                const float w1 = joseph_weight(e1, i, j, g.c0) * (two ? 1.f : 0.f);
 #pragma unroll
                 for (int q = 0; q < BT; q++) part[q] = fmaf(w1, yv1[q], fmaf(w0, yv0[q], part[q]));
             }
