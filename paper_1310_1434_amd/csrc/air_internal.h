@@ -34,25 +34,36 @@ struct KGeom {
     const float2* views;    // [n_views] (cos, sin) as float
 };
 
-// Per-launch description of where an image batch and its padded copies live.
+// Images are processed in groups of image_group(batch) in {1, 2, 4, 8}: the
+// group a backprojector thread serves.  The choice minimises
+// ceil(batch / G) * (2 + G), i.e. it shares the per-sample index work over as
+// many images as possible without too many idle lanes in the last group.
+int image_group(int batch);
+// Padded image copies of a batch, image-interleaved in pairs:
+// [ceil(batch / P)][2][n][line][P] with P = pad_group(batch) (1 for a single
+// image, else 2; P divides image_group(batch)); line set 0 = columns (for
+// x-driven rays), 1 = rows.  A lane of the last pair beyond the batch holds
+// zeros.  A pair keeps the projector's gathers at 16 bytes while the working
+// set of one pair of 512^2 images (4 MB) still fits an XCD's L2.
+int pad_group(int batch);
 struct PadBuf {
-    float* base;    // [batch][2][n][line]: line set 0 = columns (for x-driven rays), 1 = rows
+    float* base;
 };
 
 // ---- kernel launchers (kernels_*.hip) -------------------------------------------------
 hipError_t launch_pad(const KGeom& g, const float* x, PadBuf pad, int batch, hipStream_t s);
 // y = J x (scaled = false: bare interpolation weights) or y = A x = S J x (scaled = true).
 hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, bool scaled, hipStream_t s);
-// Backprojector input layout: batch-interleaved rows [n_views][ds][bs] with
-// bs = bp_batch_stride(batch) >= batch, so that the images a backprojector
-// thread serves are contiguous.
-int bp_batch_stride(int batch);
-// out (interleaved, stride bs) = y (rows [batch * n_views][ds]) * step^power (power 1 or 2).
-hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, int power, int bs, hipStream_t s);
+// Backprojector input layout: group-interleaved [ceil(batch / G)][n_views][ds][G]
+// with G = image_group(batch), so that the images a backprojector thread serves
+// are contiguous and each group is one dense block.  Lanes of the last group
+// beyond the batch are never written (and their results never stored).
+// out (group-interleaved, G = grp) = y (rows [batch * n_views][ds]) * step^power (power 1 or 2).
+hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, int power, int grp, hipStream_t s);
 
 // Backprojection epilogue modes (per pixel, acc = (J^T y)_pixel, J the bare
 // interpolation weights; callers fold the path lengths into y, which is in the
-// batch-interleaved layout of stride bp_batch_stride(batch)):
+// group-interleaved layout with G = image_group(batch)):
 enum BpMode {
     BP_PLAIN = 0,     // out = acc
     BP_MATVEC = 1,    // out = acc + mu * p;  partial sums of p . out (float64)
@@ -87,23 +98,23 @@ struct RampTables {
     float out_scale;           // kappa * 2^-12 for the 16-bit modes
 };
 // scale: 0 = C y;  RAMP_POST = S C y;  RAMP_PRE | RAMP_POST = S C S y  (S = diag(step)).
-// Input rows [batch * n_views][ds].  Output: the same layout when bs == 0, else
-// batch-interleaved [n_views][ds][bs] (the backprojector's input).
+// Input rows [batch * n_views][ds].  Output: the same layout when grp == 0, else
+// group-interleaved with G = grp (the backprojector's input).
 enum { RAMP_PRE = 1, RAMP_POST = 2 };
 hipError_t launch_ramp(int prec, const RampTables& t, const float* y, float* yf, int rows, int ds, int scale,
-                       int bs, hipStream_t s);
+                       int grp, hipStream_t s);
 
 // CG vector updates on 16x16 tiles (float32 vectors, float64 scalars).
 struct CgArgs {
     int n;
     float* x; float* r; float* p; const float* q;
-    PadBuf pad;                 // padded copy target (x or p), or base = null
+    PadBuf pad;                 // padded copy of p (update_p)
     const double* alpha;        // [batch] (update_xr)
     const double* beta;         // [batch] (update_p)
     double* partial;            // [batch][tiles16(n)] partial sums of r . r (update_xr)
 };
 hipError_t launch_cg_update_xr(const CgArgs& a, int batch, hipStream_t s);   // x += a p, r -= a q; partials of r.r
-hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s);    // p = r + b p (+ pad)
+hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s);    // p = r + b p, and its pad
 
 // Fixed-order sums of the block partials [batch][nblk] and the scalars derived from them:
 enum FinalizeMode {

@@ -187,7 +187,7 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
         p->off_taps = c.take(p->taps32.size() * sizeof(float));
         for (int t = 0; t < p->n_terms; t++) p->off_frag[t] = c.take(p->frag[t].size() * sizeof(uint16_t));
         const size_t mb = (size_t)max_batch;
-        p->off_pad = c.take(mb * 2 * g.n * p->line * sizeof(float));
+        p->off_pad = c.take((mb + 7) / 8 * 8 * 2 * g.n * p->line * sizeof(float));   // grouped padded copies
         p->off_s1 = c.take(mb * g.n_views * ds * sizeof(float));
         p->off_s2 = c.take((mb + 7) / 8 * 8 * g.n_views * ds * sizeof(float));   // interleaved, stride <= roundup(batch, 8)
         p->total = c.off;
@@ -284,10 +284,10 @@ air_status air_filtered_backproject(air_plan p, const float* y, float* x, int32_
     const float* src = nullptr;
     if (air_status st = stage_sino(p, y, batch, p->at<float>(p->off_s1), &src, s)) return st;
     float* s2 = p->at<float>(p->off_s2);
-    const int bs = bp_batch_stride(batch);
+    const int grp = image_group(batch);
     if (filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, s2, batch * p->g.n_views, p->ds,
-                                              RAMP_POST, bs, s));
-    else AIR_K(AIR_K_OTHER, launch_scale(p->kgeom(), src, s2, batch, 1, bs, s));
+                                              RAMP_POST, grp, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(p->kgeom(), src, s2, batch, 1, grp, s));
     BpArgs a{};
     a.mode = BP_PLAIN;
     a.out = x;
@@ -310,10 +310,10 @@ air_status air_normal_apply(air_plan p, const float* x, float* out, int32_t batc
     // A^T C A x = J^T (S C S) J x;  A^T A x = J^T S^2 J x
     AIR_K(AIR_K_OTHER, launch_pad(kg, x, pad, batch, s));
     AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, false, s));
-    const int bs = bp_batch_stride(batch);
+    const int grp = image_group(batch);
     if (filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), s1, s2, batch * p->g.n_views, p->ds,
-                                              RAMP_PRE | RAMP_POST, bs, s));
-    else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 2, bs, s));
+                                              RAMP_PRE | RAMP_POST, grp, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 2, grp, s));
     const float* src = s2;
     BpArgs a{};
     a.mode = BP_MATVEC;

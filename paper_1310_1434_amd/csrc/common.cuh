@@ -40,27 +40,84 @@ __device__ __forceinline__ void block_partial(double v, double* slot) {
     __syncthreads();
 }
 
-// Write one 16x16 tile of an image into its two padded line sets: rows (line
-// set 1, pad[j][kPad + i]) and columns (line set 0, pad[i][kPad + j]), plus the
-// zero samples at both ends of every line the tile touches at the border.
-// tile is 16 x 17 shared floats; all 256 threads of the block must call this.
-__device__ __forceinline__ void store_padded_tile(float* pad_b, int n, int line, int i0, int j0, int tx,
-                                                  int ty, float v, float (*tile)[17]) {
-    float* cols = pad_b;
-    float* rows = pad_b + (size_t)n * line;
-    const int i = i0 + tx, j = j0 + ty;
-    if (i < n && j < n) rows[(size_t)j * line + kPad + i] = v;
-    if (j < n && tx < kPad) {
-        if (i0 == 0) rows[(size_t)j * line + tx] = 0.f;
-        if (i0 + 16 >= n) rows[(size_t)j * line + kPad + n + tx] = 0.f;
+// G contiguous floats at p, aligned to min(4 G, 16) bytes.
+template <int G>
+__device__ __forceinline__ void load_group(const float* p, float (&v)[G]) {
+    if constexpr (G % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < G; q += 4) {
+            const float4 t = *reinterpret_cast<const float4*>(p + q);
+            v[q] = t.x; v[q + 1] = t.y; v[q + 2] = t.z; v[q + 3] = t.w;
+        }
+    } else if constexpr (G == 2) {
+        const float2 t = *reinterpret_cast<const float2*>(p);
+        v[0] = t.x; v[1] = t.y;
+    } else {
+#pragma unroll
+        for (int q = 0; q < G; q++) v[q] = p[q];
     }
-    tile[ty][tx] = v;
+}
+template <int G>
+__device__ __forceinline__ void store_group(float* p, const float (&v)[G]) {
+    if constexpr (G % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < G; q += 4) *reinterpret_cast<float4*>(p + q) = make_float4(v[q], v[q + 1], v[q + 2], v[q + 3]);
+    } else if constexpr (G == 2) {
+        *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < G; q++) p[q] = v[q];
+    }
+}
+template <int G>
+__device__ __forceinline__ void store_zero_group(float* p) {
+    float z[G];
+#pragma unroll
+    for (int q = 0; q < G; q++) z[q] = 0.f;
+    store_group<G>(p, z);
+}
+
+// Write one 16x16 tile of a group of G images into its padded line sets,
+// which hold the images in consecutive pairs (or singles) of P (see PadBuf;
+// pad points at the first of the G / P sub-groups): rows (line set 1,
+// [j][kPad + i][q]) and columns (line set 0, [i][kPad + j][q]), plus the zero
+// samples at both ends of every line the tile touches at the border.  The
+// column copy goes through shared memory so that both copies are written as
+// contiguous runs.  lds holds 16 * 17 * G floats; all 256 threads of the
+// block must call this.
+template <int G, int P>
+__device__ __forceinline__ void store_padded_group(float* pad, int n, int line, int i0, int j0, int tx, int ty,
+                                                   const float (&v)[G], float* lds) {
+    static_assert(G % P == 0, "sub-groups must tile the group");
+    const size_t sub = (size_t)2 * n * line * P;     // floats per sub-group
+    const int i = i0 + tx, j = j0 + ty;
+#pragma unroll
+    for (int s = 0; s < G / P; s++) {
+        float* rows = pad + s * sub + (size_t)n * line * P;
+        float u[P];
+#pragma unroll
+        for (int q = 0; q < P; q++) u[q] = v[s * P + q];
+        if (i < n && j < n) store_group<P>(rows + ((size_t)j * line + kPad + i) * P, u);
+        if (j < n && tx < kPad) {
+            if (i0 == 0) store_zero_group<P>(rows + ((size_t)j * line + tx) * P);
+            if (i0 + 16 >= n) store_zero_group<P>(rows + ((size_t)j * line + kPad + n + tx) * P);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < G; q++) lds[(ty * 17 + tx) * G + q] = v[q];
     __syncthreads();
     const int ic = i0 + ty, jc = j0 + tx;   // column line ic, sample jc
-    if (ic < n && jc < n) cols[(size_t)ic * line + kPad + jc] = tile[tx][ty];
-    if (ic < n && tx < kPad) {
-        if (j0 == 0) cols[(size_t)ic * line + tx] = 0.f;
-        if (j0 + 16 >= n) cols[(size_t)ic * line + kPad + n + tx] = 0.f;
+#pragma unroll
+    for (int s = 0; s < G / P; s++) {
+        float* cols = pad + s * sub;
+        float w[P];
+#pragma unroll
+        for (int q = 0; q < P; q++) w[q] = lds[(tx * 17 + ty) * G + s * P + q];
+        if (ic < n && jc < n) store_group<P>(cols + ((size_t)ic * line + kPad + jc) * P, w);
+        if (ic < n && tx < kPad) {
+            if (j0 == 0) store_zero_group<P>(cols + ((size_t)ic * line + tx) * P);
+            if (j0 + 16 >= n) store_zero_group<P>(cols + ((size_t)ic * line + kPad + n + tx) * P);
+        }
     }
 }
 

@@ -12,48 +12,46 @@ namespace air {
 
 // ---------------------------------------------------------------------------- CG
 // x += alpha p, r -= alpha q; partial sums of r . r.
-// When a.pad.base is set, x is also written to its padded line sets.
 __global__ __launch_bounds__(256) void k_cg_xr(CgArgs a) {
-    __shared__ float tile[16][17];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16, b = blockIdx.z;
     const int n = a.n, i = i0 + tx, j = j0 + ty;
-    const bool valid = i < n && j < n;
     const double alpha = a.alpha[b];
     const size_t idx = (size_t)b * n * n + (size_t)j * n + i;
     double part = 0.0;
-    float xn = 0.f;
-    if (valid) {
-        xn = (float)fma(alpha, (double)a.p[idx], (double)a.x[idx]);
+    if (i < n && j < n) {
+        const float xn = (float)fma(alpha, (double)a.p[idx], (double)a.x[idx]);
         const float rn = (float)fma(-alpha, (double)a.q[idx], (double)a.r[idx]);
         a.x[idx] = xn;
         a.r[idx] = rn;
         part = (double)rn * (double)rn;
     }
-    if (a.pad.base) {
-        const int line = n + 2 * kPad;
-        store_padded_tile(a.pad.base + (size_t)b * 2 * n * line, n, line, i0, j0, tx, ty, xn, tile);
-    }
     const int nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
     block_partial<256>(part, a.partial + (size_t)b * nblk + blk);
 }
 
-// p = r + beta p; p also goes to its padded line sets.
-__global__ __launch_bounds__(256) void k_cg_p(CgArgs a) {
-    __shared__ float tile[16][17];
+// p = r + beta p for a group of G images; p also goes to its padded line sets.
+template <int G>
+__global__ __launch_bounds__(256) void k_cg_p(CgArgs a, int batch) {
+    __shared__ float lds[16 * 17 * G];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16, b = blockIdx.z;
+    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16, b0 = blockIdx.z * G;
     const int n = a.n, i = i0 + tx, j = j0 + ty;
     const bool valid = i < n && j < n;
-    const double beta = a.beta[b];
-    const size_t idx = (size_t)b * n * n + (size_t)j * n + i;
-    float pn = 0.f;
-    if (valid) {
-        pn = (float)fma(beta, (double)a.p[idx], (double)a.r[idx]);
-        a.p[idx] = pn;
+    float pn[G];
+#pragma unroll
+    for (int q = 0; q < G; q++) {
+        pn[q] = 0.f;
+        const int b = b0 + q;
+        if (valid && b < batch) {
+            const size_t idx = (size_t)b * n * n + (size_t)j * n + i;
+            pn[q] = (float)fma(a.beta[b], (double)a.p[idx], (double)a.r[idx]);
+            a.p[idx] = pn[q];
+        }
     }
     const int line = n + 2 * kPad;
-    store_padded_tile(a.pad.base + (size_t)b * 2 * n * line, n, line, i0, j0, tx, ty, pn, tile);
+    constexpr int P = G < 2 ? G : 2;    // pad_group(batch)
+    store_padded_group<G, P>(a.pad.base + (size_t)b0 * 2 * n * line, n, line, i0, j0, tx, ty, pn, lds);
 }
 
 hipError_t launch_cg_update_xr(const CgArgs& a, int batch, hipStream_t s) {
@@ -63,8 +61,12 @@ hipError_t launch_cg_update_xr(const CgArgs& a, int batch, hipStream_t s) {
 }
 
 hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s) {
-    dim3 grid((a.n + 15) / 16, (a.n + 15) / 16, batch);
-    hipLaunchKernelGGL(k_cg_p, grid, dim3(256), 0, s, a);
+    const int grp = image_group(batch);
+    dim3 grid((a.n + 15) / 16, (a.n + 15) / 16, (batch + grp - 1) / grp), block(256);
+    if (grp == 8) hipLaunchKernelGGL(k_cg_p<8>, grid, block, 0, s, a, batch);
+    else if (grp == 4) hipLaunchKernelGGL(k_cg_p<4>, grid, block, 0, s, a, batch);
+    else if (grp == 2) hipLaunchKernelGGL(k_cg_p<2>, grid, block, 0, s, a, batch);
+    else hipLaunchKernelGGL(k_cg_p<1>, grid, block, 0, s, a, batch);
     return hipGetLastError();
 }
 

@@ -4,59 +4,63 @@
 // Memory layout the projector samples from: every image is kept twice, as
 // padded column lines (for x-driven rays, which step over columns and
 // interpolate between rows) and padded row lines (for y-driven rays), each
-// line with two zero samples at both ends.  A wavefront holds 64 neighbouring
+// line with two zero samples at both ends, and the images of a group
+// interleaved sample by sample (PadBuf).  A wavefront holds 64 neighbouring
 // detector bins of one view; at each driving step they all read the same line
-// at nearby positions, so the gathers are coalesced and no bounds test is
-// needed in the inner loop.
+// at nearby positions, so the gathers are coalesced, one gather serves every
+// image of the group, and no bounds test is needed in the inner loop.
 #include "common.cuh"
 
 namespace air {
 
+// ---------------------------------------------------------------------------- image groups
+int image_group(int batch) {
+    if (batch <= 1) return 1;
+    int best = 1, best_cost = batch * 3;
+    for (int g : {2, 4, 8}) {
+        const int cost = (batch + g - 1) / g * (2 + g);
+        if (cost < best_cost) {
+            best = g;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
+int pad_group(int batch) { return batch >= 2 ? 2 : 1; }
+
 // ---------------------------------------------------------------------------- padded copies
-__global__ __launch_bounds__(256) void k_pad(const float* __restrict__ x, float* __restrict__ pad, int n,
-                                             int line) {
-    __shared__ float tile[32][33];
-    const int b = blockIdx.z;
-    const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
-    const int tx = threadIdx.x, ty = threadIdx.y;   // 32 x 8
-    const float* xb = x + (size_t)b * n * n;
-    float* cols = pad + (size_t)b * 2 * n * line;
-    float* rows = cols + (size_t)n * line;
-    for (int r = ty; r < 32; r += 8) {
-        const int j = j0 + r, i = i0 + tx;
-        const float v = (j < n && i < n) ? xb[(size_t)j * n + i] : 0.f;
-        tile[r][tx] = v;
-        if (j < n && i < n) rows[(size_t)j * line + kPad + i] = v;
-        if (j < n && tx < kPad) {
-            if (i0 == 0) rows[(size_t)j * line + tx] = 0.f;
-            if (i0 + 32 >= n) rows[(size_t)j * line + kPad + n + tx] = 0.f;
-        }
-    }
-    __syncthreads();
-    for (int r = ty; r < 32; r += 8) {
-        const int i = i0 + r, j = j0 + tx;
-        if (i < n && j < n) cols[(size_t)i * line + kPad + j] = tile[tx][r];
-        if (i < n && tx < kPad) {
-            if (j0 == 0) cols[(size_t)i * line + tx] = 0.f;
-            if (j0 + 32 >= n) cols[(size_t)i * line + kPad + n + tx] = 0.f;
-        }
-    }
+template <int P>
+__global__ __launch_bounds__(256) void k_pad(const float* __restrict__ x, float* __restrict__ pad, int n, int line,
+                                             int batch) {
+    __shared__ float lds[16 * 17 * P];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16, b0 = blockIdx.z * P;
+    const int i = i0 + tx, j = j0 + ty;
+    float v[P];
+#pragma unroll
+    for (int q = 0; q < P; q++)
+        v[q] = (i < n && j < n && b0 + q < batch) ? x[((size_t)(b0 + q) * n + j) * n + i] : 0.f;
+    store_padded_group<P, P>(pad + (size_t)b0 * 2 * n * line, n, line, i0, j0, tx, ty, v, lds);
 }
 
 hipError_t launch_pad(const KGeom& g, const float* x, PadBuf pad, int batch, hipStream_t s) {
-    dim3 grid((g.n + 31) / 32, (g.n + 31) / 32, batch), block(32, 8);
-    hipLaunchKernelGGL(k_pad, grid, block, 0, s, x, pad.base, g.n, g.line);
+    const int pg = pad_group(batch);
+    dim3 grid((g.n + 15) / 16, (g.n + 15) / 16, (batch + pg - 1) / pg), block(256);
+    if (pg == 2) hipLaunchKernelGGL(k_pad<2>, grid, block, 0, s, x, pad.base, g.n, g.line, batch);
+    else hipLaunchKernelGGL(k_pad<1>, grid, block, 0, s, x, pad.base, g.n, g.line, batch);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------- forward A
-// One thread per ray.
+// One thread per ray and pair of images (PadBuf).
 //   y[b][v][k] = s * sum_{a=lo..hi} (1-f) L_a[j] + f L_a[j+1],
 //   T = tc + (a - c0) m (fixed point), j = T >> kFrac, f = frac(T) as float32,
 // L_a the padded line a of image b.  Bins k in [n_bins, ds) are written as zero.
 // The driving index runs over the union of the wavefront's ranges, so at every
 // step all lanes of one axis read the same image line (coalesced gathers); a
-// lane outside its own range samples the zero padding.
+// lane outside its own range samples the zero padding.  The two samples of
+// both images of a pair are 4 contiguous floats, read as one 16-byte load.
 constexpr int kProjBlock = 256;
 
 __device__ __forceinline__ int wave_min_i(int v) {
@@ -86,12 +90,16 @@ __device__ __forceinline__ int64_t fx_at(const RayEntry& e, int a_minus_c0) {
 // out-of-range step contributes exactly zero (no range test needed).
 __device__ __forceinline__ int fx_clamped_index(int64_t t, int n) { return min(max(fx_index(t), 0), n + 2); }
 
-template <bool SCALED>
+typedef float float2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+typedef float float4_a8 __attribute__((ext_vector_type(4), aligned(8)));
+
+template <bool SCALED, int P>
 __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __restrict__ pad,
                                                          float* __restrict__ y, int chunks, int batch) {
+    static_assert(P == 1 || P == 2, "images per thread");
     const int v = blockIdx.x / chunks;
     const int k = (blockIdx.x - v * chunks) * kProjBlock + threadIdx.x;
-    const int b = blockIdx.y;
+    const int b0 = blockIdx.y * P;
     const bool ray = k < g.n_bins;
     RayEntry e;
     e.tc = 0;
@@ -107,73 +115,75 @@ __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __
     const int a_lo = max(0, __builtin_amdgcn_readfirstlane(wave_min_i(lo)) - 1);
     const int a_hi = min(g.n - 1, __builtin_amdgcn_readfirstlane(wave_max_i(hi)) + 1);
     const int line = g.line;
-    const float* lines = pad + ((size_t)b * 2 + axis) * g.n * line;
-    float acc = 0.f;
+    const float* lines = pad + ((size_t)blockIdx.y * 2 + axis) * g.n * line * P;
+    float acc[P];
+#pragma unroll
+    for (int q = 0; q < P; q++) acc[q] = 0.f;
     int64_t t = fx_at(e, a_lo - g.c0);
     const int64_t m = (int64_t)e.m * 2;
     uint32_t row = (uint32_t)(a_lo * line);
 #pragma unroll 4
     for (int a = a_lo; a <= a_hi; a++, t += m, row += line) {
         const float f = fx_frac(t);
-        const float* p = lines + row + fx_clamped_index(t, g.n);
-        acc = fmaf(1.f - f, p[0], acc);
-        acc = fmaf(f, p[1], acc);
+        const float* p = lines + (size_t)((row + (uint32_t)fx_clamped_index(t, g.n)) * (uint32_t)P);
+        if constexpr (P == 1) {
+            const float2_a4 u = *reinterpret_cast<const float2_a4*>(p);
+            acc[0] = fmaf(1.f - f, u.x, acc[0]);
+            acc[0] = fmaf(f, u.y, acc[0]);
+        } else {
+            const float4_a8 u = *reinterpret_cast<const float4_a8*>(p);    // [j][0..1], [j + 1][0..1]
+            acc[0] = fmaf(1.f - f, u.x, acc[0]);
+            acc[0] = fmaf(f, u.z, acc[0]);
+            acc[1] = fmaf(1.f - f, u.y, acc[1]);
+            acc[1] = fmaf(f, u.w, acc[1]);
+        }
     }
     if (k >= g.ds) return;
-    float out = 0.f;
-    if (ray) out = SCALED ? acc * g.step[(size_t)v * g.ds + k] : acc;
-    y[((size_t)b * g.n_views + v) * g.ds + k] = out;
+    const float sv = (SCALED && ray) ? g.step[(size_t)v * g.ds + k] : 1.f;
+#pragma unroll
+    for (int q = 0; q < P; q++) {
+        if (b0 + q >= batch) break;
+        float out = 0.f;
+        if (ray) out = SCALED ? acc[q] * sv : acc[q];
+        y[((size_t)(b0 + q) * g.n_views + v) * g.ds + k] = out;
+    }
+}
+
+template <bool SCALED>
+static void launch_project_g(const KGeom& g, PadBuf pad, float* y, int batch, hipStream_t s) {
+    const int chunks = (g.ds + kProjBlock - 1) / kProjBlock;
+    const int pg = pad_group(batch);
+    dim3 grid(g.n_views * chunks, (batch + pg - 1) / pg), block(kProjBlock);
+    if (pg == 2) hipLaunchKernelGGL((k_project<SCALED, 2>), grid, block, 0, s, g, pad.base, y, chunks, batch);
+    else hipLaunchKernelGGL((k_project<SCALED, 1>), grid, block, 0, s, g, pad.base, y, chunks, batch);
 }
 
 hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, bool scaled, hipStream_t s) {
-    const int chunks = (g.ds + kProjBlock - 1) / kProjBlock;
-    dim3 grid(g.n_views * chunks, batch);
-    if (scaled) hipLaunchKernelGGL(k_project<true>, grid, dim3(kProjBlock), 0, s, g, pad.base, y, chunks, batch);
-    else hipLaunchKernelGGL(k_project<false>, grid, dim3(kProjBlock), 0, s, g, pad.base, y, chunks, batch);
+    if (scaled) launch_project_g<true>(g, pad, y, batch, s);
+    else launch_project_g<false>(g, pad, y, batch, s);
     return hipGetLastError();
 }
 
-// out[v][k][b] (stride bs) = y[b][v][k] * step[v][k]^power  (power 1: S y, power 2: S^2 y).
+// out[b / grp][v][k][b % grp] = y[b][v][k] * step[v][k]^power  (power 1: S y, power 2: S^2 y).
 __global__ __launch_bounds__(256) void k_scale(KGeom g, const float* __restrict__ y, float* __restrict__ out,
-                                               size_t count, int power, int bs) {
+                                               size_t count, int power, int grp) {
     const size_t per_batch = (size_t)g.n_views * g.ds;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) {
         const size_t b = i / per_batch, vk = i - b * per_batch;
         const float sv = g.step[vk];
-        out[vk * bs + b] = power == 2 ? y[i] * sv * sv : y[i] * sv;
+        const size_t gi = b / grp;
+        out[(gi * per_batch + vk) * grp + (b - gi * grp)] = power == 2 ? y[i] * sv * sv : y[i] * sv;
     }
 }
 
-hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, int power, int bs, hipStream_t s) {
+hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, int power, int grp, hipStream_t s) {
     const size_t count = (size_t)batch * g.n_views * g.ds;
     const size_t blocks = (count + 255) / 256 < 8192 ? (count + 255) / 256 : 8192;
-    hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, s, g, y, out, count, power, bs);
+    hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, s, g, y, out, count, power, grp);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------- adjoint J^T
-// Images per backprojector thread.  The detector window and the table reads
-// (about two thirds of the per-candidate work) are shared by the tile, so a
-// group of BT images costs roughly (2 + BT) units: pick the tile that
-// minimises ceil(batch / BT) * (2 + BT).
-static int batch_tile(int batch) {
-    if (batch <= 1) return 1;
-    int best = 1, best_cost = batch * 3;
-    for (int bt : {2, 4, 8}) {
-        const int cost = (batch + bt - 1) / bt * (2 + bt);
-        if (cost < best_cost) {
-            best = bt;
-            best_cost = cost;
-        }
-    }
-    return best;
-}
-
-int bp_batch_stride(int batch) {
-    const int bt = batch_tile(batch);
-    return (batch + bt - 1) / bt * bt;
-}
-
 // One thread per pixel and up to BT images, 16x16 pixels per block.  For every
 // view the pixel finds the bins whose rays can give it a non-zero Joseph
 // weight: the detector interval covered by the diamond |dx| + |dy| <= pixel
@@ -196,27 +206,9 @@ __device__ __forceinline__ float joseph_weight(const RayEntry& e, int i, int j, 
     return (ob == j0) ? (1.f - f) : ((ob == j0 + 1) ? f : 0.f);
 }
 
-// BT contiguous floats, aligned to min(4 BT, 16) bytes.
-template <int BT>
-__device__ __forceinline__ void load_group(const float* p, float (&v)[BT]) {
-    if constexpr (BT % 4 == 0) {
-#pragma unroll
-        for (int q = 0; q < BT; q += 4) {
-            const float4 t = *reinterpret_cast<const float4*>(p + q);
-            v[q] = t.x; v[q + 1] = t.y; v[q + 2] = t.z; v[q + 3] = t.w;
-        }
-    } else if constexpr (BT == 2) {
-        const float2 t = *reinterpret_cast<const float2*>(p);
-        v[0] = t.x; v[1] = t.y;
-    } else {
-#pragma unroll
-        for (int q = 0; q < BT; q++) v[q] = p[q];
-    }
-}
-
 template <int MODE, bool REDUCE, int BT>
 __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __restrict__ y, BpArgs a, int batch) {
-    __shared__ float tile[16][17];
+    __shared__ float lds[MODE == BP_RESIDUAL ? 16 * 17 * BT : 1];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
     const int i = i0 + tx, j = j0 + ty;
@@ -225,10 +217,9 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     const bool valid = i < n && j < n;
     const float px = ((float)i - g.half_n) * g.pixel;
     const float py = ((float)j - g.half_n) * g.pixel;
-    // batch-interleaved input [v][k][bs]: this thread's BT images are contiguous
-    // (bs is a multiple of BT, so the group is 4 * BT-byte aligned)
-    const int bs = (batch + BT - 1) / BT * BT;
-    const float* yb = y + b0;
+    // group-interleaved input [group][v][k][BT]: this thread's BT images are
+    // contiguous and 4 * BT-byte aligned
+    const float* yb = y + (size_t)blockIdx.z * g.n_views * g.ds * BT;
     double tot[BT];
 #pragma unroll
     for (int q = 0; q < BT; q++) tot[q] = 0.0;
@@ -258,7 +249,7 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
             const int klo = max(0, (int)ceilf(fmaxf(kmin, -1.f)));
             const int khi = min(g.n_bins - 1, (int)floorf(fminf(kmax, (float)g.n_bins)));
             const RayEntry* rv = g.rays + (size_t)v * g.n_bins;
-            const float* yv = yb + (size_t)v * g.ds * bs;
+            const float* yv = yb + (size_t)v * g.ds * BT;
             float part[BT];
 #pragma unroll
             for (int q = 0; q < BT; q++) part[q] = 0.f;
@@ -267,8 +258,8 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                 const int k1 = two ? k + 1 : k;
                 const RayEntry e0 = rv[k], e1 = rv[k1];
                 float yv0[BT], yv1[BT];
-                load_group<BT>(yv + (size_t)k * bs, yv0);
-                load_group<BT>(yv + (size_t)k1 * bs, yv1);
+                load_group<BT>(yv + (size_t)k * BT, yv0);
+                load_group<BT>(yv + (size_t)k1 * BT, yv1);
                 const float w0 = joseph_weight(e0, i, j, g.c0);
                 const float w1 = joseph_weight(e1, i, j, g.c0) * (two ? 1.f : 0.f);
 #pragma unroll
@@ -280,10 +271,12 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     }
     const int nblk = gridDim.x * gridDim.y;
     const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    float rq[BT];     // RESIDUAL: r of every image of the group (0 beyond the batch)
 #pragma unroll
     for (int q = 0; q < BT; q++) {
+        rq[q] = 0.f;
         const int b = b0 + q;
-        if (b >= batch) break;     // uniform across the block
+        if (b >= batch) continue;     // uniform across the block
         const size_t idx = (size_t)b * n * n + (size_t)j * n + i;
         double part = 0.0;
         if (MODE == BP_PLAIN) {
@@ -296,24 +289,26 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                 part = (double)pv * (double)qv;
             }
         } else {  // BP_RESIDUAL
-            float r = 0.f;
             if (valid) {
                 const float xv = a.aux[idx];
-                r = (float)((double)a.out[idx] - fma((double)a.mu, (double)xv, tot[q]));
+                const float r = (float)((double)a.out[idx] - fma((double)a.mu, (double)xv, tot[q]));
                 a.out[idx] = r;
                 a.p_out[idx] = r;
+                rq[q] = r;
                 part = (double)r * (double)r;
             }
-            store_padded_tile(a.pad_out.base + (size_t)b * 2 * n * g.line, n, g.line, i0, j0, tx, ty, r, tile);
-            __syncthreads();   // the tile is reused by the next batch item
         }
         if (REDUCE) block_partial<256>(part, a.partial + (size_t)b * nblk + blk);
+    }
+    if (MODE == BP_RESIDUAL) {
+        constexpr int P = BT < 2 ? BT : 2;    // pad_group(batch)
+        store_padded_group<BT, P>(a.pad_out.base + (size_t)b0 * 2 * n * g.line, n, g.line, i0, j0, tx, ty, rq, lds);
     }
 }
 
 template <int MODE, bool REDUCE>
 static void launch_bp_mode(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s) {
-    const int bt = batch_tile(batch);
+    const int bt = image_group(batch);
     dim3 grid((g.n + 15) / 16, (g.n + 15) / 16, (batch + bt - 1) / bt), block(256);
     if (bt == 8) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 8>), grid, block, 0, s, g, y, a, batch);
     else if (bt == 4) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 4>), grid, block, 0, s, g, y, a, batch);

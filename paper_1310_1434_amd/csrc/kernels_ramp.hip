@@ -23,17 +23,18 @@ typedef __bf16 b8_t __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------------------- float32
 // Output address of element (row, col): row = b * n_views + v of the input
-// layout; bs == 0 keeps that layout, bs > 0 interleaves the batch.
-__device__ __forceinline__ size_t ramp_out_index(int row, int col, int ds, int n_views, int bs) {
-    if (bs == 0) return (size_t)row * ds + col;
+// layout; grp == 0 keeps that layout, grp > 0 interleaves groups of grp images.
+__device__ __forceinline__ size_t ramp_out_index(int row, int col, int ds, int n_views, int grp) {
+    if (grp == 0) return (size_t)row * ds + col;
     const int b = row / n_views, v = row - b * n_views;
-    return ((size_t)v * ds + col) * bs + b;
+    const int gi = b / grp;
+    return (((size_t)gi * n_views + v) * ds + col) * grp + (b - gi * grp);
 }
 
 template <int SCALE>
 __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, float* __restrict__ yf,
                                                   const float* __restrict__ taps, const float* __restrict__ step,
-                                                  int n_views, int rows, int ds, int bs) {
+                                                  int n_views, int rows, int ds, int grp) {
     extern __shared__ float T[];   // [2 ds]: T[d + ds] = kappa r(|d|)
     for (int i = threadIdx.x; i < 2 * ds; i += 256) T[i] = taps[i];
     __syncthreads();
@@ -80,8 +81,8 @@ __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, f
                 o0 *= so[ncol];
                 o1 *= so[ncol + 16];
             }
-            yf[ramp_out_index(row, ncol, ds, n_views, bs)] = o0;
-            yf[ramp_out_index(row, ncol + 16, ds, n_views, bs)] = o1;
+            yf[ramp_out_index(row, ncol, ds, n_views, grp)] = o0;
+            yf[ramp_out_index(row, ncol + 16, ds, n_views, grp)] = o1;
         }
     }
 }
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, f
 // i = 0..7, with delta = dmin + 16 f (delta = k0 - n0 of the tile).
 template <int PREC, int SCALE>
 __global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y, float* __restrict__ yf,
-                                                    RampTables t, int rows, int ds, int bs) {
+                                                    RampTables t, int rows, int ds, int grp) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = blockIdx.x * 64 + w * 16 + (lane & 15);
     const int slot = lane >> 4;                 // k slots 8 slot .. 8 slot + 7
@@ -179,23 +180,23 @@ __global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y,
                 o0 *= so[ncol];
                 o1 *= so[ncol + 16];
             }
-            yf[ramp_out_index(row, ncol, ds, t.n_views, bs)] = o0;
-            yf[ramp_out_index(row, ncol + 16, ds, t.n_views, bs)] = o1;
+            yf[ramp_out_index(row, ncol, ds, t.n_views, grp)] = o0;
+            yf[ramp_out_index(row, ncol + 16, ds, t.n_views, grp)] = o1;
         }
     }
 }
 
 template <int SCALE>
 static hipError_t launch_ramp_scaled(int prec, const RampTables& t, const float* y, float* yf, int rows, int ds,
-                                     int bs, hipStream_t s) {
+                                     int grp, hipStream_t s) {
     dim3 grid((rows + 63) / 64, ds / 32), block(256);
     if (prec == AIR_FP32) {
         hipLaunchKernelGGL(k_ramp_f32<SCALE>, grid, block, 2 * ds * sizeof(float), s, y, yf, t.taps32, t.step,
-                           t.n_views, rows, ds, bs);
+                           t.n_views, rows, ds, grp);
     } else if (prec == AIR_MIXED_F16) {
-        hipLaunchKernelGGL((k_ramp_split<AIR_MIXED_F16, SCALE>), grid, block, 0, s, y, yf, t, rows, ds, bs);
+        hipLaunchKernelGGL((k_ramp_split<AIR_MIXED_F16, SCALE>), grid, block, 0, s, y, yf, t, rows, ds, grp);
     } else if (prec == AIR_MIXED_BF16) {
-        hipLaunchKernelGGL((k_ramp_split<AIR_MIXED_BF16, SCALE>), grid, block, 0, s, y, yf, t, rows, ds, bs);
+        hipLaunchKernelGGL((k_ramp_split<AIR_MIXED_BF16, SCALE>), grid, block, 0, s, y, yf, t, rows, ds, grp);
     } else {
         return hipErrorInvalidValue;
     }
@@ -203,11 +204,11 @@ static hipError_t launch_ramp_scaled(int prec, const RampTables& t, const float*
 }
 
 hipError_t launch_ramp(int prec, const RampTables& t, const float* y, float* yf, int rows, int ds, int scale,
-                       int bs, hipStream_t s) {
+                       int grp, hipStream_t s) {
     switch (scale) {
-    case 0: return launch_ramp_scaled<0>(prec, t, y, yf, rows, ds, bs, s);
-    case RAMP_POST: return launch_ramp_scaled<RAMP_POST>(prec, t, y, yf, rows, ds, bs, s);
-    case RAMP_PRE | RAMP_POST: return launch_ramp_scaled<RAMP_PRE | RAMP_POST>(prec, t, y, yf, rows, ds, bs, s);
+    case 0: return launch_ramp_scaled<0>(prec, t, y, yf, rows, ds, grp, s);
+    case RAMP_POST: return launch_ramp_scaled<RAMP_POST>(prec, t, y, yf, rows, ds, grp, s);
+    case RAMP_PRE | RAMP_POST: return launch_ramp_scaled<RAMP_PRE | RAMP_POST>(prec, t, y, yf, rows, ds, grp, s);
     default: return hipErrorInvalidValue;
     }
 }

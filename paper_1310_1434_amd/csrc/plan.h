@@ -172,9 +172,9 @@ inline air_status stage_sino(air_plan p, const float* y, int32_t batch, float* s
 // (images at positions [0, batch); per-image buffers are contiguous per image).
 struct SolveBufs {
     float* X;       // [batch][n][n] current image
-    float* pad;     // [batch][2][n][line] padded copies of X or p
+    float* pad;     // grouped padded copies of X or p (PadBuf), rebuilt every outer iteration
     float* s1;      // [batch][n_views][ds] projections
-    float* s2;      // interleaved backprojector input, stride bp_batch_stride(batch)
+    float* s2;      // group-interleaved backprojector input (G = image_group(batch))
     float* g;       // [batch][n][n]  A'^T Y
     float* r;       // [batch][n][n]  right-hand side, then CG residual
     float* p;       // [batch][n][n]
@@ -204,7 +204,7 @@ struct SolveLayout {
 SolveLayout solve_layout(const air_plan_s* p, int batch);
 SolveBufs solve_bufs(const air_plan_s* p, const SolveLayout& L, char* ws, float* X, int batch);
 
-// g = A'^T Y (or A^T Y); zero b and e; padded copies of X.  Y: [batch][V][D] (public layout).
+// g = A'^T Y (or A^T Y); zero b and e.  Y: [batch][V][D] (public layout).
 air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch, const SolveSetup& st, hipStream_t s);
 // One outer iteration (split Bregman) or the whole CG run (L2) for images [0, batch).
 air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSetup& st, hipStream_t s);

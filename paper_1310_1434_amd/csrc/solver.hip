@@ -10,7 +10,7 @@ SolveLayout solve_layout(const air_plan_s* p, int batch) {
     const size_t B = (size_t)batch, n = (size_t)p->g.n, np = n * n;
     Carver c;
     SolveLayout L;
-    L.pad = c.take(B * 2 * n * p->line * sizeof(float));
+    L.pad = c.take((B + 7) / 8 * 8 * 2 * n * p->line * sizeof(float));   // grouped padded copies
     L.s1 = c.take(B * p->g.n_views * p->ds * sizeof(float));
     L.s2 = c.take((B + 7) / 8 * 8 * p->g.n_views * p->ds * sizeof(float));   // interleaved backprojector input
     L.g = c.take(B * np * sizeof(float));
@@ -58,9 +58,9 @@ air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch,
     // g = A'^T Y = J^T (S C Y), or A^T Y = J^T (S Y) for the IR arm
     const float* src = nullptr;
     if (air_status e = stage_sino(p, Y, batch, B.s1, &src, s)) return e;
-    const int bs = bp_batch_stride(batch);
-    if (st.filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, B.s2, rows, p->ds, RAMP_POST, bs, s));
-    else AIR_K(AIR_K_OTHER, launch_scale(kg, src, B.s2, batch, 1, bs, s));
+    const int grp = image_group(batch);
+    if (st.filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, B.s2, rows, p->ds, RAMP_POST, grp, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(kg, src, B.s2, batch, 1, grp, s));
     BpArgs a{};
     a.mode = BP_PLAIN;
     a.out = B.g;
@@ -70,7 +70,6 @@ air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch,
         AIR_K(AIR_K_OTHER, launch_fill(B.e, (size_t)batch * 9 * np, 0.f, s));
     }
     if (B.iters) AIR_K(AIR_K_OTHER, launch_fill(reinterpret_cast<float*>(B.iters), (size_t)batch, 0.f, s));
-    AIR_K(AIR_K_OTHER, launch_pad(kg, B.X, PadBuf{B.pad}, batch, s));
     return AIR_OK;
 }
 
@@ -79,20 +78,22 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
     const RampTables rt = p->ramp_tables();
     const int n = p->g.n, rows = batch * p->g.n_views, nblk = tiles16(n);
     const size_t np = (size_t)n * n;
-    const int bs = bp_batch_stride(batch);
+    const int grp = image_group(batch);
     const bool tf = st.reg == 0;
     const float mu_op = (float)(tf ? st.mu : st.lambda);
     const PadBuf pad{B.pad};
     // operator A'^T A + mu I = J^T (S C S) J + mu I (IR arm: J^T S^2 J + mu I)
     auto filtered = [&]() -> air_status {
         if (st.filter)
-            AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, B.s1, B.s2, rows, p->ds, RAMP_PRE | RAMP_POST, bs, s));
-        else AIR_K(AIR_K_OTHER, launch_scale(kg, B.s1, B.s2, batch, 2, bs, s));
+            AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, B.s1, B.s2, rows, p->ds, RAMP_PRE | RAMP_POST, grp, s));
+        else AIR_K(AIR_K_OTHER, launch_scale(kg, B.s1, B.s2, batch, 2, grp, s));
         return AIR_OK;
     };
     if (tf) AIR_K(AIR_K_FRAMELET, launch_tf_rhs(n, B.g, B.e, (float)st.mu, B.r, batch, s));
     else AIR_HIP(hipMemcpyAsync(B.r, B.g, (size_t)batch * np * sizeof(float), hipMemcpyDeviceToDevice, s));
-    // r = rhs - M X, p = r, rho = r.r
+    // r = rhs - M X, p = r, rho = r.r (the padded copies of X are rebuilt here,
+    // so they never outlive a step and follow the current batch's grouping)
+    AIR_K(AIR_K_OTHER, launch_pad(kg, B.X, pad, batch, s));
     AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, false, s));
     if (air_status e = filtered()) return e;
     {
@@ -124,7 +125,6 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
         cg.r = B.r;
         cg.p = B.p;
         cg.q = B.q;
-        cg.pad.base = it == st.n_cg - 1 ? B.pad : nullptr;
         cg.alpha = B.alpha;
         cg.beta = B.beta;
         cg.partial = B.part;
@@ -135,7 +135,6 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
             AIR_K(AIR_K_CG, launch_cg_update_p(cg, batch, s));
         }
     }
-    if (st.n_cg == 0) AIR_K(AIR_K_OTHER, launch_pad(kg, B.X, pad, batch, s));
     if (tf) {
         TfArgs t{};
         t.n = n;

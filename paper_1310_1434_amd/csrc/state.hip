@@ -53,13 +53,11 @@ struct air_state_s {
             if (g) (void)hipGraphExecDestroy(g);
     }
     size_t np() const { return (size_t)plan->g.n * plan->g.n; }
-    size_t pad_floats() const { return 2 * (size_t)plan->g.n * plan->line; }
     // SolveBufs viewing a single image at position `pos` (batch 1)
     SolveBufs at(int pos) const {
         SolveBufs b = B;
         const size_t n = np();
         b.X += pos * n;
-        b.pad += pos * pad_floats();
         b.g += pos * n;
         b.r += pos * n;
         b.p += pos * n;
@@ -109,7 +107,6 @@ air_status move_slot(air_state st, int from, int to, hipStream_t s) {
     AIR_HIP(hipMemcpyAsync(b.g, a.g, n, hipMemcpyDeviceToDevice, s));
     AIR_HIP(hipMemcpyAsync(b.bb, a.bb, 8 * n, hipMemcpyDeviceToDevice, s));
     AIR_HIP(hipMemcpyAsync(b.e, a.e, 9 * n, hipMemcpyDeviceToDevice, s));
-    AIR_HIP(hipMemcpyAsync(b.pad, a.pad, st->pad_floats() * sizeof(float), hipMemcpyDeviceToDevice, s));
     AIR_HIP(hipMemcpyAsync(b.resid, a.resid, st->max_outer * sizeof(double), hipMemcpyDeviceToDevice, s));
     AIR_HIP(hipMemcpyAsync(b.iters, a.iters, sizeof(int), hipMemcpyDeviceToDevice, s));
     return AIR_OK;
@@ -356,7 +353,6 @@ air_status air_state_restore(air_state st, const void* host_buf, hipStream_t s, 
     const int it = h.iters;
     AIR_HIP(hipMemcpyAsync(b.iters, &it, sizeof(int), hipMemcpyHostToDevice, s));
     AIR_HIP(hipStreamSynchronize(s));     // `it` and the caller's buffer are read before returning
-    AIR_HIP(launch_pad(p->kgeom(), b.X, PadBuf{b.pad}, 1, s));
     *slot_out = slot;
     return AIR_OK;
 }
