@@ -184,21 +184,30 @@ hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, i
 }
 
 // ---------------------------------------------------------------------------- adjoint J^T
-// One thread per pixel and up to BT images, 16x16 pixels per block.  For every
-// view the pixel finds the bins whose rays can give it a non-zero Joseph
-// weight: the detector interval covered by the diamond |dx| + |dy| <= pixel
-// around its centre (any sample that touches the pixel lies inside it),
-// widened by 0.01 bin.  For each candidate it re-evaluates the forward
-// projector's own fixed-point intercept and float32 weight, so the result is
-// the exact transpose of k_project (unscaled) up to summation order.
-// Candidates are taken two at a time with predication, so that their table
-// and sinogram loads are in flight together.  Per view the (few) terms are
-// summed in float32, across views in float64.  No atomics.
-__device__ __forceinline__ float joseph_weight(const RayEntry& e, int i, int j, int c0) {
-    const int ax = ray_axis(e.meta);
-    const int da = ax ? j : i;      // driving index of this pixel for the ray
-    const int ob = ax ? i : j;      // interpolated index
-    const int64_t t = fx_at(e, da - c0);
+// One thread per pair of vertically adjacent pixels (i, j) and (i, j + 1) and
+// up to BT images; 16 x 32 pixels per block.  For every view the pair takes
+// the bins whose rays can give either pixel a non-zero Joseph weight: any
+// sample that touches a pixel lies in the diamond |dx| + |dy| < pixel around
+// its centre, so its ray meets the detector within hw bins of the centre's own
+// projection k_c, where hw bounds the projected half-width of the diamond over
+// the whole tile; the interval (from the lower to the higher k_c of the two
+// centres) is widened by 0.01 bin.  For each candidate the thread re-evaluates
+// the forward projector's own fixed-point intercept and float32 weights, so
+// the result is the exact transpose of k_project (unscaled) up to summation
+// order.  An x-driven ray crosses both pixels of the pair at the same
+// intercept, so one evaluation gives both weights; a y-driven ray needs a
+// second intercept, one 64-bit add away.
+//
+// Views are processed kBpViews at a time.  Per view, the tile's bins (the
+// union of its pixels' intervals, at most kBpBins per pass) and their
+// sinogram values are staged in shared memory by one wavefront, one bin per
+// lane, so all candidates are read from LDS.  The terms of a pass are summed
+// in float32, across passes in float64.  No atomics.
+constexpr int kBpViews = 4;    // views per pass = wavefronts per block
+constexpr int kBpBins = 64;    // staged bins per view and pass = lanes per wavefront
+
+// Joseph weight of the sample at fixed-point intercept t for interpolated index ob.
+__device__ __forceinline__ float joseph_weight_at(int64_t t, int ob) {
     const float f = fx_frac(t);
     const int j0 = fx_index(t) - kPad;
     // ob in {j0, j0 + 1} implies -1 <= t < n: exactly the samples the forward
@@ -206,110 +215,268 @@ __device__ __forceinline__ float joseph_weight(const RayEntry& e, int i, int j, 
     return (ob == j0) ? (1.f - f) : ((ob == j0 + 1) ? f : 0.f);
 }
 
+// Weights of ray e for the pixels (i, j) and (i, j + 1).  AX: 0 = the ray is
+// x-driven, 1 = y-driven, 2 = either (read from the table).  With d = j0 - ob
+// (j0 the first sample's index, ob the pixel's interpolated index) a pixel
+// takes 1 - f at d == 0 and f at d == -1.
+template <int AX>
+__device__ __forceinline__ void joseph_pair(const RayEntry& e, int i, int j, int c0, float& wa, float& wb) {
+    if constexpr (AX == 0) {
+        // both pixels sit on the column the ray samples at i: one intercept
+        const int64_t t = fx_at(e, i - c0);
+        const float f = fx_frac(t);
+        const int d = fx_index(t) - kPad - j;
+        wa = d == 0 ? 1.f - f : (d == -1 ? f : 0.f);
+        wb = d == 1 ? 1.f - f : (d == 0 ? f : 0.f);
+    } else if constexpr (AX == 1) {
+        // driving rows j and j + 1, interpolated index i for both
+        const int64_t ta = fx_at(e, j - c0);
+        const int64_t tb = ta + (int64_t)e.m * 2;
+        const float fa = fx_frac(ta), fb = fx_frac(tb);
+        const int da = fx_index(ta) - kPad - i, db = fx_index(tb) - kPad - i;
+        wa = da == 0 ? 1.f - fa : (da == -1 ? fa : 0.f);
+        wb = db == 0 ? 1.f - fb : (db == -1 ? fb : 0.f);
+    } else {
+        const int ax = ray_axis(e.meta);
+        const int64_t ta = fx_at(e, (ax ? j : i) - c0);
+        const int64_t tb = ax ? ta + (int64_t)e.m * 2 : ta;   // y-driven: next driving row
+        wa = joseph_weight_at(ta, ax ? i : j);
+        wb = joseph_weight_at(tb, ax ? i : j + 1);
+    }
+}
+
+// Accumulate the candidates [wlo, whi] (staged bins of one view) into both pixels.
+template <int AX, int BT>
+__device__ __forceinline__ void bp_candidates(const RayEntry* rays, const float* vals, int wlo, int whi, int i,
+                                              int j, int c0, float (&acc_a)[BT], float (&acc_b)[BT]) {
+    for (int w = wlo; w <= whi; w += 2) {
+        const bool two = w + 1 <= whi;
+        const int w1 = two ? w + 1 : w;
+        const RayEntry e0 = rays[w], e1 = rays[w1];
+        float y0[BT], y1[BT];
+        load_group<BT>(vals + w * BT, y0);
+        load_group<BT>(vals + w1 * BT, y1);
+        float wa0, wb0, wa1, wb1;
+        joseph_pair<AX>(e0, i, j, c0, wa0, wb0);
+        joseph_pair<AX>(e1, i, j, c0, wa1, wb1);
+        const float keep = two ? 1.f : 0.f;
+        wa1 *= keep;
+        wb1 *= keep;
+#pragma unroll
+        for (int q = 0; q < BT; q++) {
+            acc_a[q] = fmaf(wa1, y1[q], fmaf(wa0, y0[q], acc_a[q]));
+            acc_b[q] = fmaf(wb1, y1[q], fmaf(wb0, y0[q], acc_b[q]));
+        }
+    }
+}
+
+// Continuous detector bin of the projection of point (px, py) in view (c, s).
+__device__ __forceinline__ float bin_of(const KGeom& g, float px, float py, float c, float s) {
+    if (g.beam == 0) return fmaf(fmaf(px, c, py * s), g.inv_bin, g.half_d);
+    const float ap = fmaf(py, c, -px * s);
+    const float bp = g.sod - fmaf(px, c, py * s);
+    return fmaf(g.sdd * ap * __builtin_amdgcn_rcpf(bp), g.inv_bin, g.half_d);
+}
+
+int bp_blocks(int n) { return ((n + 15) / 16) * ((n + 31) / 32); }
+
 template <int MODE, bool REDUCE, int BT>
 __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __restrict__ y, BpArgs a, int batch) {
-    __shared__ float lds[MODE == BP_RESIDUAL ? 16 * 17 * BT : 1];
+    static_assert(kBpViews * kWave == 256 && kBpBins == kWave, "one wavefront stages one view");
+    __shared__ __align__(16) RayEntry s_ray[kBpViews][kBpBins];
+    __shared__ __align__(16) float s_val[kBpViews][kBpBins * BT];
+    __shared__ int s_axes[kBpViews];     // staged rays all x-driven (0), all y-driven (1), or both (2)
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
-    const int i = i0 + tx, j = j0 + ty;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 32;
+    const int i = i0 + tx, j = j0 + 2 * ty;      // pixels (i, j) and (i, j + 1)
     const int b0 = blockIdx.z * BT;
     const int n = g.n;
-    const bool valid = i < n && j < n;
-    const float px = ((float)i - g.half_n) * g.pixel;
-    const float py = ((float)j - g.half_n) * g.pixel;
+    const bool va = i < n && j < n, vb = i < n && j + 1 < n;
+    // (pixels past the image edge take an in-image neighbour's window; their sums are dropped)
+    const float px = ((float)min(i, n - 1) - g.half_n) * g.pixel;
+    const float py = ((float)min(j, n - 2) - g.half_n) * g.pixel;
+    // corners of the tile's in-image pixel centres, for the tile windows
+    const float cx[2] = {((float)i0 - g.half_n) * g.pixel, ((float)min(i0 + 15, n - 1) - g.half_n) * g.pixel};
+    const float cy[2] = {((float)j0 - g.half_n) * g.pixel, ((float)min(j0 + 31, n - 1) - g.half_n) * g.pixel};
     // group-interleaved input [group][v][k][BT]: this thread's BT images are
     // contiguous and 4 * BT-byte aligned
-    const float* yb = y + (size_t)blockIdx.z * g.n_views * g.ds * BT;
-    double tot[BT];
+    const float* yg = y + (size_t)blockIdx.z * g.n_views * g.ds * BT;
+    double tot_a[BT], tot_b[BT];
 #pragma unroll
-    for (int q = 0; q < BT; q++) tot[q] = 0.0;
-    if (valid) {
-        for (int v = 0; v < g.n_views; v++) {
-            const float2 cs = g.views[v];
-            const float c = cs.x, s = cs.y;
-            float umin, umax;
-            if (g.beam == 0) {
-                const float uc = fmaf(px, c, py * s);
-                const float hw = g.pixel * fmaxf(fabsf(c), fabsf(s));
-                umin = uc - hw;
-                umax = uc + hw;
+    for (int q = 0; q < BT; q++) tot_a[q] = tot_b[q] = 0.0;
+    for (int v0 = 0; v0 < g.n_views; v0 += kBpViews) {
+        // Tile windows of the pass's views, computed redundantly by every
+        // wavefront: lane 4 s + c takes corner c of view v0 + s.
+        float kc_lo = 3e38f, kc_hi = -3e38f, hw = 0.f;
+        {
+            const int s = (lane >> 2) & 3, c = lane & 3;
+            const int v = v0 + s;
+            if (lane < 16 && v < g.n_views) {
+                const float2 cs = g.views[v];
+                const float qx = cx[c & 1], qy = cy[c >> 1];
+                const float kc = bin_of(g, qx, qy, cs.x, cs.y);
+                const float m = fmaxf(fabsf(cs.x), fabsf(cs.y));
+                float bp_min = 1.f, ap_max = 0.f;
+                if (g.beam != 0) {
+                    ap_max = fabsf(fmaf(qy, cs.x, -qx * cs.y));
+                    bp_min = g.sod - fmaf(qx, cs.x, qy * cs.y);
+                }
+                kc_lo = kc;
+                kc_hi = kc;
+#pragma unroll
+                for (int off = 1; off <= 2; off <<= 1) {
+                    kc_lo = fminf(kc_lo, __shfl_xor(kc_lo, off, kWave));
+                    kc_hi = fmaxf(kc_hi, __shfl_xor(kc_hi, off, kWave));
+                    bp_min = fminf(bp_min, __shfl_xor(bp_min, off, kWave));
+                    ap_max = fmaxf(ap_max, __shfl_xor(ap_max, off, kWave));
+                }
+                // projected half-width of a pixel's diamond, in bins: parallel
+                // pixel * m; fan: a vertex moves ap and bp by at most pixel * m,
+                // so |du| <= sdd pixel m (bp + |ap|) / (bp (bp - pixel m)), which
+                // grows with |ap| and falls with bp over the tile
+                const float dm = g.pixel * m;
+                hw = g.beam == 0 ? dm * g.inv_bin
+                                 : g.sdd * dm * (bp_min + ap_max) *
+                                       __builtin_amdgcn_rcpf(bp_min * (bp_min - dm)) * g.inv_bin;
+            }
+        }
+        int kb0[kBpViews], nb[kBpViews];
+        float hws[kBpViews];
+#pragma unroll
+        for (int s = 0; s < kBpViews; s++) {
+            const float klo_f = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc_lo), 4 * s));
+            const float khi_f = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc_hi), 4 * s));
+            hws[s] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hw), 4 * s));
+            if (v0 + s < g.n_views) {
+                kb0[s] = max(0, (int)floorf(klo_f - hws[s] - 0.5f));
+                const int kb1 = min(g.n_bins - 1, (int)ceilf(khi_f + hws[s] + 0.5f));
+                nb[s] = max(0, kb1 - kb0[s] + 1);
             } else {
-                const float ap = fmaf(py, c, -px * s);
-                const float bp = g.sod - fmaf(px, c, py * s);
-                const float ds_ = g.pixel * s, dc = g.pixel * c;
-                const float u1 = (ap - ds_) * __builtin_amdgcn_rcpf(bp - dc);
-                const float u2 = (ap + ds_) * __builtin_amdgcn_rcpf(bp + dc);
-                const float u3 = (ap + dc) * __builtin_amdgcn_rcpf(bp - ds_);
-                const float u4 = (ap - dc) * __builtin_amdgcn_rcpf(bp + ds_);
-                umin = g.sdd * fminf(fminf(u1, u2), fminf(u3, u4));
-                umax = g.sdd * fmaxf(fmaxf(u1, u2), fmaxf(u3, u4));
+                kb0[s] = 0;
+                nb[s] = 0;
             }
-            const float kmin = fmaf(umin, g.inv_bin, g.half_d) - 0.01f;
-            const float kmax = fmaf(umax, g.inv_bin, g.half_d) + 0.01f;
-            const int klo = max(0, (int)ceilf(fmaxf(kmin, -1.f)));
-            const int khi = min(g.n_bins - 1, (int)floorf(fminf(kmax, (float)g.n_bins)));
-            const RayEntry* rv = g.rays + (size_t)v * g.n_bins;
-            const float* yv = yb + (size_t)v * g.ds * BT;
-            float part[BT];
+        }
+        int passes = 1;
 #pragma unroll
-            for (int q = 0; q < BT; q++) part[q] = 0.f;
-            for (int k = klo; k <= khi; k += 2) {
-                const bool two = k + 1 <= khi;
-                const int k1 = two ? k + 1 : k;
-                const RayEntry e0 = rv[k], e1 = rv[k1];
-                float yv0[BT], yv1[BT];
-                load_group<BT>(yv + (size_t)k * BT, yv0);
-                load_group<BT>(yv + (size_t)k1 * BT, yv1);
-                const float w0 = joseph_weight(e0, i, j, g.c0);
-                const float w1 = joseph_weight(e1, i, j, g.c0) * (two ? 1.f : 0.f);
+        for (int s = 0; s < kBpViews; s++) passes = max(passes, (nb[s] + kBpBins - 1) / kBpBins);
+        // the pair's bin interval per view (absolute bins), from its two centres
+        int klo[kBpViews], khi[kBpViews];
 #pragma unroll
-                for (int q = 0; q < BT; q++) part[q] = fmaf(w1, yv1[q], fmaf(w0, yv0[q], part[q]));
+        for (int s = 0; s < kBpViews; s++) {
+            klo[s] = 0;
+            khi[s] = -1;
+            if (v0 + s < g.n_views) {
+                const float2 cs = g.views[v0 + s];
+                const float ka = bin_of(g, px, py, cs.x, cs.y);
+                const float kb = bin_of(g, px, py + g.pixel, cs.x, cs.y);
+                klo[s] = max(kb0[s], (int)ceilf(fminf(ka, kb) - hws[s] - 0.01f));
+                khi[s] = min(kb0[s] + nb[s] - 1, (int)floorf(fmaxf(ka, kb) + hws[s] + 0.01f));
             }
+        }
+        float acc_a[BT], acc_b[BT];
 #pragma unroll
-            for (int q = 0; q < BT; q++) tot[q] += (double)part[q];
+        for (int q = 0; q < BT; q++) acc_a[q] = acc_b[q] = 0.f;
+        for (int p = 0; p < passes; p++) {
+            // stage: wavefront s loads bins kb0 + p * kBpBins + lane of view v0 + s
+            {
+                int my_kb0 = kb0[0], my_nb = nb[0];
+#pragma unroll
+                for (int s = 1; s < kBpViews; s++)
+                    if (wave == s) {
+                        my_kb0 = kb0[s];
+                        my_nb = nb[s];
+                    }
+                const int w = p * kBpBins + lane;
+                const bool act = w < my_nb;
+                int ax = 0;
+                if (act) {
+                    const int v = v0 + wave, k = my_kb0 + w;
+                    const RayEntry e = g.rays[(size_t)v * g.n_bins + k];
+                    s_ray[wave][lane] = e;
+                    ax = ray_axis(e.meta);
+                    float t[BT];
+                    load_group<BT>(yg + ((size_t)v * g.ds + k) * BT, t);
+                    store_group<BT>(&s_val[wave][lane * BT], t);
+                }
+                const bool any_x = __ballot(act && ax == 0) != 0, any_y = __ballot(act && ax == 1) != 0;
+                if (lane == 0) s_axes[wave] = any_y ? (any_x ? 2 : 1) : 0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < kBpViews; s++) {
+                const int base = kb0[s] + p * kBpBins;
+                const int wlo = max(klo[s] - base, 0), whi = min(khi[s] - base, kBpBins - 1);
+                const int axes = __builtin_amdgcn_readfirstlane(s_axes[s]);   // uniform over the block
+                if (axes == 0)
+                    bp_candidates<0, BT>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc_a, acc_b);
+                else if (axes == 1)
+                    bp_candidates<1, BT>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc_a, acc_b);
+                else
+                    bp_candidates<2, BT>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc_a, acc_b);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < BT; q++) {
+            tot_a[q] += (double)acc_a[q];
+            tot_b[q] += (double)acc_b[q];
         }
     }
     const int nblk = gridDim.x * gridDim.y;
     const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-    float rq[BT];     // RESIDUAL: r of every image of the group (0 beyond the batch)
+    float ra[BT], rb[BT];     // RESIDUAL: r of both pixels for every image (0 beyond the batch)
 #pragma unroll
     for (int q = 0; q < BT; q++) {
-        rq[q] = 0.f;
+        ra[q] = rb[q] = 0.f;
         const int b = b0 + q;
         if (b >= batch) continue;     // uniform across the block
-        const size_t idx = (size_t)b * n * n + (size_t)j * n + i;
+        const size_t ia = (size_t)b * n * n + (size_t)j * n + i, ib = ia + n;
         double part = 0.0;
         if (MODE == BP_PLAIN) {
-            if (valid) a.out[idx] = (float)tot[q];
+            if (va) a.out[ia] = (float)tot_a[q];
+            if (vb) a.out[ib] = (float)tot_b[q];
         } else if (MODE == BP_MATVEC) {
-            if (valid) {
-                const float pv = a.aux[idx];
-                const float qv = (float)fma((double)a.mu, (double)pv, tot[q]);
-                a.out[idx] = qv;
+            if (va) {
+                const float pv = a.aux[ia];
+                const float qv = (float)fma((double)a.mu, (double)pv, tot_a[q]);
+                a.out[ia] = qv;
                 part = (double)pv * (double)qv;
             }
+            if (vb) {
+                const float pv = a.aux[ib];
+                const float qv = (float)fma((double)a.mu, (double)pv, tot_b[q]);
+                a.out[ib] = qv;
+                part += (double)pv * (double)qv;
+            }
         } else {  // BP_RESIDUAL
-            if (valid) {
-                const float xv = a.aux[idx];
-                const float r = (float)((double)a.out[idx] - fma((double)a.mu, (double)xv, tot[q]));
-                a.out[idx] = r;
-                a.p_out[idx] = r;
-                rq[q] = r;
+            if (va) {
+                const float r = (float)((double)a.out[ia] - fma((double)a.mu, (double)a.aux[ia], tot_a[q]));
+                a.out[ia] = r;
+                a.p_out[ia] = r;
+                ra[q] = r;
                 part = (double)r * (double)r;
+            }
+            if (vb) {
+                const float r = (float)((double)a.out[ib] - fma((double)a.mu, (double)a.aux[ib], tot_b[q]));
+                a.out[ib] = r;
+                a.p_out[ib] = r;
+                rb[q] = r;
+                part += (double)r * (double)r;
             }
         }
         if (REDUCE) block_partial<256>(part, a.partial + (size_t)b * nblk + blk);
     }
     if (MODE == BP_RESIDUAL) {
         constexpr int P = BT < 2 ? BT : 2;    // pad_group(batch)
-        store_padded_group<BT, P>(a.pad_out.base + (size_t)b0 * 2 * n * g.line, n, g.line, i0, j0, tx, ty, rq, lds);
+        store_padded_pair<BT, P>(a.pad_out.base + (size_t)b0 * 2 * n * g.line, n, g.line, i0, j0, tx, ty, ra, rb);
     }
 }
 
 template <int MODE, bool REDUCE>
 static void launch_bp_mode(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s) {
     const int bt = image_group(batch);
-    dim3 grid((g.n + 15) / 16, (g.n + 15) / 16, (batch + bt - 1) / bt), block(256);
+    dim3 grid((g.n + 15) / 16, (g.n + 31) / 32, (batch + bt - 1) / bt), block(256);
     if (bt == 8) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 8>), grid, block, 0, s, g, y, a, batch);
     else if (bt == 4) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 4>), grid, block, 0, s, g, y, a, batch);
     else if (bt == 2) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 2>), grid, block, 0, s, g, y, a, batch);

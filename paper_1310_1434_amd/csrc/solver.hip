@@ -76,7 +76,7 @@ air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch,
 air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSetup& st, hipStream_t s) {
     const KGeom kg = p->kgeom();
     const RampTables rt = p->ramp_tables();
-    const int n = p->g.n, rows = batch * p->g.n_views, nblk = tiles16(n);
+    const int n = p->g.n, rows = batch * p->g.n_views, nblk = tiles16(n), nblk_bp = bp_blocks(n);
     const size_t np = (size_t)n * n;
     const int grp = image_group(batch);
     const bool tf = st.reg == 0;
@@ -106,7 +106,7 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
         a.pad_out = pad;
         a.partial = B.part;
         AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, B.s2, a, batch, s));
-        AIR_K(AIR_K_CG, launch_finalize(FIN_RHO, B.part, nblk, batch, B.rho, nullptr, nullptr, 0, nullptr, s));
+        AIR_K(AIR_K_CG, launch_finalize(FIN_RHO, B.part, nblk_bp, batch, B.rho, nullptr, nullptr, 0, nullptr, s));
     }
     for (int it = 0; it < st.n_cg; it++) {
         AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, false, s));
@@ -118,7 +118,7 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
         a.out = B.q;
         a.partial = B.part;
         AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, B.s2, a, batch, s));
-        AIR_K(AIR_K_CG, launch_finalize(FIN_ALPHA, B.part, nblk, batch, B.rho, B.alpha, nullptr, 0, nullptr, s));
+        AIR_K(AIR_K_CG, launch_finalize(FIN_ALPHA, B.part, nblk_bp, batch, B.rho, B.alpha, nullptr, 0, nullptr, s));
         CgArgs cg{};
         cg.n = n;
         cg.x = B.X;

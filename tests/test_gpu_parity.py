@@ -50,11 +50,15 @@ def host(x):
 
 RAGGED = Geometry("fan", n=100, pixel=1.1, n_views=37, n_bins=150, bin=1.3, sod=400.0, sdd=700.0)
 SMALL_PAR = Geometry("parallel", n=40, pixel=1.0, n_views=30, n_bins=61, bin=1.0)
+# bins much finer than pixels: a 16x16 tile's detector window spans ~350 bins,
+# so the backprojector stages every view in several passes (about 6)
+FINE = Geometry("fan", n=48, pixel=1.0, n_views=23, n_bins=960, bin=0.17, sod=120.0, sdd=200.0)
 
 
 def geom(name):
     return {"c1": synth.workload("c1").geom, "c2": synth.workload("c2").geom,
-            "c2_25": synth.workload("c2_25").geom, "ragged": RAGGED, "small_par": SMALL_PAR}[name]
+            "c2_25": synth.workload("c2_25").geom, "ragged": RAGGED, "small_par": SMALL_PAR,
+            "fine": FINE}[name]
 
 
 def image_for(name, seed=0):
@@ -98,7 +102,7 @@ def test_ramp_parity(air, torch_mod, orc, record, name, prec):
 
 
 @pytest.mark.parametrize("filt", [0, 1])
-@pytest.mark.parametrize("name", ["c1", "ragged", "c2"])
+@pytest.mark.parametrize("name", ["c1", "ragged", "fine", "c2"])
 def test_filtered_backproject_parity(air, torch_mod, orc, record, name, filt):
     g = geom(name)
     y = sino_for(name).astype(np.float32)
@@ -135,10 +139,15 @@ def test_framelet_parity(air, torch_mod, orc, n):
         assert rel(xa[b], orc.framelet_adjoint(zz[b].astype(np.float64))) < 1e-6
 
 
-def test_gpu_adjoint_is_exact_transpose(air, torch_mod):
+@pytest.mark.parametrize("g", [Geometry("fan", n=12, pixel=1.0, n_views=9, n_bins=21, bin=1.0, sod=40.0, sdd=70.0),
+                               Geometry("fan", n=10, pixel=1.0, n_views=5, n_bins=150, bin=0.19, sod=40.0, sdd=70.0),
+                               Geometry("parallel", n=19, pixel=0.8, n_views=7, n_bins=30, bin=1.1)],
+                         ids=["fan", "fan_fine_bins", "parallel_ragged"])
+def test_gpu_adjoint_is_exact_transpose(air, torch_mod, g):
     """Dense A from unit images and dense A^T from unit rays agree bit for bit:
-    the gather backprojector evaluates exactly the forward projector's weights."""
-    g = Geometry("fan", n=12, pixel=1.0, n_views=9, n_bins=21, bin=1.0, sod=40.0, sdd=70.0)
+    the gather backprojector evaluates exactly the forward projector's weights
+    (also when a tile's window needs several staging passes, and on tiles cut
+    by the image edge)."""
     n, nr = g.n, g.n_views * g.n_bins
     plan = air.Plan(g, max_batch=max(n * n, nr))
     t = torch_mod
@@ -170,6 +179,24 @@ def test_operator_batch_matches_single(air, torch_mod):
     for b in range(3):
         y1 = host(plan.project(dev(torch_mod, xs[b:b + 1])))[0]
         assert np.array_equal(y1, yb[b])
+
+
+@pytest.mark.parametrize("batch", [2, 3, 5, 9])
+def test_backprojection_batch_matches_single(air, torch_mod, batch):
+    """Every image gets the same bits whatever group of images it is processed
+    in (groups of 2, 4 or 8, with idle lanes in the last group)."""
+    g = geom("ragged")
+    plan = air.Plan(g, max_batch=batch)
+    ys = np.stack([sino_for("ragged", s) for s in range(batch)]).astype(np.float32)
+    for filt in (0, 1):
+        xb = host(plan.filtered_backproject(dev(torch_mod, ys), filter=filt))
+        for b in range(batch):
+            x1 = host(plan.filtered_backproject(dev(torch_mod, ys[b:b + 1]), filter=filt))[0]
+            assert np.array_equal(x1, xb[b]), (filt, b)
+    xs = np.random.default_rng(batch).uniform(0, 0.03, (batch, g.n, g.n)).astype(np.float32)
+    yb = host(plan.project(dev(torch_mod, xs)))
+    for b in range(batch):
+        assert np.array_equal(host(plan.project(dev(torch_mod, xs[b:b + 1])))[0], yb[b])
 
 
 def test_batch_above_plan_limit_is_rejected(air, torch_mod):
