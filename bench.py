@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=40.0, help="offered load, requests per second")
     ap.add_argument("--serve-capacity", type=int, default=8, help="slots per geometry group")
     ap.add_argument("--serve-precision", default="mixed_f16", choices=["fp32", "mixed_f16", "mixed_bf16"])
+    ap.add_argument("--quality", action="store_true",
+                    help="run the FBP / IR / AIR image-quality comparison (CNR, FWHM) on the paper-shaped scan")
+    ap.add_argument("--quality-i0", type=float, default=2e4, help="incident photons per ray of the quality scans")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into profiles/traffic_c2.json")
     return ap.parse_args()
@@ -204,8 +207,52 @@ def serve_bench(a):
             "mean_bregman_iterations": float(np.mean([r.n_outer for r in reqs]))}
 
 
+def quality_bench(a):
+    """FBP, IR and AIR on the resolution and contrast phantoms, 100% and 25% data
+    of the paper-shaped scan (350^2, 528 bins, 800 / 200 views), 50 x 5 iterations."""
+    import torch
+    from paper_1310_1434_amd import air
+    from paper_1310_1434_amd import quality as Q
+    from synth import quality as SQ
+
+    lam, mu, n_outer, n_cg = 0.005, 1.0, 50, 5
+    phantoms = [SQ.resolution_phantom(), SQ.contrast_phantom()]
+    out = {"geometry": "fan 350^2 x 1 mm, 528 bins x 1.1 mm, SOD 850, SDD 1450", "i0": a.quality_i0,
+           "lambda": lam, "mu": mu, "n_outer": n_outer, "n_cg": n_cg, "data": {}}
+    for label, step in (("100%", 1), ("25%", 4)):
+        g = SQ.paper_geometry(step)
+        cases = [SQ.make_quality_case(ph, g, a.quality_i0, 11 + k) for k, ph in enumerate(phantoms)]
+        plan = air.Plan(g, max_batch=len(cases))
+        s = Q.top_eigenvalue(plan, 0) / Q.top_eigenvalue(plan, 1)
+        y = torch.from_numpy(np.stack([c["y"] for c in cases]).astype(np.float32)).cuda()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        arms = Q.run_arms(plan, y, lam, mu, n_outer, n_cg, s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        res = {"views": g.n_views, "ir_scale": s, "wall_s_all_arms": wall, "arms": {}}
+        for arm, x in arms.items():
+            imgs = x.cpu().numpy().astype(np.float64)
+            r = {}
+            for ph, img, c in zip(phantoms, imgs, cases):
+                r["rmse_vs_truth"] = r.get("rmse_vs_truth", []) + [float(np.sqrt(np.mean((img - c["x_true"]) ** 2)))]
+                if ph.bar_groups:
+                    r["fwhm"] = [Q.bar_fwhm(img, gr, g.pixel) for gr in ph.bar_groups]
+                else:
+                    r["cnr"] = Q.target_cnrs(img, ph, g.pixel)
+            res["arms"][arm] = r
+        out["data"][label] = res
+    return out
+
+
 def main():
     a = parse()
+    if a.quality:
+        if a.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({"quality": quality_bench(a)}), flush=True)
+        return
     if a.serve:
         if a.gpus != 1:
             print("bench.py: one GPU only", file=sys.stderr)
