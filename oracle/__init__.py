@@ -206,7 +206,7 @@ def cg(g: Geom, rhs, mu: float, n_iter: int, x0=None, filter: int = 1) -> np.nda
 
 def solve(g: Geom, y, lam: float, mu: float, n_outer: int, n_cg: int, reg: int = 0,
           filter: int = 1, x0=None, return_b: bool = False):
-    """Split Bregman (reg=0) or Eq. (5) L2 (reg=1).
+    """Split Bregman (reg=0), Eq. (5) L2 (reg=1) or forward-backward splitting (reg=2, mu = step of Eq. (6)).
 
     Returns (X, resid[n_outer]), plus the final Bregman variable b [9, n, n]
     when ``return_b`` is set."""

@@ -346,6 +346,47 @@ int orc_cg(const orc_geom* g, const double* rhs, double mu, int32_t filter, int3
     return rc;
 }
 
+/* Forward-backward splitting (Eq. (6)) for min ||P(AX - Y)||^2 + lambda ||W X||_1:
+ *   repeat n_outer times:
+ *     X' = X - mu A^T C (A X - Y)                (forward step, Eq. (6); A^T alone when filter == 0)
+ *     X  = W^T shrink(W X', mu lambda / 2)       (proximal step; band 0 passes through)
+ *     resid[k] = ||X_new - X_old||_2
+ * The data term's gradient is 2 A^T C (A X - Y), so the step of Eq. (6) is mu / 2
+ * and the matching threshold mu lambda / 2.  For the tight frame (W^T W = I)
+ * W^T shrink W stands in for the exact proximal map of lambda ||W X||_1. */
+static int orc_fbs(const orc_geom* g, const double* y, const orc_params* prm, double* x, double* resid) {
+    const int n = g->n;
+    const size_t np = (size_t)n * n, nz = 9 * np, ns = (size_t)g->n_views * g->n_bins;
+    double* ax = (double*)malloc(ns * sizeof(double));
+    double* grad = (double*)malloc(np * sizeof(double));
+    double* z = (double*)malloc(nz * sizeof(double));
+    double* d = (double*)malloc(nz * sizeof(double));
+    double* xn = (double*)malloc(np * sizeof(double));
+    int rc = (ax && grad && z && d && xn) ? 0 : -3;
+    const double thr = prm->mu * prm->lambda / 2.0;
+    for (int k = 0; k < prm->n_outer && rc == 0; k++) {
+        rc = orc_project(g, x, ax);                                    /* A X */
+        if (rc) break;
+        for (size_t i = 0; i < ns; i++) ax[i] -= y[i];                  /* A X - Y */
+        rc = orc_filtered_backproject(g, ax, grad, prm->filter);      /* A'^T (A X - Y) */
+        if (rc) break;
+        for (size_t p = 0; p < np; p++) xn[p] = x[p] - prm->mu * grad[p];
+        rc = orc_framelet(n, xn, z);
+        if (rc) break;
+        orc_shrink(n, z, thr, d);
+        rc = orc_framelet_adjoint(n, d, xn);
+        if (rc) break;
+        double ss = 0.0;
+        for (size_t p = 0; p < np; p++) {
+            ss += (xn[p] - x[p]) * (xn[p] - x[p]);
+            x[p] = xn[p];
+        }
+        if (resid) resid[k] = sqrt(ss);
+    }
+    free(ax); free(grad); free(z); free(d); free(xn);
+    return rc;
+}
+
 /* Split Bregman for min ||P(AX - Y)||^2 + lambda ||W X||_1 (detail bands):
  *   g = A^T C Y;  d = b = 0
  *   repeat n_outer times:
@@ -354,12 +395,14 @@ int orc_cg(const orc_geom* g, const double* rhs, double mu, int32_t filter, int3
  *     resid[k] = ||W X - d||_2
  * reg = 1: the L2-regularised case, Eq. (5): n_cg CG steps on
  * (A^T C A + lambda I) X = A^T C Y from the given X.
+ * reg = 2: forward-backward splitting (orc_fbs), mu the step of Eq. (6).
  * X holds the start value on entry (zeros for the standard start); b_out, if
  * not NULL, receives the final Bregman variable b [9][n][n]. */
 int orc_solve(const orc_geom* g, const double* y, const orc_params* prm, double* x, double* resid,
               double* b_out) {
     if (!geom_ok(g) || !y || !prm || !x) return -1;
     if (prm->n_outer < 0 || prm->n_cg < 0 || !(prm->mu > 0.0) || prm->lambda < 0.0) return -1;
+    if (prm->reg == 2) return orc_fbs(g, y, prm, x, resid);
     const int n = g->n;
     const size_t np = (size_t)n * n, nz = 9 * np;
     double* gb = (double*)malloc(np * sizeof(double));

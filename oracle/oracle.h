@@ -48,10 +48,11 @@ typedef struct {
 
 typedef struct {
     double lambda;         /* framelet weight, or the L2 weight when reg = 1 */
-    double mu;             /* Bregman penalty */
-    int32_t n_outer;       /* Bregman iterations */
+    double mu;             /* Bregman penalty (reg = 0), or the step of Eq. (6) (reg = 2) */
+    int32_t n_outer;       /* Bregman (reg = 0) or forward-backward (reg = 2) iterations */
     int32_t n_cg;          /* CG steps per L2 sub-problem */
-    int32_t reg;           /* 0 = tensor framelet (split Bregman), 1 = L2, Eq. (5) */
+    int32_t reg;           /* 0 = tensor framelet (split Bregman), 1 = L2, Eq. (5),
+                              2 = tensor framelet by forward-backward splitting, Eq. (6) */
     int32_t filter;        /* 1 = AIR (A^T C), 0 = plain IR (A^T) */
 } orc_params;
 

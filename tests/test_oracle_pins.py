@@ -371,3 +371,84 @@ def test_ir_mode_uses_plain_adjoint(orc):
     M0 = _dense(orc, g, geo.n, 0.0, 0)
     A = np.stack([orc.project(g, e.reshape(16, 16)).ravel() for e in np.eye(256)], axis=1)
     np.testing.assert_allclose(M0, A.T @ A, atol=1e-10 * np.abs(M0).max())
+
+
+# ----------------------------------------------------------------------------- forward-backward splitting, Eq. (6)
+
+def _dense_ops(orc, g, geo):
+    """Dense A [rays x pixels] and C [rays x rays] from the oracle's pinned operators."""
+    n, nr = geo.n, geo.n_views * geo.n_bins
+    A = np.stack([orc.project(g, e.reshape(n, n)).ravel() for e in np.eye(n * n)], axis=1)
+    C = np.stack([orc.ramp(g, e.reshape(geo.n_views, geo.n_bins)).ravel() for e in np.eye(nr)], axis=1)
+    return A, C
+
+
+@pytest.mark.parametrize("filt", [1, 0])
+def test_fbs_without_prior_is_landweber(orc, filt):
+    """lambda = 0: the proximal step is the identity (W^T W = I), so Eq. (6) is
+    the Landweber iteration X <- X - mu A'^T (A X - Y), here with dense matrices."""
+    geo, g, y = _small_problem(orc, n=12, views=16, bins=19)
+    A, C = _dense_ops(orc, g, geo)
+    At = A.T @ C if filt else A.T
+    mu = 0.5 if filt else 0.5 / np.linalg.norm(A.T @ A, 2)
+    x = np.zeros(geo.n * geo.n)
+    for _ in range(6):
+        x = x - mu * (At @ (A @ x - y.ravel()))
+    xo, res = orc.solve(g, y, 0.0, mu, 6, 0, reg=2, filter=filt)
+    assert np.linalg.norm(xo.ravel() - x) < 1e-12 * np.linalg.norm(x)
+    assert res.shape == (6,) and res[0] > 0.0
+
+
+def test_fbs_prox_with_large_lambda_is_the_low_pass_band(orc):
+    """With Y = A X0 the forward step leaves X0 unchanged; a threshold above
+    every detail coefficient keeps only band 0, and W^T of band 0 is
+    (h0^T h0) in x and y: the periodic blur [1, 4, 6, 4, 1] / 16 per axis."""
+    geo, g, _ = _small_problem(orc, n=12, views=16, bins=19)
+    x0 = np.random.default_rng(3).uniform(size=(12, 12))
+    y = orc.project(g, x0)
+    xo, _ = orc.solve(g, y, 1e6, 1.0, 1, 0, reg=2, x0=x0)
+    k = np.array([1, 4, 6, 4, 1]) / 16.0
+    blur = sum(k[a + 2] * np.roll(x0, a, axis=1) for a in range(-2, 3))
+    blur = sum(k[a + 2] * np.roll(blur, a, axis=0) for a in range(-2, 3))
+    assert np.abs(xo - blur).max() < 1e-12
+
+
+def test_fbs_converges_to_a_fixed_point(orc):
+    """With a step inside the stability bound the forward-backward map is a
+    contraction on this problem: the step norms ||X_{k+1} - X_k|| fall and the
+    last iterate is (to 1e-9) a fixed point of one more forward-backward step."""
+    geo, g, y = _small_problem(orc, n=16, views=24, bins=25)
+    x, res = orc.solve(g, y, 0.01, 1.0, 400, 0, reg=2)
+    assert res[-1] < 1e-9 * res[0]
+    assert np.all(np.diff(res[5:]) <= 1e-15)
+    x2, _ = orc.solve(g, y, 0.01, 1.0, 1, 0, reg=2, x0=x)
+    assert np.linalg.norm(x2 - x) < 1e-9 * np.linalg.norm(x)
+
+
+def test_fbs_prox_threshold_is_half_step_times_lambda(orc):
+    """One step from a consistent start (Y = A X0): X1 = W^T shrink(W X0, mu lambda / 2)
+    on the detail bands, with W built here from its filters by periodic shifts."""
+    geo, g, _ = _small_problem(orc, n=12, views=16, bins=19)
+    x0 = np.random.default_rng(5).uniform(size=(12, 12))
+    y = orc.project(g, x0)
+    lam, mu = 0.08, 0.7
+    s2 = math.sqrt(2.0)
+    h = [np.array([1, 2, 1]) / 4.0, s2 * np.array([1, 0, -1]) / 4.0, np.array([-1, 2, -1]) / 4.0]
+
+    def corr(x, f, axis):            # (H x)[n] = sum_k f[k + 1] x[n + k], periodic
+        return sum(f[k + 1] * np.roll(x, -k, axis=axis) for k in (-1, 0, 1))
+
+    def corr_t(x, f, axis):          # adjoint of corr
+        return sum(f[k + 1] * np.roll(x, k, axis=axis) for k in (-1, 0, 1))
+
+    t = mu * lam / 2.0
+    x1 = np.zeros_like(x0)
+    for my in range(3):
+        for mx in range(3):
+            z = corr(corr(x0, h[my], 0), h[mx], 1)
+            if my or mx:
+                z = np.sign(z) * np.maximum(np.abs(z) - t, 0.0)
+            x1 += corr_t(corr_t(z, h[mx], 1), h[my], 0)
+    xo, res = orc.solve(g, y, lam, mu, 1, 0, reg=2, x0=x0)
+    assert np.abs(xo - x1).max() < 1e-12
+    assert res[0] == pytest.approx(np.linalg.norm(x1 - x0), rel=1e-12)
