@@ -141,11 +141,12 @@ air_status air_framelet(air_plan plan, const float* in, float* out, int32_t batc
                         hipStream_t stream);
 
 typedef struct {
-    double lambda;     /* framelet weight (reg = 0) or L2 weight of Eq. (5) (reg = 1), >= 0 */
-    double mu;         /* Bregman penalty, > 0 (unused for reg = 1) */
-    int32_t n_outer;   /* Bregman iterations, >= 0 (unused for reg = 1) */
-    int32_t n_cg;      /* CG steps per L2 sub-problem, >= 0 */
-    int32_t reg;       /* 0 = tensor framelet via split Bregman, 1 = L2 (Eq. (5)) */
+    double lambda;     /* framelet weight (reg = 0, 2) or L2 weight of Eq. (5) (reg = 1), >= 0 */
+    double mu;         /* Bregman penalty (reg = 0) or step of Eq. (6) (reg = 2), > 0; unused for reg = 1 */
+    int32_t n_outer;   /* Bregman (reg = 0) or forward-backward (reg = 2) iterations, >= 0 */
+    int32_t n_cg;      /* CG steps per L2 sub-problem, >= 0 (unused for reg = 2) */
+    int32_t reg;       /* 0 = tensor framelet via split Bregman, 1 = L2 (Eq. (5)),
+                          2 = tensor framelet via forward-backward splitting (Eq. (6)) */
     int32_t filter;    /* 1 = AIR (A'^T = A^T C), 0 = IR (A^T) */
 } air_solve_params;
 
@@ -161,7 +162,14 @@ air_status air_solve_workspace_size(air_plan plan, int32_t batch, size_t* bytes)
  *                   v = W X + b; d = shrink(v, lambda / (2 mu)) on bands 1..8,
  *                   d = v on band 0; b = v - d
  * L2 (reg = 1): n_cg CG steps on (A'^T A + lambda I) X = A'^T Y from X.
- * resid (device, may be NULL) receives [batch][n_outer] float64 ||W X - d||_2.
+ * Forward-backward splitting (reg = 2; Methods, Eq. (6) and the proximal step):
+ *   n_outer times:  X' = X - mu A'^T (A X - Y)
+ *                   X  = W^T shrink(W X', mu lambda / 2)   (band 0 passes through)
+ *   (the data term's gradient is 2 A'^T (A X - Y), so the step is mu / 2 and the
+ *   threshold mu lambda / 2; W^T shrink W stands in for the proximal map of the
+ *   tight frame).  Stable for mu < 2 / ||A'^T A||.
+ * resid (device, may be NULL) receives [batch][n_outer] float64 ||W X - d||_2
+ * (split Bregman) or ||X_new - X_old||_2 (forward-backward).
  * ws: device, >= air_solve_workspace_size(plan, batch) bytes, 256-byte
  * aligned; it is scratch for this call only.  The plan's own workspace is
  * not used, so batch may exceed max_batch. */

@@ -244,7 +244,8 @@ class Plan:
     def solve(self, y: torch.Tensor, lam: float, mu: float, n_outer: int, n_cg: int, reg: int = 0,
               filter: int = 1, x0: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
               with_resid: bool = True):
-        """Split Bregman AIR (reg=0) or the L2 problem of Eq. (5) (reg=1).
+        """Split Bregman AIR (reg=0), the L2 problem of Eq. (5) (reg=1), or forward-backward
+        splitting of Eq. (6) (reg=2, mu = the step).
 
         Returns (X [B, n, n], resid [B, n_outer] float64 or None); asynchronous
         on the current stream."""

@@ -69,11 +69,13 @@ enum BpMode {
     BP_MATVEC = 1,    // out = acc + mu * p;  partial sums of p . out (float64)
     BP_RESIDUAL = 2,  // r = rhs - (acc + mu * x) (rhs read from `out`, r written there);
                       // p = r, padded copy of p; partial sums of r . r
+    BP_STEP = 3,      // out = x + mu * (rhs - acc): the forward step of Eq. (6), rhs = A'^T Y
 };
 struct BpArgs {
     int mode;
     float mu;
-    const float* aux;   // p (MATVEC) or x (RESIDUAL)
+    const float* aux;   // p (MATVEC) or x (RESIDUAL, STEP)
+    const float* rhs;   // STEP: A'^T Y
     float* out;         // [batch][n][n]
     float* p_out;       // RESIDUAL: p
     PadBuf pad_out;     // RESIDUAL: padded copy of p
@@ -144,6 +146,12 @@ struct TfArgs {
     double* partial;    // [batch][tiles16(n)]
 };
 hipError_t launch_tf_shrink(const TfArgs& a, int batch, hipStream_t s);
+// Proximal step of forward-backward splitting: e = shrink(W x, thr) on bands
+// 1..8 (band 0 passes through), then x_new = W^T e written over bb (= the
+// iterate X) with partial sums of (x_new - X)^2.  TfArgs: x = the forward-step
+// image, e = 9 band scratch, bb = X (in/out), thr = mu lambda / 2.
+hipError_t launch_fbs_shrink(const TfArgs& a, int batch, hipStream_t s);
+hipError_t launch_fbs_adjoint(const TfArgs& a, int batch, hipStream_t s);
 hipError_t launch_fill(float* p, size_t count, float v, hipStream_t s);
 
 // Number of 16x16 tiles of an n x n image (blocks per batch item of tile kernels).

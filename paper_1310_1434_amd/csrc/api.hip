@@ -377,10 +377,10 @@ air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const 
     if (air_status st = check_batch(p, batch, false)) return st;
     if (!Y || !X || !prm || !ws) return fail(AIR_E_INVALID, "null pointer");
     if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(AIR_E_INVALID, "workspace must be 256-byte aligned");
-    if (prm->reg != 0 && prm->reg != 1) return fail(AIR_E_INVALID, "reg must be 0 or 1");
+    if (prm->reg < 0 || prm->reg > 2) return fail(AIR_E_INVALID, "reg must be 0, 1 or 2");
     if (prm->filter != 0 && prm->filter != 1) return fail(AIR_E_INVALID, "filter must be 0 or 1");
     if (!(prm->lambda >= 0.0) || !std::isfinite(prm->lambda)) return fail(AIR_E_INVALID, "lambda must be >= 0");
-    if (prm->reg == 0 && (!(prm->mu > 0.0) || !std::isfinite(prm->mu))) return fail(AIR_E_INVALID, "mu must be > 0");
+    if (prm->reg != 1 && (!(prm->mu > 0.0) || !std::isfinite(prm->mu))) return fail(AIR_E_INVALID, "mu must be > 0");
     if (prm->n_outer < 0 || prm->n_cg < 0) return fail(AIR_E_INVALID, "iteration counts must be >= 0");
     const SolveLayout L = solve_layout(p, batch);
     if (ws_bytes < L.total) return fail(AIR_E_NOMEM, "workspace smaller than air_solve_workspace_size");
@@ -393,7 +393,7 @@ air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const 
     }
     const SolveSetup setup{prm->reg, prm->filter, prm->lambda, prm->mu, prm->n_cg};
     if (air_status st = solve_init(p, B, Y, batch, setup, s)) return st;
-    const int n_out = prm->reg == 0 ? prm->n_outer : 1;
+    const int n_out = prm->reg == 1 ? 1 : prm->n_outer;
     for (int k = 0; k < n_out; k++)
         if (air_status st = solve_outer(p, B, batch, setup, s)) return st;
     return AIR_OK;

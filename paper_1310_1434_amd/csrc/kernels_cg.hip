@@ -223,6 +223,52 @@ __global__ __launch_bounds__(256) void k_tf_shrink(TfArgs a) {
     block_partial<256>(part, a.partial + (size_t)b * nblk + blk);
 }
 
+// Forward-backward splitting, proximal step part 1: e = shrink(W x, thr), band 0 kept.
+__global__ __launch_bounds__(256) void k_fbs_shrink(TfArgs a) {
+    const int i = blockIdx.x * 16 + (threadIdx.x & 15), j = blockIdx.y * 16 + (threadIdx.x >> 4), b = blockIdx.z;
+    const int n = a.n;
+    if (i >= n || j >= n) return;
+    const size_t np = (size_t)n * n, pix = (size_t)j * n + i;
+    float z[9];
+    framelet_at(a.x + b * np, n, i, j, z);
+    float* eb = a.e + (size_t)b * 9 * np;
+    eb[pix] = z[0];
+#pragma unroll
+    for (int band = 1; band < 9; band++) {
+        const float mag = fabsf(z[band]) - a.thr;
+        eb[band * np + pix] = mag > 0.f ? copysignf(mag, z[band]) : 0.f;
+    }
+}
+
+// part 2: X_new = W^T e over X (= a.bb), partial sums of (X_new - X)^2.
+__global__ __launch_bounds__(256) void k_fbs_adjoint(TfArgs a) {
+    const int i = blockIdx.x * 16 + (threadIdx.x & 15), j = blockIdx.y * 16 + (threadIdx.x >> 4), b = blockIdx.z;
+    const int n = a.n;
+    const size_t np = (size_t)n * n;
+    double part = 0.0;
+    if (i < n && j < n) {
+        const size_t idx = b * np + (size_t)j * n + i;
+        const float xn = framelet_adj_at(a.e + (size_t)b * 9 * np, n, i, j);
+        const double dx = (double)xn - (double)a.bb[idx];
+        part = dx * dx;
+        a.bb[idx] = xn;
+    }
+    const int nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
+    block_partial<256>(part, a.partial + (size_t)b * nblk + blk);
+}
+
+hipError_t launch_fbs_shrink(const TfArgs& a, int batch, hipStream_t s) {
+    dim3 grid((a.n + 15) / 16, (a.n + 15) / 16, batch);
+    hipLaunchKernelGGL(k_fbs_shrink, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fbs_adjoint(const TfArgs& a, int batch, hipStream_t s) {
+    dim3 grid((a.n + 15) / 16, (a.n + 15) / 16, batch);
+    hipLaunchKernelGGL(k_fbs_adjoint, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_framelet_fwd(int n, const float* x, float* z, int batch, hipStream_t s) {
     dim3 grid((n + 15) / 16, (n + 15) / 16, batch);
     hipLaunchKernelGGL(k_framelet_fwd, grid, dim3(256), 0, s, x, z, n);

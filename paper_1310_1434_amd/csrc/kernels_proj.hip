@@ -449,6 +449,9 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                 a.out[ib] = qv;
                 part += (double)pv * (double)qv;
             }
+        } else if (MODE == BP_STEP) {
+            if (va) a.out[ia] = (float)fma((double)a.mu, (double)a.rhs[ia] - tot_a[q], (double)a.aux[ia]);
+            if (vb) a.out[ib] = (float)fma((double)a.mu, (double)a.rhs[ib] - tot_b[q], (double)a.aux[ib]);
         } else {  // BP_RESIDUAL
             if (va) {
                 const float r = (float)((double)a.out[ia] - fma((double)a.mu, (double)a.aux[ia], tot_a[q]));
@@ -495,6 +498,9 @@ hipError_t launch_backproject(const KGeom& g, const float* y, const BpArgs& a, i
         break;
     case BP_RESIDUAL:
         launch_bp_mode<BP_RESIDUAL, true>(g, y, a, batch, s);
+        break;
+    case BP_STEP:
+        launch_bp_mode<BP_STEP, false>(g, y, a, batch, s);
         break;
     default:
         return hipErrorInvalidValue;

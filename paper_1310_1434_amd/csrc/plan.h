@@ -191,7 +191,7 @@ struct SolveBufs {
 };
 
 struct SolveSetup {
-    int reg;        // 0 split Bregman, 1 L2
+    int reg;        // 0 split Bregman, 1 L2 (Eq. (5)), 2 forward-backward splitting (Eq. (6))
     int filter;     // 1 AIR, 0 IR
     double lambda, mu;
     int n_cg;

@@ -73,7 +73,41 @@ air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch,
     return AIR_OK;
 }
 
+// One forward-backward iteration (Eq. (6) and the framelet proximal step):
+//   X' = X + mu (g - A'^T A X)  (= X - mu A'^T (A X - Y), g = A'^T Y from solve_init)
+//   X  = W^T shrink(W X', mu lambda / 2);  resid = ||X_new - X_old||_2
+static air_status fbs_iteration(air_plan p, const SolveBufs& B, int batch, const SolveSetup& st, hipStream_t s) {
+    const KGeom kg = p->kgeom();
+    const int n = p->g.n, rows = batch * p->g.n_views;
+    const int grp = image_group(batch);
+    AIR_K(AIR_K_OTHER, launch_pad(kg, B.X, PadBuf{B.pad}, batch, s));
+    AIR_K(AIR_K_PROJECT, launch_project(kg, PadBuf{B.pad}, B.s1, batch, false, s));
+    if (st.filter)
+        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), B.s1, B.s2, rows, p->ds, RAMP_PRE | RAMP_POST, grp, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(kg, B.s1, B.s2, batch, 2, grp, s));
+    BpArgs a{};
+    a.mode = BP_STEP;
+    a.mu = (float)st.mu;
+    a.aux = B.X;
+    a.rhs = B.g;
+    a.out = B.r;
+    AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, B.s2, a, batch, s));
+    TfArgs t{};
+    t.n = n;
+    t.x = B.r;
+    t.e = B.e;
+    t.bb = B.X;
+    t.thr = (float)(st.mu * st.lambda / 2.0);
+    t.partial = B.part;
+    AIR_K(AIR_K_FRAMELET, launch_fbs_shrink(t, batch, s));
+    AIR_K(AIR_K_FRAMELET, launch_fbs_adjoint(t, batch, s));
+    AIR_K(AIR_K_FRAMELET, launch_finalize(FIN_RESID, B.part, tiles16(n), batch, nullptr, nullptr, B.resid,
+                                          B.resid_stride, B.iters, s));
+    return AIR_OK;
+}
+
 air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSetup& st, hipStream_t s) {
+    if (st.reg == 2) return fbs_iteration(p, B, batch, st, s);
     const KGeom kg = p->kgeom();
     const RampTables rt = p->ramp_tables();
     const int n = p->g.n, rows = batch * p->g.n_views, nblk = tiles16(n), nblk_bp = bp_blocks(n);

@@ -368,3 +368,37 @@ def test_c5_solve_against_stored_oracle(air, torch_mod, record, c5_case):
     record("rel_l2_final", e)
     assert e < 1e-4
     np.testing.assert_allclose(host(resid)[0], ref["resid"], rtol=1e-2)
+
+
+# ----------------------------------------------------------------------------- forward-backward splitting
+
+def _ir_step(air, torch_mod, g):
+    from paper_1310_1434_amd import quality as Q
+    plan = air.Plan(g)
+    return 1.0 / Q.top_eigenvalue(plan, 0)
+
+
+@pytest.mark.parametrize("name,filt", [("c1", 1), ("c1", 0), ("ragged", 1)])
+def test_solve_fbs_parity(air, torch_mod, orc, record, name, filt):
+    """Eq. (6) with the framelet proximal step: iterate and step-norm history
+    against the oracle (AIR with A'^T, IR with A^T at step 1 / ||A^T A||)."""
+    g = geom(name)
+    y = sino_for(name, 2).astype(np.float32)
+    mu = 1.0 if filt else _ir_step(air, torch_mod, g)
+    plan = air.Plan(g)
+    x, r = plan.solve(dev(torch_mod, y[None]), 0.005, mu, 15, 0, reg=2, filter=filt)
+    xr, rr = orc.solve(orc.Geom(g), y.astype(np.float64), 0.005, mu, 15, 0, reg=2, filter=filt)
+    record(f"rel_l2_fbs_{name}_{filt}", rel(host(x)[0], xr))
+    assert rel(host(x)[0], xr) < 1e-4
+    assert rel(r.cpu().numpy()[0], rr) < 1e-3
+
+
+def test_solve_fbs_batch_invariance(air, torch_mod):
+    g = geom("c1")
+    plan = air.Plan(g)
+    ys = np.stack([sino_for("c1", s) for s in range(3)]).astype(np.float32)
+    xb, rb = plan.solve(dev(torch_mod, ys), 0.005, 1.0, 5, 0, reg=2)
+    for b in range(3):
+        x1, r1 = plan.solve(dev(torch_mod, ys[b:b + 1]), 0.005, 1.0, 5, 0, reg=2)
+        assert np.array_equal(host(x1)[0], host(xb)[b])
+        assert np.array_equal(r1.cpu().numpy()[0], rb.cpu().numpy()[b])
