@@ -37,7 +37,13 @@ class _Geom(ctypes.Structure):
     _fields_ = [("beam", ctypes.c_int32), ("n", ctypes.c_int32), ("pixel", ctypes.c_double),
                 ("n_views", ctypes.c_int32), ("n_bins", ctypes.c_int32),
                 ("cosv", ctypes.c_void_p), ("sinv", ctypes.c_void_p),
-                ("bin", ctypes.c_double), ("sod", ctypes.c_double), ("sdd", ctypes.c_double)]
+                ("bin", ctypes.c_double), ("sod", ctypes.c_double), ("sdd", ctypes.c_double),
+                ("ramp", ctypes.c_int32)]
+
+
+# filtration C (orc_geom.ramp): window in bits 0-3, symmetric cosine weighting in bit 4
+RAMP_WINDOWS = {"ram-lak": 0, "shepp-logan": 1, "hann": 2}
+RAMP_COSINE = 16
 
 
 class _Params(ctypes.Structure):
@@ -67,6 +73,8 @@ def _load():
             "orc_apply_normal": [G, P, ctypes.c_double, ctypes.c_int32, P],
             "orc_cg": [G, P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P],
             "orc_solve": [G, P, ctypes.POINTER(_Params), P, P, P],
+            "orc_ramp_taps_kind": [ctypes.c_int32, ctypes.c_int32, P],
+            "orc_ramp_weights": [G, P],
         }
         for name, args in sigs.items():
             fn = getattr(lib, name)
@@ -94,8 +102,9 @@ def _ptr(a: np.ndarray):
 class Geom:
     """Oracle view of a scan geometry (any object with the ``synth.Geometry`` fields)."""
 
-    def __init__(self, geom):
+    def __init__(self, geom, ramp: int = 0):
         self.beam = 0 if geom.beam == "parallel" else 1
+        self.ramp = int(ramp)
         self.n = int(geom.n)
         self.n_views = int(geom.n_views)
         self.n_bins = int(geom.n_bins)
@@ -103,7 +112,7 @@ class Geom:
         self._sin = _f64(geom.view_sin)
         self._s = _Geom(self.beam, self.n, float(geom.pixel), self.n_views, self.n_bins,
                         self._cos.ctypes.data, self._sin.ctypes.data, float(geom.bin),
-                        float(geom.sod), float(geom.sdd))
+                        float(geom.sod), float(geom.sdd), self.ramp)
 
     @property
     def ref(self):
@@ -151,6 +160,18 @@ def ramp_taps(n_bins: int) -> np.ndarray:
     r = np.empty(n_bins)
     _load().orc_ramp_taps(int(n_bins), _ptr(r))
     return r
+
+
+def ramp_taps_kind(kind: int, n_bins: int) -> np.ndarray:
+    r = np.empty(n_bins)
+    _check(_load().orc_ramp_taps_kind(int(kind), int(n_bins), _ptr(r)), "ramp_taps_kind")
+    return r
+
+
+def ramp_weights(g: Geom) -> np.ndarray:
+    w = np.empty(g.n_bins)
+    _check(_load().orc_ramp_weights(g.ref, _ptr(w)), "ramp_weights")
+    return w
 
 
 def ramp(g: Geom, y) -> np.ndarray:

@@ -38,6 +38,7 @@ static int geom_ok(const orc_geom* g) {
     if (!g || g->n <= 0 || g->n_views <= 0 || g->n_bins <= 0) return 0;
     if (!(g->pixel > 0.0) || !(g->bin > 0.0) || !g->cosv || !g->sinv) return 0;
     if (g->beam == 1 && !(g->sdd > g->sod && g->sod > 0.0)) return 0;
+    if ((g->ramp & ~31) != 0 || (g->ramp & 15) > 2) return 0;
     return g->beam == 0 || g->beam == 1;
 }
 
@@ -200,25 +201,74 @@ void orc_ramp_taps(int32_t n_bins, double* r) {
     }
 }
 
-/* C = kappa R per view: linear (non-circular) convolution with the taps,
- * truncated to the detector, kappa = pi / (n_views * pixel^2). */
+/* Apodised ramp windows (Methods: C is any symmetric positive semi-definite
+ * filtration, Eq. (2)), in the same dimensionless units as the Ram-Lak taps:
+ *   kind 0  Ram-Lak      frequency response |w| / (2 pi)
+ *   kind 1  Shepp-Logan  r(m) = -2 / (pi^2 (4 m^2 - 1)),  response |sin(w / 2)| / pi
+ *   kind 2  Hann         r(m) = r_RL(m) / 2 + (r_RL(m - 1) + r_RL(m + 1)) / 4,
+ *                        response |w| / (2 pi) * (1 + cos w) / 2 */
+int orc_ramp_taps_kind(int32_t kind, int32_t n_bins, double* r) {
+    if (n_bins < 1 || !r) return -1;
+    if (kind == 0) {
+        orc_ramp_taps(n_bins, r);
+        return 0;
+    }
+    if (kind == 1) {
+        for (int m = 0; m < n_bins; m++) r[m] = -2.0 / (ORC_PI * ORC_PI * (4.0 * (double)m * (double)m - 1.0));
+        return 0;
+    }
+    if (kind == 2) {
+        double* rl = (double*)malloc(((size_t)n_bins + 1) * sizeof(double));
+        if (!rl) return -3;
+        orc_ramp_taps(n_bins + 1, rl);
+        for (int m = 0; m < n_bins; m++) {
+            const double left = rl[m == 0 ? 1 : m - 1];     /* r_RL is even: r(-1) = r(1) */
+            r[m] = 0.5 * rl[m] + 0.25 * (left + rl[m + 1]);
+        }
+        free(rl);
+        return 0;
+    }
+    return -1;
+}
+
+/* Fan-beam cosine weights of a flat detector, w_k = sdd / sqrt(sdd^2 + u_k^2)
+ * (the cosine of the ray's angle to the central ray); 1 for parallel beams or
+ * when the weighting bit is off. */
+int orc_ramp_weights(const orc_geom* g, double* w) {
+    if (!geom_ok(g) || !w) return -1;
+    const int on = (g->ramp & 16) && g->beam == 1;
+    for (int k = 0; k < g->n_bins; k++) {
+        const double u = ((double)k - 0.5 * (g->n_bins - 1)) * g->bin;
+        w[k] = on ? g->sdd / sqrt(g->sdd * g->sdd + u * u) : 1.0;
+    }
+    return 0;
+}
+
+/* C = kappa D^(1/2) R D^(1/2) per view: D the cosine weights (identity unless
+ * requested), R the symmetric Toeplitz matrix of the window's taps, applied as
+ * a linear (non-circular) convolution truncated to the detector,
+ * kappa = pi / (n_views * pixel^2).  C stays symmetric positive semi-definite. */
 int orc_ramp(const orc_geom* g, const double* y, double* yf) {
     if (!geom_ok(g) || !y || !yf) return -1;
     const int nb = g->n_bins, nv = g->n_views;
     double* r = (double*)malloc((size_t)nb * sizeof(double));
-    if (!r) return -3;
-    orc_ramp_taps(nb, r);
+    double* w = (double*)malloc((size_t)nb * sizeof(double));
+    if (!r || !w) { free(r); free(w); return -3; }
+    int rc = orc_ramp_taps_kind(g->ramp & 15, nb, r);
+    if (rc == 0) rc = orc_ramp_weights(g, w);
+    if (rc) { free(r); free(w); return rc; }
     const double kappa = ORC_PI / ((double)nv * g->pixel * g->pixel);
 #pragma omp parallel for schedule(static)
     for (int v = 0; v < nv; v++) {
         const double* row = y + (size_t)v * nb;
         for (int m = 0; m < nb; m++) {
             double s = 0.0;
-            for (int k = 0; k < nb; k++) s += r[abs(m - k)] * row[k];
-            yf[(size_t)v * nb + m] = kappa * s;
+            for (int k = 0; k < nb; k++) s += r[abs(m - k)] * sqrt(w[k]) * row[k];
+            yf[(size_t)v * nb + m] = kappa * sqrt(w[m]) * s;
         }
     }
     free(r);
+    free(w);
     return 0;
 }
 

@@ -44,6 +44,8 @@ typedef struct {
     double bin;            /* detector pitch, mm */
     double sod;            /* source to isocentre, mm (fan) */
     double sdd;            /* source to detector, mm (fan) */
+    int32_t ramp;          /* filtration C: bits 0-3 window (0 Ram-Lak, 1 Shepp-Logan, 2 Hann),
+                              bit 4 symmetric cosine weighting (fan beam) */
 } orc_geom;
 
 typedef struct {
@@ -66,7 +68,9 @@ int orc_tables(const orc_geom* g, int8_t* axis, int32_t* lo, int32_t* hi);
 
 int orc_project(const orc_geom* g, const double* x, double* y);          /* y = A x   */
 int orc_backproject(const orc_geom* g, const double* y, double* x);      /* x = A^T y */
-void orc_ramp_taps(int32_t n_bins, double* r);                           /* r[0..n_bins-1] */
+void orc_ramp_taps(int32_t n_bins, double* r);                           /* Ram-Lak r[0..n_bins-1] */
+int  orc_ramp_taps_kind(int32_t kind, int32_t n_bins, double* r);        /* window `kind` */
+int  orc_ramp_weights(const orc_geom* g, double* w);                     /* cosine weights [n_bins] */
 int orc_ramp(const orc_geom* g, const double* y, double* yf);            /* yf = C y  */
 int orc_filtered_backproject(const orc_geom* g, const double* y, double* x, int32_t filter);
 int orc_framelet(int32_t n, const double* x, double* z);                 /* z = W x   */
