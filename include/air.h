@@ -80,12 +80,32 @@ typedef struct {
 
 typedef struct air_plan_s* air_plan;
 
+/* Plan flags: the filtration C of AIR (Methods, Eqs. (2)-(3): any symmetric
+ * positive semi-definite C = P^T P; the analytic method's filter is the
+ * natural choice).  C = kappa D^(1/2) R D^(1/2) per view, R the symmetric
+ * Toeplitz matrix of a ramp window's taps (dimensionless, see air_ramp):
+ *   AIR_RAMP_RAM_LAK      r(0) = 1/4, r(odd m) = -1/(pi m)^2, else 0   (response |w| / 2 pi)
+ *   AIR_RAMP_SHEPP_LOGAN  r(m) = -2 / (pi^2 (4 m^2 - 1))               (response |sin(w/2)| / pi)
+ *   AIR_RAMP_HANN         Ram-Lak apodised by (1 + cos w) / 2:
+ *                         r(m) / 2 + (r(m - 1) + r(m + 1)) / 4
+ * and D the identity, or with AIR_RAMP_COSINE_WEIGHTED the flat-detector
+ * fan-beam cosine weights D = diag(sdd / sqrt(sdd^2 + u_k^2)) (identity for
+ * parallel beams), applied on both sides so that C stays symmetric. */
+enum {
+    AIR_RAMP_RAM_LAK = 0,
+    AIR_RAMP_SHEPP_LOGAN = 1,
+    AIR_RAMP_HANN = 2,
+    AIR_RAMP_WINDOW_MASK = 15,
+    AIR_RAMP_COSINE_WEIGHTED = 16
+};
+
 /* Create a plan: validates the geometry and builds, on the host in float64,
  * the per-ray Joseph tables (driving axis, index range, intercept, slope,
  * step length) and the ramp taps.  Nothing touches the GPU.
  * max_batch bounds the batch of the operator calls that use the plan's
  * workspace (air_project, air_filtered_backproject, air_ramp,
- * air_normal_apply).  flags must be 0. */
+ * air_normal_apply).  flags: a ramp window, optionally or-ed with
+ * AIR_RAMP_COSINE_WEIGHTED; any other bit is AIR_E_INVALID. */
 air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_precision prec,
                            uint32_t flags, air_plan* out);
 
@@ -111,11 +131,11 @@ void air_plan_destroy(air_plan plan);
  * 1 <= batch <= max_batch. */
 air_status air_project(air_plan plan, const float* x, float* y, int32_t batch, hipStream_t stream);
 
-/* y' = C y, C = kappa R per view, R the symmetric Toeplitz Ram-Lak matrix
- * (r(0) = 1/4, r(odd m) = -1/(pi m)^2, r(even m != 0) = 0), kappa =
- * pi / (n_views pixel^2); linear convolution truncated to the detector
- * (paper: Methods, Eq. (2): C is a filtration diagonal in Fourier space).
- * In-place (y == yf) is not allowed. */
+/* y' = C y, C = kappa D^(1/2) R D^(1/2) per view (the plan's window and
+ * weighting, see the plan flags; Ram-Lak and D = I by default), kappa =
+ * pi / (n_views pixel^2); R acts as a linear convolution truncated to the
+ * detector (paper: Methods, Eq. (2): C is a filtration diagonal in Fourier
+ * space).  In-place (y == yf) is not allowed. */
 air_status air_ramp(air_plan plan, const float* y, float* yf, int32_t batch, hipStream_t stream);
 
 /* x = A'^T y = A^T C y (filter = 1, the filtered adjoint of AIR), or the plain

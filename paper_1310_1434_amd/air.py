@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libair.so")
 
 AIR_OK, AIR_E_INVALID, AIR_E_UNSUPPORTED, AIR_E_NOMEM, AIR_E_HIP, AIR_E_NONFINITE = 0, -1, -2, -3, -4, -5
 PRECISIONS = {"fp32": 0, "mixed_f16": 1, "mixed_bf16": 2}
+# plan flags: ramp window (bits 0-3) and symmetric cosine weighting of C
+RAMP_WINDOWS = {"ram-lak": 0, "shepp-logan": 1, "hann": 2}
+AIR_RAMP_COSINE_WEIGHTED = 16
 
 
 class AirError(RuntimeError):
@@ -143,7 +146,13 @@ class Plan:
     n_views, n_bins, bin, sod, sdd, view_cos, view_sin (float64 arrays).
     """
 
-    def __init__(self, geom, max_batch: int = 1, precision: str = "fp32", device="cuda:0"):
+    def __init__(self, geom, max_batch: int = 1, precision: str = "fp32", device="cuda:0",
+                 ramp: str = "ram-lak", cosine_weight: bool = False):
+        """ramp / cosine_weight select the filtration C (the plan flags of air.h)."""
+        if ramp not in RAMP_WINDOWS:
+            raise ValueError(f"ramp must be one of {sorted(RAMP_WINDOWS)}")
+        flags = RAMP_WINDOWS[ramp] | (AIR_RAMP_COSINE_WEIGHTED if cosine_weight else 0)
+        self.ramp_window, self.cosine_weight = ramp, bool(cosine_weight)
         self.device = torch.device(device)
         self.n, self.n_views, self.n_bins = int(geom.n), int(geom.n_views), int(geom.n_bins)
         self.precision = precision
@@ -152,7 +161,7 @@ class Plan:
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         h = ctypes.c_void_p()
-        _check(lib.air_plan_create(ctypes.byref(g), self.max_batch, PRECISIONS[precision], 0, ctypes.byref(h)),
+        _check(lib.air_plan_create(ctypes.byref(g), self.max_batch, PRECISIONS[precision], flags, ctypes.byref(h)),
                "air_plan_create")
         self._h = h
         size = ctypes.c_size_t()

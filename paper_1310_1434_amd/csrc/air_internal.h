@@ -100,6 +100,7 @@ struct RampTables {
     int n_frag;                // fragments per term (indexed by (k0 - n0 - dmin) / 16)
     int dmin;
     float out_scale;           // kappa * 2^-12 for the 16-bit modes
+    const float* wsq;          // [ds] D^(1/2) of a cosine-weighted C (applied before and after R), or null
 };
 // scale: 0 = C y;  RAMP_POST = S C y;  RAMP_PRE | RAMP_POST = S C S y  (S = diag(step)).
 // Input rows [batch * n_views][ds].  Output: the same layout when grp == 0, else

@@ -84,7 +84,9 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
     if (!out) return fail(AIR_E_INVALID, "out is null");
     *out = nullptr;
     if (!geom) return fail(AIR_E_INVALID, "geometry is null");
-    if (flags != 0) return fail(AIR_E_INVALID, "flags must be 0");
+    if ((flags & ~(uint32_t)(AIR_RAMP_WINDOW_MASK | AIR_RAMP_COSINE_WEIGHTED)) != 0 ||
+        (flags & AIR_RAMP_WINDOW_MASK) > AIR_RAMP_HANN)
+        return fail(AIR_E_INVALID, "unknown plan flags");
     if (geom->beam != AIR_PARALLEL && geom->beam != AIR_FAN_FLAT) return fail(AIR_E_INVALID, "unknown beam");
     if (geom->n < 1 || geom->n_views < 1 || geom->n_bins < 1) return fail(AIR_E_INVALID, "sizes must be >= 1");
     if (geom->n > kMaxN) return fail(AIR_E_UNSUPPORTED, "n exceeds 16384");
@@ -142,9 +144,20 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
             p->views[2 * v] = (float)g.cosv[v];
             p->views[2 * v + 1] = (float)g.sinv[v];
         }
+        p->ramp_window = (int)(flags & AIR_RAMP_WINDOW_MASK);
+        p->cos_weight = (flags & AIR_RAMP_COSINE_WEIGHTED) != 0;
         std::vector<double> r;
-        ramp_taps64(g.n_bins, r);
+        ramp_taps64(g.n_bins, p->ramp_window, r);
         const int ds = p->ds;
+        if (p->cos_weight) {
+            // D^(1/2), D = diag(sdd / sqrt(sdd^2 + u_k^2)) for a flat fan-beam detector, identity for parallel beams
+            p->wsq.assign(ds, 0.f);
+            for (int k = 0; k < g.n_bins; k++) {
+                const double u = ((double)k - 0.5 * (double)(g.n_bins - 1)) * g.bin;
+                const double w = g.beam == AIR_FAN_FLAT ? g.sdd / std::sqrt(g.sdd * g.sdd + u * u) : 1.0;
+                p->wsq[k] = (float)std::sqrt(w);
+            }
+        }
         p->taps32.assign(2 * (size_t)ds, 0.f);
         for (int idx = 0; idx < 2 * ds; idx++) {
             const int d = std::abs(idx - ds);
@@ -186,6 +199,7 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
         p->off_views = c.take(p->views.size() * sizeof(float));
         p->off_taps = c.take(p->taps32.size() * sizeof(float));
         for (int t = 0; t < p->n_terms; t++) p->off_frag[t] = c.take(p->frag[t].size() * sizeof(uint16_t));
+        if (p->cos_weight) p->off_wsq = c.take(p->wsq.size() * sizeof(float));
         const size_t mb = (size_t)max_batch;
         p->off_pad = c.take((mb + 7) / 8 * 8 * 2 * g.n * p->line * sizeof(float));   // grouped padded copies
         p->off_s1 = c.take(mb * g.n_views * ds * sizeof(float));
@@ -223,6 +237,8 @@ air_status air_plan_bind_workspace(air_plan p, void* dev, size_t bytes, hipStrea
     for (int t = 0; t < p->n_terms; t++)
         AIR_HIP(hipMemcpyAsync(ws + p->off_frag[t], p->frag[t].data(), p->frag[t].size() * sizeof(uint16_t),
                                hipMemcpyHostToDevice, s));
+    if (p->cos_weight)
+        AIR_HIP(hipMemcpyAsync(ws + p->off_wsq, p->wsq.data(), p->wsq.size() * sizeof(float), hipMemcpyHostToDevice, s));
     AIR_HIP(hipStreamSynchronize(s));
     p->ws = ws;
     return AIR_OK;

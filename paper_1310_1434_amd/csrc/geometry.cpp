@@ -19,6 +19,7 @@
 #include "geometry.h"
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 
 namespace air {
@@ -62,12 +63,17 @@ inline double t_at(const GeomHost& g, const Ray64& r, double slope, int a) {
 
 }  // namespace
 
-void ramp_taps64(int n_bins, std::vector<double>& r) {
+void ramp_taps64(int n_bins, int window, std::vector<double>& r) {
     const double pi = 3.14159265358979323846;
+    auto ram_lak = [pi](int m) {
+        m = std::abs(m);
+        return m == 0 ? 0.25 : ((m & 1) ? -1.0 / (pi * pi * (double)m * (double)m) : 0.0);
+    };
     r.assign(n_bins, 0.0);
     for (int m = 0; m < n_bins; m++) {
-        if (m == 0) r[m] = 0.25;
-        else if (m & 1) r[m] = -1.0 / (pi * pi * (double)m * (double)m);
+        if (window == 1) r[m] = -2.0 / (pi * pi * (4.0 * (double)m * (double)m - 1.0));   // Shepp-Logan
+        else if (window == 2) r[m] = 0.5 * ram_lak(m) + 0.25 * (ram_lak(m - 1) + ram_lak(m + 1));   // Hann
+        else r[m] = ram_lak(m);
     }
 }
 

@@ -56,7 +56,11 @@ struct GeomHost {
 std::string build_ray_tables(const GeomHost& g, std::vector<RayEntry>& rays, std::vector<float>& step,
                              std::vector<int8_t>& axis, std::vector<int32_t>& lo, std::vector<int32_t>& hi);
 
-// Ram-Lak taps r(0..n_bins-1), float64.
-void ramp_taps64(int n_bins, std::vector<double>& r);
+// Taps r(0..n_bins-1) of the ramp window, float64, dimensionless (the
+// detector pitch and the view count enter through kappa):
+//   0 Ram-Lak      r(0) = 1/4, r(odd m) = -1/(pi m)^2, r(even m != 0) = 0
+//   1 Shepp-Logan  r(m) = -2 / (pi^2 (4 m^2 - 1))
+//   2 Hann         Ram-Lak times (1 + cos w) / 2 in frequency: r/2 + (r(m-1) + r(m+1))/4
+void ramp_taps64(int n_bins, int window, std::vector<double>& r);
 
 }  // namespace air

@@ -34,7 +34,8 @@ __device__ __forceinline__ size_t ramp_out_index(int row, int col, int ds, int n
 template <int SCALE>
 __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, float* __restrict__ yf,
                                                   const float* __restrict__ taps, const float* __restrict__ step,
-                                                  int n_views, int rows, int ds, int grp) {
+                                                  const float* __restrict__ wsq, int n_views, int rows, int ds,
+                                                  int grp) {
     extern __shared__ float T[];   // [2 ds]: T[d + ds] = kappa r(|d|)
     for (int i = threadIdx.x; i < 2 * ds; i += 256) T[i] = taps[i];
     __syncthreads();
@@ -57,6 +58,13 @@ __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, f
             av.z *= sv.z;
             av.w *= sv.w;
         }
+        if (wsq) {      // cosine-weighted C: D^(1/2) before R
+            const float4 wv = *reinterpret_cast<const float4*>(wsq + k0 + 4 * slot);
+            av.x *= wv.x;
+            av.y *= wv.y;
+            av.z *= wv.z;
+            av.w *= wv.w;
+        }
         if (!mvalid) av = make_float4(0.f, 0.f, 0.f, 0.f);
         // MFMA #q uses actual k = k0 + 4 slot + q in this lane's slot
         const int d = k0 + 4 * slot - ncol + ds;
@@ -76,6 +84,10 @@ __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, f
         const int row = rbase + r;
         if (row < rows) {
             float o0 = acc0[r], o1 = acc1[r];
+            if (wsq) {      // and D^(1/2) after
+                o0 *= wsq[ncol];
+                o1 *= wsq[ncol + 16];
+            }
             if (SCALE & RAMP_POST) {
                 const float* so = step + (size_t)(row % n_views) * ds;
                 o0 *= so[ncol];
@@ -110,6 +122,12 @@ __global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y,
             const float4 s1 = *reinterpret_cast<const float4*>(srow + k0 + 8 * slot + 4);
             a0.x *= s0.x; a0.y *= s0.y; a0.z *= s0.z; a0.w *= s0.w;
             a1.x *= s1.x; a1.y *= s1.y; a1.z *= s1.z; a1.w *= s1.w;
+        }
+        if (t.wsq) {    // cosine-weighted C: D^(1/2) before R
+            const float4 w0 = *reinterpret_cast<const float4*>(t.wsq + k0 + 8 * slot);
+            const float4 w1 = *reinterpret_cast<const float4*>(t.wsq + k0 + 8 * slot + 4);
+            a0.x *= w0.x; a0.y *= w0.y; a0.z *= w0.z; a0.w *= w0.w;
+            a1.x *= w1.x; a1.y *= w1.y; a1.z *= w1.z; a1.w *= w1.w;
         }
         if (!mvalid) {
             a0 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -175,6 +193,10 @@ __global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y,
         if (row < rows) {
             float o0 = t.out_scale * fmaf(accB0[r], cross, accA0[r]);
             float o1 = t.out_scale * fmaf(accB1[r], cross, accA1[r]);
+            if (t.wsq) {    // and D^(1/2) after
+                o0 *= t.wsq[ncol];
+                o1 *= t.wsq[ncol + 16];
+            }
             if (SCALE & RAMP_POST) {
                 const float* so = t.step + (size_t)(row % t.n_views) * ds;
                 o0 *= so[ncol];
@@ -192,7 +214,7 @@ static hipError_t launch_ramp_scaled(int prec, const RampTables& t, const float*
     dim3 grid((rows + 63) / 64, ds / 32), block(256);
     if (prec == AIR_FP32) {
         hipLaunchKernelGGL(k_ramp_f32<SCALE>, grid, block, 2 * ds * sizeof(float), s, y, yf, t.taps32, t.step,
-                           t.n_views, rows, ds, grp);
+                           t.wsq, t.n_views, rows, ds, grp);
     } else if (prec == AIR_MIXED_F16) {
         hipLaunchKernelGGL((k_ramp_split<AIR_MIXED_F16, SCALE>), grid, block, 0, s, y, yf, t, rows, ds, grp);
     } else if (prec == AIR_MIXED_BF16) {

@@ -46,10 +46,13 @@ struct air_plan_s {
     std::vector<int32_t> lo, hi;
     std::vector<float> views;      // interleaved (cos, sin) as float
     std::vector<float> taps32;     // [2 ds]
+    int ramp_window = 0;           // 0 Ram-Lak, 1 Shepp-Logan, 2 Hann
+    bool cos_weight = false;       // symmetric fan-beam cosine weighting of C
+    std::vector<float> wsq;        // [ds] sqrt of the cosine weights (0 in the padding), if cos_weight
     std::vector<uint16_t> frag[3];
     int n_terms = 0, n_frag = 0, dmin = 0;
     // workspace layout (bytes)
-    size_t off_rays = 0, off_step = 0, off_views = 0, off_taps = 0, off_frag[3] = {0, 0, 0};
+    size_t off_rays = 0, off_step = 0, off_views = 0, off_taps = 0, off_frag[3] = {0, 0, 0}, off_wsq = 0;
     size_t off_pad = 0, off_s1 = 0, off_s2 = 0, total = 0;
     char* ws = nullptr;
     // per-kernel event timing (air_kernel_timing_enable)
@@ -110,6 +113,7 @@ struct air_plan_s {
         t.n_frag = n_frag;
         t.dmin = dmin;
         t.out_scale = (float)(kappa / 4096.0);
+        t.wsq = cos_weight ? reinterpret_cast<const float*>(ws + off_wsq) : nullptr;
         return t;
     }
     template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }

@@ -402,3 +402,50 @@ def test_solve_fbs_batch_invariance(air, torch_mod):
         x1, r1 = plan.solve(dev(torch_mod, ys[b:b + 1]), 0.005, 1.0, 5, 0, reg=2)
         assert np.array_equal(host(x1)[0], host(xb)[b])
         assert np.array_equal(r1.cpu().numpy()[0], rb.cpu().numpy()[b])
+
+
+# ----------------------------------------------------------------------------- filtration variants
+
+_VARIANTS = [("shepp-logan", False), ("hann", False), ("ram-lak", True), ("hann", True)]
+
+
+def _flags(orc, ramp, cw):
+    return orc.RAMP_WINDOWS[ramp] | (orc.RAMP_COSINE if cw else 0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed_f16", "mixed_bf16"])
+@pytest.mark.parametrize("ramp,cw", _VARIANTS)
+@pytest.mark.parametrize("name", ["ragged", "c1"])
+def test_ramp_variant_parity(air, torch_mod, orc, record, name, ramp, cw, prec):
+    """C = kappa D^(1/2) R D^(1/2) with the Shepp-Logan / Hann windows and the
+    fan-beam cosine weighting (identity for the parallel-beam c1)."""
+    g = geom(name)
+    y = sino_for(name).astype(np.float32)
+    plan = air.Plan(g, max_batch=1, precision=prec, ramp=ramp, cosine_weight=cw)
+    og = orc.Geom(g, ramp=_flags(orc, ramp, cw))
+    yf = host(plan.ramp(dev(torch_mod, y[None])))[0]
+    e = rel(yf, orc.ramp(og, y.astype(np.float64)))
+    record(f"rel_l2_C_{ramp}_{int(cw)}_{prec}", e)
+    assert e < 1e-5, e
+    if prec == "fp32":
+        x = host(plan.filtered_backproject(dev(torch_mod, y[None]), filter=1))[0]
+        assert rel(x, orc.filtered_backproject(og, y.astype(np.float64), 1)) < 1e-5
+
+
+def test_variant_filtration_at_c2_and_in_a_solve(air, torch_mod, orc, record):
+    """Hann window with cosine weighting: A'^T at full C2 size, and a split
+    Bregman solve on the ragged fan geometry, against the oracle."""
+    flags = _flags(orc, "hann", True)
+    g = geom("c2")
+    y = sino_for("c2").astype(np.float32)
+    plan = air.Plan(g, ramp="hann", cosine_weight=True)
+    x = host(plan.filtered_backproject(dev(torch_mod, y[None]), filter=1))[0]
+    e = rel(x, orc.filtered_backproject(orc.Geom(g, ramp=flags), y.astype(np.float64), 1))
+    record("rel_l2_AtC_c2_hann_cos", e)
+    assert e < 1e-5
+    g = geom("ragged")
+    y = sino_for("ragged", 3).astype(np.float32)
+    plan = air.Plan(g, ramp="hann", cosine_weight=True)
+    xs, _ = plan.solve(dev(torch_mod, y[None]), 0.005, 1.0, 4, 4)
+    xr, _ = orc.solve(orc.Geom(g, ramp=flags), y.astype(np.float64), 0.005, 1.0, 4, 4)
+    assert rel(host(xs)[0], xr) < 1e-4

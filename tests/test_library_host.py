@@ -101,7 +101,12 @@ def test_plan_argument_validation(air):
         assert not h.value
     assert _create(air, base, max_batch=0)[0] == air.AIR_E_INVALID
     assert _create(air, base, prec=7)[0] == air.AIR_E_INVALID
-    assert _create(air, base, flags=1)[0] == air.AIR_E_INVALID
+    for bad_flags in (3, 15, 32, 1 << 31, 16 | 3):
+        assert _create(air, base, flags=bad_flags)[0] == air.AIR_E_INVALID, bad_flags
+    for good in (0, 1, 2, 16, 17, 18):
+        rc, h = _create(air, base, flags=good)
+        assert rc == air.AIR_OK, (good, air.lib.air_last_error())
+        air.lib.air_plan_destroy(h)
 
     class NonUnit:
         beam, n, pixel, n_views, n_bins, bin, sod, sdd = "parallel", 8, 1.0, 2, 9, 1.0, 0.0, 0.0
