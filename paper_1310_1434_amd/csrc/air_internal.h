@@ -46,9 +46,24 @@ int image_group(int batch);
 // zeros.  A pair keeps the projector's gathers at 16 bytes while the working
 // set of one pair of 512^2 images (4 MB) still fits an XCD's L2.
 int pad_group(int batch);
+// Mixed-precision plans keep the padded copies as float16 instead:
+// [ceil(batch / P)][2][n][line][P] halves with P = pad_group16(batch) in
+// {1, 2, 4} (four images per 16-byte gather; the same working set as a float32
+// pair), image b holding round_to_half(scale[b] * x) with scale[b] a power of
+// two chosen from max |x| (so the largest value lands in [2^13, 2^14)).  The
+// projector multiplies its float32 sums by 1 / scale[b], exactly.
+int pad_group16(int batch);
 struct PadBuf {
-    float* base;
+    float* base = nullptr;           // float32 copies, or
+    uint16_t* half = nullptr;        // float16 copies (when set)
+    float* scale = nullptr;          // [batch] their power-of-two scales
 };
+// Block partial maxima of |x| per image ([batch][tiles16(n)], as float64), and
+// the float16 scale per image from them: 2^(14 - e) with max = m 2^e, m in [0.5, 1)
+// (1 if the image is zero or not finite).
+hipError_t launch_absmax(int n, const float* x, double* partial, int batch, hipStream_t s);
+hipError_t launch_pad_scale(const double* partial, int nblk, int batch, float* scale, hipStream_t s);
+hipError_t launch_pad16(const KGeom& g, const float* x, PadBuf pad, int batch, hipStream_t s);
 
 // ---- kernel launchers (kernels_*.hip) -------------------------------------------------
 hipError_t launch_pad(const KGeom& g, const float* x, PadBuf pad, int batch, hipStream_t s);

@@ -204,6 +204,8 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
         p->off_pad = c.take((mb + 7) / 8 * 8 * 2 * g.n * p->line * sizeof(float));   // grouped padded copies
         p->off_s1 = c.take(mb * g.n_views * ds * sizeof(float));
         p->off_s2 = c.take((mb + 7) / 8 * 8 * g.n_views * ds * sizeof(float));   // interleaved, stride <= roundup(batch, 8)
+        p->off_pscale = c.take((mb + 63) / 64 * 64 * sizeof(float));
+        p->off_ppart = c.take(mb * (size_t)tiles16(g.n) * sizeof(double));
         p->total = c.off;
     } catch (const std::bad_alloc&) {
         delete p;
@@ -260,8 +262,8 @@ air_status air_project(air_plan p, const float* x, float* y, int32_t batch, hipS
     if (air_status st = check_batch(p, batch, true)) return st;
     if (!x || !y) return fail(AIR_E_INVALID, "null pointer");
     const KGeom kg = p->kgeom();
-    PadBuf pad{p->at<float>(p->off_pad)};
-    AIR_K(AIR_K_OTHER, launch_pad(kg, x, pad, batch, s));
+    const PadBuf pad = plan_pad(p, p->at<float>(p->off_pad), p->at<float>(p->off_pscale));
+    if (air_status e = build_pad(p, x, pad, p->at<double>(p->off_ppart), batch, s)) return e;
     if (p->direct(y)) {
         AIR_K(AIR_K_PROJECT, launch_project(kg, pad, y, batch, true, s));
     } else {
@@ -320,11 +322,11 @@ air_status air_normal_apply(air_plan p, const float* x, float* out, int32_t batc
     if (filter != 0 && filter != 1) return fail(AIR_E_INVALID, "filter must be 0 or 1");
     if (!std::isfinite(mu)) return fail(AIR_E_INVALID, "mu must be finite");
     const KGeom kg = p->kgeom();
-    PadBuf pad{p->at<float>(p->off_pad)};
+    const PadBuf pad = plan_pad(p, p->at<float>(p->off_pad), p->at<float>(p->off_pscale));
     float* s1 = p->at<float>(p->off_s1);
     float* s2 = p->at<float>(p->off_s2);
     // A^T C A x = J^T (S C S) J x;  A^T A x = J^T S^2 J x
-    AIR_K(AIR_K_OTHER, launch_pad(kg, x, pad, batch, s));
+    if (air_status e = build_pad(p, x, pad, p->at<double>(p->off_ppart), batch, s)) return e;
     AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, false, s));
     const int grp = image_group(batch);
     if (filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), s1, s2, batch * p->g.n_views, p->ds,

@@ -1,6 +1,7 @@
 // Device helpers shared by the AIR kernels (gfx950, wave64).
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include "air_internal.h"

@@ -49,6 +49,7 @@ __global__ __launch_bounds__(256) void k_cg_p(CgArgs a, int batch) {
             a.p[idx] = pn[q];
         }
     }
+    if (!a.pad.base) return;    // float16 copies are built separately (uniform over the block)
     const int line = n + 2 * kPad;
     constexpr int P = G < 2 ? G : 2;    // pad_group(batch)
     store_padded_group<G, P>(a.pad.base + (size_t)b0 * 2 * n * line, n, line, i0, j0, tx, ty, pn, lds);

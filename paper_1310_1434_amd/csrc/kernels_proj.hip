@@ -28,6 +28,7 @@ int image_group(int batch) {
 }
 
 int pad_group(int batch) { return batch >= 2 ? 2 : 1; }
+int pad_group16(int batch) { return batch >= 3 ? 4 : batch; }
 
 // ---------------------------------------------------------------------------- padded copies
 template <int P>
@@ -49,6 +50,109 @@ hipError_t launch_pad(const KGeom& g, const float* x, PadBuf pad, int batch, hip
     dim3 grid((g.n + 15) / 16, (g.n + 15) / 16, (batch + pg - 1) / pg), block(256);
     if (pg == 2) hipLaunchKernelGGL(k_pad<2>, grid, block, 0, s, x, pad.base, g.n, g.line, batch);
     else hipLaunchKernelGGL(k_pad<1>, grid, block, 0, s, x, pad.base, g.n, g.line, batch);
+    return hipGetLastError();
+}
+
+// float16 copies: 16x16 tiles of P images, scaled per image; the column copy
+// goes through shared memory so both copies are written as contiguous runs.
+template <int P>
+__device__ __forceinline__ void store_half_group(uint16_t* p, const float (&v)[P]) {
+    uint16_t h[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < P; q++) h[q] = __half_as_ushort(__float2half_rn(v[q]));
+    if constexpr (P == 4) *reinterpret_cast<uint2*>(p) = make_uint2(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16);
+    else if constexpr (P == 2) *reinterpret_cast<uint32_t*>(p) = h[0] | (uint32_t)h[1] << 16;
+    else p[0] = h[0];
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_pad16(const float* __restrict__ x, uint16_t* __restrict__ pad,
+                                               const float* __restrict__ scale, int n, int line, int batch) {
+    __shared__ float lds[16 * 17 * P];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16, b0 = blockIdx.z * P;
+    const int i = i0 + tx, j = j0 + ty;
+    float v[P];
+#pragma unroll
+    for (int q = 0; q < P; q++)
+        v[q] = (i < n && j < n && b0 + q < batch) ? x[((size_t)(b0 + q) * n + j) * n + i] * scale[b0 + q] : 0.f;
+    const float zero[P] = {};
+    uint16_t* cols = pad + (size_t)blockIdx.z * 2 * n * line * P;
+    uint16_t* rows = cols + (size_t)n * line * P;
+    if (i < n && j < n) store_half_group<P>(rows + ((size_t)j * line + kPad + i) * P, v);
+    if (j < n && tx < kPad) {
+        if (i0 == 0) store_half_group<P>(rows + ((size_t)j * line + tx) * P, zero);
+        if (i0 + 16 >= n) store_half_group<P>(rows + ((size_t)j * line + kPad + n + tx) * P, zero);
+    }
+#pragma unroll
+    for (int q = 0; q < P; q++) lds[(ty * 17 + tx) * P + q] = v[q];
+    __syncthreads();
+    const int ic = i0 + ty, jc = j0 + tx;
+    float w[P];
+#pragma unroll
+    for (int q = 0; q < P; q++) w[q] = lds[(tx * 17 + ty) * P + q];
+    if (ic < n && jc < n) store_half_group<P>(cols + ((size_t)ic * line + kPad + jc) * P, w);
+    if (ic < n && tx < kPad) {
+        if (j0 == 0) store_half_group<P>(cols + ((size_t)ic * line + tx) * P, zero);
+        if (j0 + 16 >= n) store_half_group<P>(cols + ((size_t)ic * line + kPad + n + tx) * P, zero);
+    }
+}
+
+hipError_t launch_pad16(const KGeom& g, const float* x, PadBuf pad, int batch, hipStream_t s) {
+    const int pg = pad_group16(batch);
+    dim3 grid((g.n + 15) / 16, (g.n + 15) / 16, (batch + pg - 1) / pg), block(256);
+    if (pg == 4) hipLaunchKernelGGL(k_pad16<4>, grid, block, 0, s, x, pad.half, pad.scale, g.n, g.line, batch);
+    else if (pg == 2) hipLaunchKernelGGL(k_pad16<2>, grid, block, 0, s, x, pad.half, pad.scale, g.n, g.line, batch);
+    else hipLaunchKernelGGL(k_pad16<1>, grid, block, 0, s, x, pad.half, pad.scale, g.n, g.line, batch);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_absmax(const float* __restrict__ x, double* __restrict__ partial, int n) {
+    __shared__ float sh[4];
+    const int i = blockIdx.x * 16 + (threadIdx.x & 15), j = blockIdx.y * 16 + (threadIdx.x >> 4), b = blockIdx.z;
+    float m = 0.f;
+    if (i < n && j < n) m = fabsf(x[((size_t)b * n + j) * n + i]);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, kWave));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
+        partial[(size_t)b * nblk + blk] = (double)fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+    }
+}
+
+hipError_t launch_absmax(int n, const float* x, double* partial, int batch, hipStream_t s) {
+    dim3 grid((n + 15) / 16, (n + 15) / 16, batch);
+    hipLaunchKernelGGL(k_absmax, grid, dim3(256), 0, s, x, partial, n);
+    return hipGetLastError();
+}
+
+// One block per image: max of the partials, then the power-of-two scale.
+__global__ __launch_bounds__(256) void k_pad_scale(const double* __restrict__ partial, int nblk,
+                                                   float* __restrict__ scale) {
+    __shared__ double sh[4];
+    const int b = blockIdx.x;
+    double m = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += 256) m = fmax(m, partial[(size_t)b * nblk + k]);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, kWave));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double mx = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+        float s = 1.f;
+        if (mx > 0.0 && isfinite(mx)) {
+            int e;
+            frexp(mx, &e);                                 // mx = f 2^e, f in [0.5, 1)
+            s = ldexpf(1.f, min(max(14 - e, -126), 126));  // mx * s in [2^13, 2^14)
+        }
+        scale[b] = s;
+    }
+}
+
+hipError_t launch_pad_scale(const double* partial, int nblk, int batch, float* scale, hipStream_t s) {
+    hipLaunchKernelGGL(k_pad_scale, dim3(batch), dim3(256), 0, s, partial, nblk, scale);
     return hipGetLastError();
 }
 
@@ -149,8 +253,97 @@ __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __
     }
 }
 
+// The same projector over float16 copies (mixed-precision plans): groups of
+// P <= 4 images per sample, converted to float32 before the multiply-adds, sums
+// divided by the images' power-of-two scales.
+template <int P>
+__device__ __forceinline__ void load_half_pair(const uint16_t* p, float (&s0)[P], float (&s1)[P]) {
+    if constexpr (P == 4) {
+        const float4_a8 u = *reinterpret_cast<const float4_a8*>(p);     // [j][0..3], [j + 1][0..3]
+        const uint32_t w[4] = {__float_as_uint(u.x), __float_as_uint(u.y), __float_as_uint(u.z), __float_as_uint(u.w)};
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const uint32_t a = w[q >> 1], c = w[2 + (q >> 1)];
+            s0[q] = __half2float(__ushort_as_half((unsigned short)((q & 1) ? a >> 16 : a & 0xffff)));
+            s1[q] = __half2float(__ushort_as_half((unsigned short)((q & 1) ? c >> 16 : c & 0xffff)));
+        }
+    } else if constexpr (P == 2) {
+        const float2_a4 u = *reinterpret_cast<const float2_a4*>(p);     // [j][0..1], [j + 1][0..1]
+        const uint32_t a = __float_as_uint(u.x), c = __float_as_uint(u.y);
+        s0[0] = __half2float(__ushort_as_half((unsigned short)(a & 0xffff)));
+        s0[1] = __half2float(__ushort_as_half((unsigned short)(a >> 16)));
+        s1[0] = __half2float(__ushort_as_half((unsigned short)(c & 0xffff)));
+        s1[1] = __half2float(__ushort_as_half((unsigned short)(c >> 16)));
+    } else {
+        s0[0] = __half2float(__ushort_as_half(p[0]));
+        s1[0] = __half2float(__ushort_as_half(p[1]));
+    }
+}
+
+template <bool SCALED, int P>
+__global__ __launch_bounds__(kProjBlock) void k_project16(KGeom g, const uint16_t* __restrict__ pad,
+                                                           const float* __restrict__ scale, float* __restrict__ y,
+                                                           int chunks, int batch) {
+    const int v = blockIdx.x / chunks;
+    const int k = (blockIdx.x - v * chunks) * kProjBlock + threadIdx.x;
+    const int b0 = blockIdx.y * P;
+    const bool ray = k < g.n_bins;
+    RayEntry e;
+    e.tc = 0;
+    e.m = 0;
+    e.meta = 0;
+    if (ray) e = g.rays[(size_t)v * g.n_bins + k];
+    const bool hits = ray && ray_hi(e.meta) >= ray_lo(e.meta);
+    const int lo = hits ? ray_lo(e.meta) : 0x7fffffff;
+    const int hi = hits ? ray_hi(e.meta) : -1;
+    const int axis = ray_axis(e.meta);
+    const int a_lo = max(0, __builtin_amdgcn_readfirstlane(wave_min_i(lo)) - 1);
+    const int a_hi = min(g.n - 1, __builtin_amdgcn_readfirstlane(wave_max_i(hi)) + 1);
+    const int line = g.line;
+    const uint16_t* lines = pad + ((size_t)blockIdx.y * 2 + axis) * g.n * line * P;
+    float acc[P];
+#pragma unroll
+    for (int q = 0; q < P; q++) acc[q] = 0.f;
+    int64_t t = fx_at(e, a_lo - g.c0);
+    const int64_t m = (int64_t)e.m * 2;
+    uint32_t row = (uint32_t)(a_lo * line);
+#pragma unroll 4
+    for (int a = a_lo; a <= a_hi; a++, t += m, row += line) {
+        const float f = fx_frac(t);
+        float s0[P], s1[P];
+        load_half_pair<P>(lines + (size_t)((row + (uint32_t)fx_clamped_index(t, g.n)) * (uint32_t)P), s0, s1);
+#pragma unroll
+        for (int q = 0; q < P; q++) {
+            acc[q] = fmaf(1.f - f, s0[q], acc[q]);
+            acc[q] = fmaf(f, s1[q], acc[q]);
+        }
+    }
+    if (k >= g.ds) return;
+    const float sv = (SCALED && ray) ? g.step[(size_t)v * g.ds + k] : 1.f;
+#pragma unroll
+    for (int q = 0; q < P; q++) {
+        const int b = b0 + q;
+        if (b >= batch) break;
+        float out = 0.f;
+        if (ray) out = (SCALED ? acc[q] * sv : acc[q]) / scale[b];    // exact: scale is a power of two
+        y[((size_t)b * g.n_views + v) * g.ds + k] = out;
+    }
+}
+
 template <bool SCALED>
 static void launch_project_g(const KGeom& g, PadBuf pad, float* y, int batch, hipStream_t s) {
+    if (pad.half) {
+        const int chunks = (g.ds + kProjBlock - 1) / kProjBlock;
+        const int pg = pad_group16(batch);
+        dim3 grid(g.n_views * chunks, (batch + pg - 1) / pg), block(kProjBlock);
+        if (pg == 4)
+            hipLaunchKernelGGL((k_project16<SCALED, 4>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
+        else if (pg == 2)
+            hipLaunchKernelGGL((k_project16<SCALED, 2>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
+        else
+            hipLaunchKernelGGL((k_project16<SCALED, 1>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
+        return;
+    }
     const int chunks = (g.ds + kProjBlock - 1) / kProjBlock;
     const int pg = pad_group(batch);
     dim3 grid(g.n_views * chunks, (batch + pg - 1) / pg), block(kProjBlock);
@@ -470,7 +663,7 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
         }
         if (REDUCE) block_partial<256>(part, a.partial + (size_t)b * nblk + blk);
     }
-    if (MODE == BP_RESIDUAL) {
+    if (MODE == BP_RESIDUAL && a.pad_out.base) {    // (float16 copies are built separately)
         constexpr int P = BT < 2 ? BT : 2;    // pad_group(batch)
         store_padded_pair<BT, P>(a.pad_out.base + (size_t)b0 * 2 * n * g.line, n, g.line, i0, j0, tx, ty, ra, rb);
     }

@@ -53,7 +53,7 @@ struct air_plan_s {
     int n_terms = 0, n_frag = 0, dmin = 0;
     // workspace layout (bytes)
     size_t off_rays = 0, off_step = 0, off_views = 0, off_taps = 0, off_frag[3] = {0, 0, 0}, off_wsq = 0;
-    size_t off_pad = 0, off_s1 = 0, off_s2 = 0, total = 0;
+    size_t off_pad = 0, off_s1 = 0, off_s2 = 0, off_pscale = 0, off_ppart = 0, total = 0;
     char* ws = nullptr;
     // per-kernel event timing (air_kernel_timing_enable)
     struct Timed {
@@ -118,6 +118,8 @@ struct air_plan_s {
     }
     template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
     bool direct(const void* p) const { return g.n_bins == ds && (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+    // mixed-precision plans keep the projector's padded copies in float16
+    bool half_pad() const { return prec != AIR_FP32; }
 };
 
 namespace air {
@@ -177,6 +179,7 @@ inline air_status stage_sino(air_plan p, const float* y, int32_t batch, float* s
 struct SolveBufs {
     float* X;       // [batch][n][n] current image
     float* pad;     // grouped padded copies of X or p (PadBuf), rebuilt every outer iteration
+    float* pscale;  // [batch] scales of float16 padded copies (mixed-precision plans)
     float* s1;      // [batch][n_views][ds] projections
     float* s2;      // group-interleaved backprojector input (G = image_group(batch))
     float* g;       // [batch][n][n]  A'^T Y
@@ -203,10 +206,15 @@ struct SolveSetup {
 
 // Bytes of the per-image buffers of SolveBufs (excluding the sinogram scratch).
 struct SolveLayout {
-    size_t pad, s1, s2, g, r, p, q, bb, e, part, scal, iters, total;
+    size_t pad, pscale, s1, s2, g, r, p, q, bb, e, part, scal, iters, total;
 };
 SolveLayout solve_layout(const air_plan_s* p, int batch);
 SolveBufs solve_bufs(const air_plan_s* p, const SolveLayout& L, char* ws, float* X, int batch);
+// The projector's padded copies of x: float32 image pairs, or (mixed-precision
+// plans) float16 groups with per-image power-of-two scales from max |x|
+// (partial: [batch][tiles16(n)] scratch).
+PadBuf plan_pad(const air_plan_s* p, float* pad, float* scale);
+air_status build_pad(air_plan p, const float* x, const PadBuf& pad, double* partial, int batch, hipStream_t s);
 
 // g = A'^T Y (or A^T Y); zero b and e.  Y: [batch][V][D] (public layout).
 air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch, const SolveSetup& st, hipStream_t s);

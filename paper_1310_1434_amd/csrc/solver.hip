@@ -11,6 +11,7 @@ SolveLayout solve_layout(const air_plan_s* p, int batch) {
     Carver c;
     SolveLayout L;
     L.pad = c.take((B + 7) / 8 * 8 * 2 * n * p->line * sizeof(float));   // grouped padded copies
+    L.pscale = c.take((B + 63) / 64 * 64 * sizeof(float));
     L.s1 = c.take(B * p->g.n_views * p->ds * sizeof(float));
     L.s2 = c.take((B + 7) / 8 * 8 * p->g.n_views * p->ds * sizeof(float));   // interleaved backprojector input
     L.g = c.take(B * np * sizeof(float));
@@ -32,6 +33,7 @@ SolveBufs solve_bufs(const air_plan_s* p, const SolveLayout& L, char* w, float* 
     SolveBufs B;
     B.X = X;
     B.pad = F(L.pad);
+    B.pscale = F(L.pscale);
     B.s1 = F(L.s1);
     B.s2 = F(L.s2);
     B.g = F(L.g);
@@ -73,6 +75,29 @@ air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch,
     return AIR_OK;
 }
 
+PadBuf plan_pad(const air_plan_s* p, float* pad, float* scale) {
+    PadBuf b;
+    if (p->half_pad()) {
+        b.half = reinterpret_cast<uint16_t*>(pad);
+        b.scale = scale;
+    } else {
+        b.base = pad;
+    }
+    return b;
+}
+
+air_status build_pad(air_plan p, const float* x, const PadBuf& pad, double* partial, int batch, hipStream_t s) {
+    const KGeom kg = p->kgeom();
+    if (pad.half) {
+        AIR_K(AIR_K_OTHER, launch_absmax(kg.n, x, partial, batch, s));
+        AIR_K(AIR_K_OTHER, launch_pad_scale(partial, tiles16(kg.n), batch, pad.scale, s));
+        AIR_K(AIR_K_OTHER, launch_pad16(kg, x, pad, batch, s));
+    } else {
+        AIR_K(AIR_K_OTHER, launch_pad(kg, x, pad, batch, s));
+    }
+    return AIR_OK;
+}
+
 // One forward-backward iteration (Eq. (6) and the framelet proximal step):
 //   X' = X + mu (g - A'^T A X)  (= X - mu A'^T (A X - Y), g = A'^T Y from solve_init)
 //   X  = W^T shrink(W X', mu lambda / 2);  resid = ||X_new - X_old||_2
@@ -80,8 +105,9 @@ static air_status fbs_iteration(air_plan p, const SolveBufs& B, int batch, const
     const KGeom kg = p->kgeom();
     const int n = p->g.n, rows = batch * p->g.n_views;
     const int grp = image_group(batch);
-    AIR_K(AIR_K_OTHER, launch_pad(kg, B.X, PadBuf{B.pad}, batch, s));
-    AIR_K(AIR_K_PROJECT, launch_project(kg, PadBuf{B.pad}, B.s1, batch, false, s));
+    const PadBuf pad = plan_pad(p, B.pad, B.pscale);
+    if (air_status e = build_pad(p, B.X, pad, B.part, batch, s)) return e;
+    AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, false, s));
     if (st.filter)
         AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), B.s1, B.s2, rows, p->ds, RAMP_PRE | RAMP_POST, grp, s));
     else AIR_K(AIR_K_OTHER, launch_scale(kg, B.s1, B.s2, batch, 2, grp, s));
@@ -115,7 +141,10 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
     const int grp = image_group(batch);
     const bool tf = st.reg == 0;
     const float mu_op = (float)(tf ? st.mu : st.lambda);
-    const PadBuf pad{B.pad};
+    const PadBuf pad = plan_pad(p, B.pad, B.pscale);
+    // float32 copies of p come out of the epilogues that produce p; float16
+    // copies need p's maximum first, so they are built by build_pad
+    const PadBuf fused = pad.half ? PadBuf{} : pad;
     // operator A'^T A + mu I = J^T (S C S) J + mu I (IR arm: J^T S^2 J + mu I)
     auto filtered = [&]() -> air_status {
         if (st.filter)
@@ -127,7 +156,7 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
     else AIR_HIP(hipMemcpyAsync(B.r, B.g, (size_t)batch * np * sizeof(float), hipMemcpyDeviceToDevice, s));
     // r = rhs - M X, p = r, rho = r.r (the padded copies of X are rebuilt here,
     // so they never outlive a step and follow the current batch's grouping)
-    AIR_K(AIR_K_OTHER, launch_pad(kg, B.X, pad, batch, s));
+    if (air_status e = build_pad(p, B.X, pad, B.part, batch, s)) return e;
     AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, false, s));
     if (air_status e = filtered()) return e;
     {
@@ -137,10 +166,12 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
         a.aux = B.X;
         a.out = B.r;
         a.p_out = B.p;
-        a.pad_out = pad;
+        a.pad_out = fused;
         a.partial = B.part;
         AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, B.s2, a, batch, s));
         AIR_K(AIR_K_CG, launch_finalize(FIN_RHO, B.part, nblk_bp, batch, B.rho, nullptr, nullptr, 0, nullptr, s));
+        if (pad.half && st.n_cg > 0)
+            if (air_status e = build_pad(p, B.p, pad, B.part, batch, s)) return e;
     }
     for (int it = 0; it < st.n_cg; it++) {
         AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, false, s));
@@ -165,8 +196,10 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
         AIR_K(AIR_K_CG, launch_cg_update_xr(cg, batch, s));
         if (it < st.n_cg - 1) {
             AIR_K(AIR_K_CG, launch_finalize(FIN_BETA, B.part, nblk, batch, B.rho, B.beta, nullptr, 0, nullptr, s));
-            cg.pad = pad;
+            cg.pad = fused;
             AIR_K(AIR_K_CG, launch_cg_update_p(cg, batch, s));
+            if (pad.half)
+                if (air_status e = build_pad(p, B.p, pad, B.part, batch, s)) return e;
         }
     }
     if (tf) {

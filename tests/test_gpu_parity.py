@@ -449,3 +449,53 @@ def test_variant_filtration_at_c2_and_in_a_solve(air, torch_mod, orc, record):
     xs, _ = plan.solve(dev(torch_mod, y[None]), 0.005, 1.0, 4, 4)
     xr, _ = orc.solve(orc.Geom(g, ramp=flags), y.astype(np.float64), 0.005, 1.0, 4, 4)
     assert rel(host(xs)[0], xr) < 1e-4
+
+
+# ----------------------------------------------------------------------------- float16 image storage (mixed plans)
+
+@pytest.mark.parametrize("name", ["ragged", "c2"])
+@pytest.mark.parametrize("batch", [1, 3, 8])
+def test_mixed_plan_projection_with_float16_images(air, torch_mod, orc, record, name, batch):
+    """Mixed-precision plans store the projector's image copies in float16 with a
+    per-image power-of-two scale: every sample carries a relative rounding error
+    of at most 2^-11 (unit roundoff 2^-11 of the scaled value), and the errors of
+    a ray's ~n samples average out, so 2e-4 bounds the relative L2 error of A x
+    with room to spare; each image's result is independent of its batch."""
+    g = geom(name)
+    rng = np.random.default_rng(batch)
+    xs = np.stack([image_for(name, s) * rng.uniform(1e-3, 1e3) for s in range(batch)]).astype(np.float32)
+    plan = air.Plan(g, max_batch=batch, precision="mixed_f16")
+    y = host(plan.project(dev(torch_mod, xs)))
+    for b in range(batch):
+        e = rel(y[b], orc.project(orc.Geom(g), xs[b].astype(np.float64)))
+        record(f"rel_l2_A_f16_{name}", e)
+        assert e < 2e-4, (b, e)
+        y1 = host(plan.project(dev(torch_mod, xs[b:b + 1])))[0]
+        assert rel(y1, y[b]) < 2e-4          # different grouping, same scale per image
+
+
+def test_mixed_plan_projection_of_zero_and_tiny_images(air, torch_mod):
+    g = geom("ragged")
+    plan = air.Plan(g, max_batch=3, precision="mixed_f16")
+    x = np.zeros((3, g.n, g.n), np.float32)
+    x[1] = 1e-30 * np.random.default_rng(0).uniform(size=(g.n, g.n))
+    x[2] = 1e30 * np.random.default_rng(1).uniform(size=(g.n, g.n))
+    y = host(plan.project(dev(torch_mod, x)))
+    assert np.all(y[0] == 0.0)
+    ref = host(air.Plan(g, max_batch=3).project(dev(torch_mod, x)))
+    assert np.isfinite(y).all()
+    assert rel(y[1], ref[1]) < 2e-4 and rel(y[2], ref[2]) < 2e-4
+
+
+@pytest.mark.parametrize("case,wname", [("c2_fan_512_720_seed0", "c2")])
+def test_mixed_solve_c2_full_size(air, torch_mod, record, case, wname):
+    """The mixed path (f16 hi/lo ramp and float16 image copies) at full C2 size
+    against the stored oracle reconstruction, within the mixed bound 1e-3."""
+    ref = np.load(os.path.join(HERE, "golden", case + ".npz"))
+    w = synth.workload(wname)
+    y = synth.make_case(w, 0)["y"].astype(np.float32)
+    plan = air.Plan(w.geom, precision="mixed_f16")
+    x, _ = plan.solve(dev(torch_mod, y[None]), w.lam, w.mu, w.n_outer, w.n_cg)
+    e = rel(host(x)[0], ref["x"])
+    record("rel_l2_final_mixed_c2", e)
+    assert e < 1e-3
