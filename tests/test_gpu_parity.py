@@ -457,10 +457,12 @@ def test_variant_filtration_at_c2_and_in_a_solve(air, torch_mod, orc, record):
 @pytest.mark.parametrize("batch", [1, 3, 8])
 def test_mixed_plan_projection_with_float16_images(air, torch_mod, orc, record, name, batch):
     """Mixed-precision plans store the projector's image copies in float16 with a
-    per-image power-of-two scale: every sample carries a relative rounding error
-    of at most 2^-11 (unit roundoff 2^-11 of the scaled value), and the errors of
-    a ray's ~n samples average out, so 2e-4 bounds the relative L2 error of A x
-    with room to spare; each image's result is independent of its batch."""
+    per-image power-of-two scale (no overflow, no subnormals at these values):
+    every sample carries a relative rounding error of at most the unit roundoff
+    2^-11, and a projection of a nonnegative image is a sum of nonnegative terms,
+    so its relative error stays below 2^-11 (plus float32 summation, ~1e-6); the
+    bound is 5e-4.  An image's result is the same bits in any batch (its scale
+    is its own, and its samples are summed in the same order)."""
     g = geom(name)
     rng = np.random.default_rng(batch)
     xs = np.stack([image_for(name, s) * rng.uniform(1e-3, 1e3) for s in range(batch)]).astype(np.float32)
@@ -469,9 +471,9 @@ def test_mixed_plan_projection_with_float16_images(air, torch_mod, orc, record, 
     for b in range(batch):
         e = rel(y[b], orc.project(orc.Geom(g), xs[b].astype(np.float64)))
         record(f"rel_l2_A_f16_{name}", e)
-        assert e < 2e-4, (b, e)
+        assert e < 5e-4, (b, e)
         y1 = host(plan.project(dev(torch_mod, xs[b:b + 1])))[0]
-        assert rel(y1, y[b]) < 2e-4          # different grouping, same scale per image
+        assert np.array_equal(y1, y[b])      # another grouping: same scale, same bits
 
 
 def test_mixed_plan_projection_of_zero_and_tiny_images(air, torch_mod):
@@ -484,7 +486,7 @@ def test_mixed_plan_projection_of_zero_and_tiny_images(air, torch_mod):
     assert np.all(y[0] == 0.0)
     ref = host(air.Plan(g, max_batch=3).project(dev(torch_mod, x)))
     assert np.isfinite(y).all()
-    assert rel(y[1], ref[1]) < 2e-4 and rel(y[2], ref[2]) < 2e-4
+    assert rel(y[1], ref[1]) < 5e-4 and rel(y[2], ref[2]) < 5e-4
 
 
 @pytest.mark.parametrize("case,wname", [("c2_fan_512_720_seed0", "c2")])
