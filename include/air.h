@@ -62,7 +62,11 @@ typedef enum { AIR_PARALLEL = 0, AIR_FAN_FLAT = 1 } air_beam;
  *                   three products, float32 accumulation
  *   AIR_MIXED_BF16  bfloat16 MFMA on a three-way split, six products,
  *                   float32 accumulation
- * Projectors and vectors are float32 in all modes; CG inner products, the
+ * In the two mixed modes the forward projector also reads its image copies
+ * in float16 (each image scaled by a power of two so that its largest value
+ * lies in [2^13, 2^14); the scale is undone exactly on the float32 sums), which
+ * halves the bytes of its gathers.  Projector accumulation, images,
+ * sinograms and CG vectors are float32 in all modes; CG inner products, the
  * step sizes alpha/beta and the Bregman residual norm are float64. */
 typedef enum { AIR_FP32 = 0, AIR_MIXED_F16 = 1, AIR_MIXED_BF16 = 2 } air_precision;
 
