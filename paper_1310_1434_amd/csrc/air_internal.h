@@ -32,6 +32,10 @@ struct KGeom {
     const RayEntry* rays;   // [n_views][n_bins]
     const float* step;      // [n_views][ds] path length per driving step (0 in the padding)
     const float2* views;    // [n_views] (cos, sin) as float
+    // Forward-projector block order: [2][v_half] view indices (-1 = none), the
+    // views whose rays are mostly x-driven first, then the mostly y-driven ones.
+    const int32_t* vorder;
+    int v_half;
 };
 
 // Images are processed in groups of image_group(batch) in {1, 2, 4, 8}: the

@@ -1,5 +1,6 @@
 // C ABI of the AIR library: plans, operator entry points and the split
 // Bregman solver.  Host code; all arithmetic runs in the kernels.
+#include <algorithm>
 #include <new>
 
 #include "plan.h"
@@ -139,6 +140,20 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
         p->step.assign((size_t)g.n_views * p->ds, 0.f);
         for (int v = 0; v < g.n_views; v++)
             for (int k = 0; k < g.n_bins; k++) p->step[(size_t)v * p->ds + k] = step[(size_t)v * g.n_bins + k];
+        {
+            // forward-projector block order: views whose rays are mostly x-driven
+            // (they read only the column copies) first, then the mostly y-driven ones
+            std::vector<int32_t> vx, vy;
+            for (int v = 0; v < g.n_views; v++) {
+                int ny = 0;
+                for (int k = 0; k < g.n_bins; k++) ny += p->axis[(size_t)v * g.n_bins + k];
+                (2 * ny > g.n_bins ? vy : vx).push_back(v);
+            }
+            p->v_half = (int)((std::max(vx.size(), vy.size()) + 3) / 4 * 4);
+            p->vorder.assign(2 * (size_t)p->v_half, -1);
+            std::copy(vx.begin(), vx.end(), p->vorder.begin());
+            std::copy(vy.begin(), vy.end(), p->vorder.begin() + p->v_half);
+        }
         p->views.resize(2 * (size_t)g.n_views);
         for (int v = 0; v < g.n_views; v++) {
             p->views[2 * v] = (float)g.cosv[v];
@@ -198,6 +213,7 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
         p->off_step = c.take(p->step.size() * sizeof(float));
         p->off_views = c.take(p->views.size() * sizeof(float));
         p->off_taps = c.take(p->taps32.size() * sizeof(float));
+        p->off_vorder = c.take(p->vorder.size() * sizeof(int32_t));
         for (int t = 0; t < p->n_terms; t++) p->off_frag[t] = c.take(p->frag[t].size() * sizeof(uint16_t));
         if (p->cos_weight) p->off_wsq = c.take(p->wsq.size() * sizeof(float));
         const size_t mb = (size_t)max_batch;
@@ -235,6 +251,8 @@ air_status air_plan_bind_workspace(air_plan p, void* dev, size_t bytes, hipStrea
     AIR_HIP(hipMemcpyAsync(ws + p->off_views, p->views.data(), p->views.size() * sizeof(float),
                            hipMemcpyHostToDevice, s));
     AIR_HIP(hipMemcpyAsync(ws + p->off_taps, p->taps32.data(), p->taps32.size() * sizeof(float),
+                           hipMemcpyHostToDevice, s));
+    AIR_HIP(hipMemcpyAsync(ws + p->off_vorder, p->vorder.data(), p->vorder.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, s));
     for (int t = 0; t < p->n_terms; t++)
         AIR_HIP(hipMemcpyAsync(ws + p->off_frag[t], p->frag[t].data(), p->frag[t].size() * sizeof(uint16_t),

@@ -194,6 +194,19 @@ __device__ __forceinline__ int64_t fx_at(const RayEntry& e, int a_minus_c0) {
 // out-of-range step contributes exactly zero (no range test needed).
 __device__ __forceinline__ int fx_clamped_index(int64_t t, int n) { return min(max(fx_index(t), 0), n + 2); }
 
+// Block -> (view, chunk of 256 bins).  Blocks go to the eight XCDs round-robin
+// (block L to XCD L mod 8); XCDs 0-3 take the views whose rays are mostly
+// x-driven and XCDs 4-7 the mostly y-driven ones, so each XCD's L2 holds one of
+// the two line sets of the padded copies instead of both.  Returns false for a
+// padding slot (no view).
+__device__ __forceinline__ bool proj_block(const KGeom& g, int chunks, int& v, int& chunk) {
+    const int L = blockIdx.x, r = L & 7;
+    const int idx = (L >> 3) * 4 + (r & 3);
+    v = g.vorder[(r >> 2) * g.v_half + idx / chunks];
+    chunk = idx % chunks;
+    return v >= 0;
+}
+
 typedef float float2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 typedef float float4_a8 __attribute__((ext_vector_type(4), aligned(8)));
 
@@ -201,8 +214,9 @@ template <bool SCALED, int P>
 __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __restrict__ pad,
                                                          float* __restrict__ y, int chunks, int batch) {
     static_assert(P == 1 || P == 2, "images per thread");
-    const int v = blockIdx.x / chunks;
-    const int k = (blockIdx.x - v * chunks) * kProjBlock + threadIdx.x;
+    int v, chunk;
+    if (!proj_block(g, chunks, v, chunk)) return;
+    const int k = chunk * kProjBlock + threadIdx.x;
     const int b0 = blockIdx.y * P;
     const bool ray = k < g.n_bins;
     RayEntry e;
@@ -284,8 +298,9 @@ template <bool SCALED, int P>
 __global__ __launch_bounds__(kProjBlock) void k_project16(KGeom g, const uint16_t* __restrict__ pad,
                                                            const float* __restrict__ scale, float* __restrict__ y,
                                                            int chunks, int batch) {
-    const int v = blockIdx.x / chunks;
-    const int k = (blockIdx.x - v * chunks) * kProjBlock + threadIdx.x;
+    int v, chunk;
+    if (!proj_block(g, chunks, v, chunk)) return;
+    const int k = chunk * kProjBlock + threadIdx.x;
     const int b0 = blockIdx.y * P;
     const bool ray = k < g.n_bins;
     RayEntry e;
@@ -335,7 +350,7 @@ static void launch_project_g(const KGeom& g, PadBuf pad, float* y, int batch, hi
     if (pad.half) {
         const int chunks = (g.ds + kProjBlock - 1) / kProjBlock;
         const int pg = pad_group16(batch);
-        dim3 grid(g.n_views * chunks, (batch + pg - 1) / pg), block(kProjBlock);
+        dim3 grid(2 * g.v_half * chunks, (batch + pg - 1) / pg), block(kProjBlock);
         if (pg == 4)
             hipLaunchKernelGGL((k_project16<SCALED, 4>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
         else if (pg == 2)
@@ -346,7 +361,7 @@ static void launch_project_g(const KGeom& g, PadBuf pad, float* y, int batch, hi
     }
     const int chunks = (g.ds + kProjBlock - 1) / kProjBlock;
     const int pg = pad_group(batch);
-    dim3 grid(g.n_views * chunks, (batch + pg - 1) / pg), block(kProjBlock);
+    dim3 grid(2 * g.v_half * chunks, (batch + pg - 1) / pg), block(kProjBlock);
     if (pg == 2) hipLaunchKernelGGL((k_project<SCALED, 2>), grid, block, 0, s, g, pad.base, y, chunks, batch);
     else hipLaunchKernelGGL((k_project<SCALED, 1>), grid, block, 0, s, g, pad.base, y, chunks, batch);
 }

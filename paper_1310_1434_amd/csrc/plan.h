@@ -45,6 +45,8 @@ struct air_plan_s {
     std::vector<int8_t> axis;
     std::vector<int32_t> lo, hi;
     std::vector<float> views;      // interleaved (cos, sin) as float
+    std::vector<int32_t> vorder;   // [2][v_half] views by majority axis (-1 padded), see KGeom
+    int v_half = 0;
     std::vector<float> taps32;     // [2 ds]
     int ramp_window = 0;           // 0 Ram-Lak, 1 Shepp-Logan, 2 Hann
     bool cos_weight = false;       // symmetric fan-beam cosine weighting of C
@@ -52,7 +54,8 @@ struct air_plan_s {
     std::vector<uint16_t> frag[3];
     int n_terms = 0, n_frag = 0, dmin = 0;
     // workspace layout (bytes)
-    size_t off_rays = 0, off_step = 0, off_views = 0, off_taps = 0, off_frag[3] = {0, 0, 0}, off_wsq = 0;
+    size_t off_rays = 0, off_step = 0, off_views = 0, off_taps = 0, off_frag[3] = {0, 0, 0}, off_wsq = 0,
+           off_vorder = 0;
     size_t off_pad = 0, off_s1 = 0, off_s2 = 0, off_pscale = 0, off_ppart = 0, total = 0;
     char* ws = nullptr;
     // per-kernel event timing (air_kernel_timing_enable)
@@ -100,6 +103,8 @@ struct air_plan_s {
         k.rays = reinterpret_cast<const RayEntry*>(ws + off_rays);
         k.step = reinterpret_cast<const float*>(ws + off_step);
         k.views = reinterpret_cast<const float2*>(ws + off_views);
+        k.vorder = reinterpret_cast<const int32_t*>(ws + off_vorder);
+        k.v_half = v_half;
         return k;
     }
     RampTables ramp_tables() const {
