@@ -38,7 +38,7 @@ struct KGeom {
     int v_half;
 };
 
-// Images are processed in groups of image_group(batch) in {1, 2, 4, 8}: the
+// Images are processed in groups of image_group(batch) in {1, 2, 4, 8, 16}: the
 // group a backprojector thread serves.  The choice minimises
 // ceil(batch / G) * (2 + G), i.e. it shares the per-sample index work over as
 // many images as possible without too many idle lanes in the last group.
@@ -75,7 +75,7 @@ hipError_t launch_pad(const KGeom& g, const float* x, PadBuf pad, int batch, hip
 hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, bool scaled, hipStream_t s);
 // Backprojector input layout: group-interleaved [ceil(batch / G)][n_views][ds][G]
 // with G = image_group(batch), so that the images a backprojector thread serves
-// are contiguous and each group is one dense block.  Lanes of the last group
+// are contiguous and each group is one dense block (sized for roundup(batch, 16)).  Lanes of the last group
 // beyond the batch are never written (and their results never stored).
 // out (group-interleaved, G = grp) = y (rows [batch * n_views][ds]) * step^power (power 1 or 2).
 hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, int power, int grp, hipStream_t s);

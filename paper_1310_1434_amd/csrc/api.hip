@@ -219,7 +219,7 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
         const size_t mb = (size_t)max_batch;
         p->off_pad = c.take((mb + 7) / 8 * 8 * 2 * g.n * p->line * sizeof(float));   // grouped padded copies
         p->off_s1 = c.take(mb * g.n_views * ds * sizeof(float));
-        p->off_s2 = c.take((mb + 7) / 8 * 8 * g.n_views * ds * sizeof(float));   // interleaved, stride <= roundup(batch, 8)
+        p->off_s2 = c.take((mb + 15) / 16 * 16 * g.n_views * ds * sizeof(float));   // group-interleaved, <= roundup(batch, 16) images
         p->off_pscale = c.take((mb + 63) / 64 * 64 * sizeof(float));
         p->off_ppart = c.take(mb * (size_t)tiles16(g.n) * sizeof(double));
         p->total = c.off;

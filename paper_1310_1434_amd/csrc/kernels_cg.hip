@@ -64,7 +64,8 @@ hipError_t launch_cg_update_xr(const CgArgs& a, int batch, hipStream_t s) {
 hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s) {
     const int grp = image_group(batch);
     dim3 grid((a.n + 15) / 16, (a.n + 15) / 16, (batch + grp - 1) / grp), block(256);
-    if (grp == 8) hipLaunchKernelGGL(k_cg_p<8>, grid, block, 0, s, a, batch);
+    if (grp == 16) hipLaunchKernelGGL(k_cg_p<16>, grid, block, 0, s, a, batch);
+    else if (grp == 8) hipLaunchKernelGGL(k_cg_p<8>, grid, block, 0, s, a, batch);
     else if (grp == 4) hipLaunchKernelGGL(k_cg_p<4>, grid, block, 0, s, a, batch);
     else if (grp == 2) hipLaunchKernelGGL(k_cg_p<2>, grid, block, 0, s, a, batch);
     else hipLaunchKernelGGL(k_cg_p<1>, grid, block, 0, s, a, batch);

@@ -17,7 +17,7 @@ namespace air {
 int image_group(int batch) {
     if (batch <= 1) return 1;
     int best = 1, best_cost = batch * 3;
-    for (int g : {2, 4, 8}) {
+    for (int g : {2, 4, 8, 16}) {
         const int cost = (batch + g - 1) / g * (2 + g);
         if (cost < best_cost) {
             best = g;
@@ -688,7 +688,8 @@ template <int MODE, bool REDUCE>
 static void launch_bp_mode(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s) {
     const int bt = image_group(batch);
     dim3 grid((g.n + 15) / 16, (g.n + 31) / 32, (batch + bt - 1) / bt), block(256);
-    if (bt == 8) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 8>), grid, block, 0, s, g, y, a, batch);
+    if (bt == 16) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 16>), grid, block, 0, s, g, y, a, batch);
+    else if (bt == 8) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 8>), grid, block, 0, s, g, y, a, batch);
     else if (bt == 4) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 4>), grid, block, 0, s, g, y, a, batch);
     else if (bt == 2) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 2>), grid, block, 0, s, g, y, a, batch);
     else hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 1>), grid, block, 0, s, g, y, a, batch);

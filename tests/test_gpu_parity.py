@@ -181,10 +181,10 @@ def test_operator_batch_matches_single(air, torch_mod):
         assert np.array_equal(y1, yb[b])
 
 
-@pytest.mark.parametrize("batch", [2, 3, 5, 9])
+@pytest.mark.parametrize("batch", [2, 3, 5, 9, 16, 33])
 def test_backprojection_batch_matches_single(air, torch_mod, batch):
     """Every image gets the same bits whatever group of images it is processed
-    in (groups of 2, 4 or 8, with idle lanes in the last group)."""
+    in (groups of 2, 4, 8 or 16, with idle lanes in the last group)."""
     g = geom("ragged")
     plan = air.Plan(g, max_batch=batch)
     ys = np.stack([sino_for("ragged", s) for s in range(batch)]).astype(np.float32)
