@@ -7,7 +7,12 @@
 // fragments, one per diagonal offset k0 - n0.
 //
 // Tiles: a block of 4 waves covers 64 rows x 32 columns; each wave owns 16
-// rows and two 16x16 accumulator tiles.  Rows have stride ds (n_bins rounded
+// rows and two 16x16 accumulator tiles.  When the output is group-interleaved
+// (the backprojector's input, [group][v][k][G]) the tile rows run over
+// (group, view, image in group), so the G images of one view are rows of the
+// same wave and every G-float output chunk is completed by one block.  Blocks
+// go to the eight XCDs round-robin; the column tiles of one row tile are kept
+// on one XCD, so each sinogram row is fetched into that XCD's L2 once.  Rows have stride ds (n_bins rounded
 // up to 32, zero-filled), so the K loop needs no bounds tests.  Within one
 // MFMA the assignment of actual k to the instruction's k slots is free as
 // long as both operands agree; it is chosen so that each lane reads
@@ -21,15 +26,46 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 b8_t __attribute__((ext_vector_type(8)));
 
-// ---------------------------------------------------------------------------- float32
-// Output address of element (row, col): row = b * n_views + v of the input
-// layout; grp == 0 keeps that layout, grp > 0 interleaves groups of grp images.
-__device__ __forceinline__ size_t ramp_out_index(int row, int col, int ds, int n_views, int grp) {
-    if (grp == 0) return (size_t)row * ds + col;
-    const int b = row / n_views, v = row - b * n_views;
-    const int gi = b / grp;
-    return (((size_t)gi * n_views + v) * ds + col) * grp + (b - gi * grp);
+// ---------------------------------------------------------------------------- tiles
+// Tile row m -> image b and view v.  grp == 0: m = b * n_views + v (the input
+// layout).  grp > 0: m = (gi * n_views + v) * grp + bl, b = gi * grp + bl; rows of
+// images past the batch are padding.
+struct RampRow {
+    int b, v;
+    size_t out;       // output offset of column 0 (add col * (grp ? grp : 1))
+    bool valid;
+};
+__device__ __forceinline__ RampRow ramp_row(int m, int batch, int n_views, int ds, int grp) {
+    RampRow r;
+    if (grp == 0) {
+        r.b = m / n_views;
+        r.v = m - r.b * n_views;
+        r.out = (size_t)m * ds;
+    } else {
+        const int per = n_views * grp;
+        const int gi = m / per, rem = m - gi * per;
+        r.v = rem / grp;
+        const int bl = rem - r.v * grp;
+        r.b = gi * grp + bl;
+        r.out = ((size_t)gi * n_views + r.v) * ds * grp + bl;
+    }
+    r.valid = r.b < batch;
+    return r;
 }
+
+// Tile rows of a launch and the block -> (row tile, column tile) map.
+__host__ __device__ inline int ramp_tile_rows(int batch, int n_views, int grp) {
+    return (grp == 0 ? batch : (batch + grp - 1) / grp * grp) * n_views;
+}
+__device__ __forceinline__ bool ramp_block(int row_tiles, int col_tiles, int& rt, int& ct) {
+    const int L = blockIdx.x, q = L >> 3;
+    const int j = q / col_tiles;
+    ct = q - j * col_tiles;
+    rt = j * 8 + (L & 7);
+    return rt < row_tiles;
+}
+
+// ---------------------------------------------------------------------------- float32
 
 template <int SCALE>
 __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, float* __restrict__ yf,
@@ -37,17 +73,20 @@ __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, f
                                                   const float* __restrict__ wsq, int n_views, int rows, int ds,
                                                   int grp) {
     extern __shared__ float T[];   // [2 ds]: T[d + ds] = kappa r(|d|)
+    const int batch = rows / n_views, mrows = ramp_tile_rows(batch, n_views, grp);
+    int rt, ct;
+    if (!ramp_block((mrows + 63) / 64, ds / 32, rt, ct)) return;   // (uniform over the block)
     for (int i = threadIdx.x; i < 2 * ds; i += 256) T[i] = taps[i];
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int m = blockIdx.x * 64 + w * 16 + (lane & 15);   // A row of this lane
-    const int slot = lane >> 4;                              // k slot 0..3
-    const int n0 = blockIdx.y * 32;
+    const int m = rt * 64 + w * 16 + (lane & 15);   // A row of this lane
+    const int slot = lane >> 4;                     // k slot 0..3
+    const int n0 = ct * 32;
     const int ncol = n0 + (lane & 15);
-    const int mc = min(m, rows - 1);
-    const float* arow = y + (size_t)mc * ds;
-    const float* srow = step + (size_t)(mc % n_views) * ds;
-    const bool mvalid = m < rows;
+    const RampRow ar = ramp_row(m, batch, n_views, ds, grp);
+    const bool mvalid = m < mrows && ar.valid;
+    const float* arow = y + (mvalid ? ((size_t)ar.b * n_views + ar.v) * ds : 0);
+    const float* srow = step + (mvalid ? (size_t)ar.v * ds : 0);
     f4_t acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < ds; k0 += 16) {
         float4 av = *reinterpret_cast<const float4*>(arow + k0 + 4 * slot);
@@ -78,23 +117,25 @@ __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, f
         acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, T[d + 3 - 16], acc1, 0, 0, 0);
     }
     // accumulator layout: lane holds C[4 (lane/16) + r][lane % 16]
-    const int rbase = blockIdx.x * 64 + w * 16 + 4 * (lane >> 4);
+    const int rbase = rt * 64 + w * 16 + 4 * (lane >> 4);
+    const int cs = grp ? grp : 1;
 #pragma unroll
     for (int r = 0; r < 4; r++) {
         const int row = rbase + r;
-        if (row < rows) {
+        const RampRow orow = ramp_row(row, batch, n_views, ds, grp);
+        if (row < mrows && orow.valid) {
             float o0 = acc0[r], o1 = acc1[r];
             if (wsq) {      // and D^(1/2) after
                 o0 *= wsq[ncol];
                 o1 *= wsq[ncol + 16];
             }
             if (SCALE & RAMP_POST) {
-                const float* so = step + (size_t)(row % n_views) * ds;
+                const float* so = step + (size_t)orow.v * ds;
                 o0 *= so[ncol];
                 o1 *= so[ncol + 16];
             }
-            yf[ramp_out_index(row, ncol, ds, n_views, grp)] = o0;
-            yf[ramp_out_index(row, ncol + 16, ds, n_views, grp)] = o1;
+            yf[orow.out + (size_t)ncol * cs] = o0;
+            yf[orow.out + (size_t)(ncol + 16) * cs] = o1;
         }
     }
 }
@@ -105,14 +146,17 @@ __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, f
 template <int PREC, int SCALE>
 __global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y, float* __restrict__ yf,
                                                     RampTables t, int rows, int ds, int grp) {
+    const int batch = rows / t.n_views, mrows = ramp_tile_rows(batch, t.n_views, grp);
+    int rt, ct;
+    if (!ramp_block((mrows + 63) / 64, ds / 32, rt, ct)) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int m = blockIdx.x * 64 + w * 16 + (lane & 15);
+    const int m = rt * 64 + w * 16 + (lane & 15);
     const int slot = lane >> 4;                 // k slots 8 slot .. 8 slot + 7
-    const int n0 = blockIdx.y * 32;
-    const int mc = min(m, rows - 1);
-    const float* arow = y + (size_t)mc * ds;
-    const float* srow = t.step + (size_t)(mc % t.n_views) * ds;
-    const bool mvalid = m < rows;
+    const int n0 = ct * 32;
+    const RampRow ar = ramp_row(m, batch, t.n_views, ds, grp);
+    const bool mvalid = m < mrows && ar.valid;
+    const float* arow = y + (mvalid ? ((size_t)ar.b * t.n_views + ar.v) * ds : 0);
+    const float* srow = t.step + (mvalid ? (size_t)ar.v * ds : 0);
     f4_t accA0 = {0.f, 0.f, 0.f, 0.f}, accA1 = accA0, accB0 = accA0, accB1 = accA0;
     for (int k0 = 0; k0 < ds; k0 += 32) {
         float4 a0 = *reinterpret_cast<const float4*>(arow + k0 + 8 * slot);
@@ -185,12 +229,14 @@ __global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y,
         }
     }
     const float cross = (PREC == AIR_MIXED_F16) ? (1.f / 2048.f) : 1.f;
-    const int rbase = blockIdx.x * 64 + w * 16 + 4 * (lane >> 4);
+    const int rbase = rt * 64 + w * 16 + 4 * (lane >> 4);
     const int ncol = n0 + (lane & 15);
+    const int cs = grp ? grp : 1;
 #pragma unroll
     for (int r = 0; r < 4; r++) {
         const int row = rbase + r;
-        if (row < rows) {
+        const RampRow orow = ramp_row(row, batch, t.n_views, ds, grp);
+        if (row < mrows && orow.valid) {
             float o0 = t.out_scale * fmaf(accB0[r], cross, accA0[r]);
             float o1 = t.out_scale * fmaf(accB1[r], cross, accA1[r]);
             if (t.wsq) {    // and D^(1/2) after
@@ -198,12 +244,12 @@ __global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y,
                 o1 *= t.wsq[ncol + 16];
             }
             if (SCALE & RAMP_POST) {
-                const float* so = t.step + (size_t)(row % t.n_views) * ds;
+                const float* so = t.step + (size_t)orow.v * ds;
                 o0 *= so[ncol];
                 o1 *= so[ncol + 16];
             }
-            yf[ramp_out_index(row, ncol, ds, t.n_views, grp)] = o0;
-            yf[ramp_out_index(row, ncol + 16, ds, t.n_views, grp)] = o1;
+            yf[orow.out + (size_t)ncol * cs] = o0;
+            yf[orow.out + (size_t)(ncol + 16) * cs] = o1;
         }
     }
 }
@@ -211,7 +257,9 @@ __global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y,
 template <int SCALE>
 static hipError_t launch_ramp_scaled(int prec, const RampTables& t, const float* y, float* yf, int rows, int ds,
                                      int grp, hipStream_t s) {
-    dim3 grid((rows + 63) / 64, ds / 32), block(256);
+    const int n_views = t.n_views;
+    const int row_tiles = (ramp_tile_rows(rows / n_views, n_views, grp) + 63) / 64;
+    dim3 grid(8 * ((row_tiles + 7) / 8) * (ds / 32)), block(256);
     if (prec == AIR_FP32) {
         hipLaunchKernelGGL(k_ramp_f32<SCALE>, grid, block, 2 * ds * sizeof(float), s, y, yf, t.taps32, t.step,
                            t.wsq, t.n_views, rows, ds, grp);
