@@ -98,11 +98,12 @@ struct BpArgs {
     float* out;         // [batch][n][n]
     float* p_out;       // RESIDUAL: p
     PadBuf pad_out;     // RESIDUAL: padded copy of p
-    double* partial;    // [batch][bp_blocks(n)] block partial sums, or null (MATVEC only)
+    double* partial;    // [batch][bp_blocks(n, batch)] block partial sums, or null (MATVEC only)
 };
 hipError_t launch_backproject(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s);
-// Blocks per image of the backprojector (16 x 32 pixel tiles): its partial sums per image.
-int bp_blocks(int n);
+// Blocks per image of the backprojector (16 x 16 PIX pixel tiles, PIX depends on
+// the batch): its partial sums per image.
+int bp_blocks(int n, int batch);
 
 // Sinogram repacking between the public [V][D] layout and internal [V][ds] rows.
 hipError_t launch_repack(const float* src, int src_stride, float* dst, int dst_stride, int rows, int cols,

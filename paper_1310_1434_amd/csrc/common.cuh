@@ -122,44 +122,40 @@ __device__ __forceinline__ void store_padded_group(float* pad, int n, int line, 
     }
 }
 
-// Write one 16 x 32 tile of a group of G images, held as vertical pixel pairs
-// (thread (tx, ty) holds (i0 + tx, j0 + 2 ty) in va and the pixel below in vb),
+// Write one 16 x (16 PIX) tile of a group of G images, held as vertical pixel
+// columns (thread (tx, ty) holds (i0 + tx, j0 + PIX ty + r), r < PIX, in v[r]),
 // into its padded line sets (sub-groups of P as in store_padded_group).  The
-// two pixels of a pair are adjacent samples of one column line, so both copies
+// pixels of a column are adjacent samples of one column line, so both copies
 // are written as contiguous runs without a transpose.
-template <int G, int P>
-__device__ __forceinline__ void store_padded_pair(float* pad, int n, int line, int i0, int j0, int tx, int ty,
-                                                  const float (&va)[G], const float (&vb)[G]) {
+template <int G, int P, int PIX>
+__device__ __forceinline__ void store_padded_column(float* pad, int n, int line, int i0, int j0, int tx, int ty,
+                                                    const float (&v)[PIX][G]) {
     static_assert(G % P == 0, "sub-groups must tile the group");
     const size_t sub = (size_t)2 * n * line * P;     // floats per sub-group
-    const int i = i0 + tx, j = j0 + 2 * ty;
+    const int i = i0 + tx, j = j0 + PIX * ty;
 #pragma unroll
     for (int s = 0; s < G / P; s++) {
         float* cols = pad + s * sub;
         float* rows = cols + (size_t)n * line * P;
-        float ua[P], ub[P];
 #pragma unroll
-        for (int q = 0; q < P; q++) {
-            ua[q] = va[s * P + q];
-            ub[q] = vb[s * P + q];
-        }
+        for (int r = 0; r < PIX; r++) {
+            float u[P];
 #pragma unroll
-        for (int h = 0; h < 2; h++) {       // rows j and j + 1
-            const int jr = j + h;
+            for (int q = 0; q < P; q++) u[q] = v[r][s * P + q];
+            const int jr = j + r;
             if (jr >= n) break;
-            if (i < n) store_group<P>(rows + ((size_t)jr * line + kPad + i) * P, h ? ub : ua);
+            if (i < n) {
+                store_group<P>(rows + ((size_t)jr * line + kPad + i) * P, u);        // row jr, sample i
+                store_group<P>(cols + ((size_t)i * line + kPad + jr) * P, u);        // column i, sample jr
+            }
             if (tx < kPad) {
                 if (i0 == 0) store_zero_group<P>(rows + ((size_t)jr * line + tx) * P);
                 if (i0 + 16 >= n) store_zero_group<P>(rows + ((size_t)jr * line + kPad + n + tx) * P);
             }
         }
-        if (i < n) {                         // column line i, samples j and j + 1
-            if (j < n) store_group<P>(cols + ((size_t)i * line + kPad + j) * P, ua);
-            if (j + 1 < n) store_group<P>(cols + ((size_t)i * line + kPad + j + 1) * P, ub);
-            if (ty < kPad) {
-                if (j0 == 0) store_zero_group<P>(cols + ((size_t)i * line + ty) * P);
-                if (j0 + 32 >= n) store_zero_group<P>(cols + ((size_t)i * line + kPad + n + ty) * P);
-            }
+        if (i < n && ty < kPad) {
+            if (j0 == 0) store_zero_group<P>(cols + ((size_t)i * line + ty) * P);
+            if (j0 + 16 * PIX >= n) store_zero_group<P>(cols + ((size_t)i * line + kPad + n + ty) * P);
         }
     }
 }

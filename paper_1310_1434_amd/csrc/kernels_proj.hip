@@ -392,27 +392,30 @@ hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, i
 }
 
 // ---------------------------------------------------------------------------- adjoint J^T
-// One thread per pair of vertically adjacent pixels (i, j) and (i, j + 1) and
-// up to BT images; 16 x 32 pixels per block.  For every view the pair takes
-// the bins whose rays can give either pixel a non-zero Joseph weight: any
-// sample that touches a pixel lies in the diamond |dx| + |dy| < pixel around
-// its centre, so its ray meets the detector within hw bins of the centre's own
-// projection k_c, where hw bounds the projected half-width of the diamond over
-// the whole tile; the interval (from the lower to the higher k_c of the two
-// centres) is widened by 0.01 bin.  For each candidate the thread re-evaluates
-// the forward projector's own fixed-point intercept and float32 weights, so
-// the result is the exact transpose of k_project (unscaled) up to summation
-// order.  An x-driven ray crosses both pixels of the pair at the same
-// intercept, so one evaluation gives both weights; a y-driven ray needs a
-// second intercept, one 64-bit add away.
+// One thread per column of PIX vertically adjacent pixels (i, j .. j + PIX - 1)
+// and up to BT images; 16 x 16 PIX pixels per block.  PIX = 2 throughout: four
+// pixels per thread share more intercept work, but at 512^2 and one image the
+// grid then holds a single block per CU and runs slower (measured 0.90 against
+// 0.75 ms).  For every view the thread takes the bins whose rays
+// can give any of its pixels a non-zero Joseph weight: any sample that touches
+// a pixel lies in the diamond |dx| + |dy| < pixel around its centre, so its ray
+// meets the detector within hw bins of the centre's own projection k_c, where
+// hw bounds the projected half-width of the diamond over the whole tile; the
+// interval (between the projections of the first and last centre, which bound
+// the others) is widened by 0.01 bin.  For each candidate the thread
+// re-evaluates the forward projector's own fixed-point intercept and float32
+// weights, so the result is the exact transpose of k_project (unscaled) up to
+// summation order.  An x-driven ray crosses all PIX pixels at the same
+// intercept, so one evaluation gives every weight; a y-driven ray needs one
+// more 64-bit add per pixel.  A larger window only adds candidates of weight
+// exactly zero, so every pixel gets the same bits whatever PIX and BT.
 //
 // Views are processed kBpViews at a time.  Per view, the tile's bins (the
-// union of its pixels' intervals, at most kBpBins per pass) and their
-// sinogram values are staged in shared memory by one wavefront, one bin per
-// lane, so all candidates are read from LDS.  The terms of a pass are summed
-// in float32, across passes in float64.  No atomics.
+// union of its pixels' intervals, at most 64 PIX / 2 per pass) and their
+// sinogram values are staged in shared memory by one wavefront, so all
+// candidates are read from LDS.  The terms of a pass are summed in float32,
+// across passes in float64.  No atomics.
 constexpr int kBpViews = 4;    // views per pass = wavefronts per block
-constexpr int kBpBins = 64;    // staged bins per view and pass = lanes per wavefront
 
 // Joseph weight of the sample at fixed-point intercept t for interpolated index ob.
 __device__ __forceinline__ float joseph_weight_at(int64_t t, int ob) {
@@ -423,40 +426,42 @@ __device__ __forceinline__ float joseph_weight_at(int64_t t, int ob) {
     return (ob == j0) ? (1.f - f) : ((ob == j0 + 1) ? f : 0.f);
 }
 
-// Weights of ray e for the pixels (i, j) and (i, j + 1).  AX: 0 = the ray is
+// Weights of ray e for the pixels (i, j + q), q < PIX.  AX: 0 = the ray is
 // x-driven, 1 = y-driven, 2 = either (read from the table).  With d = j0 - ob
 // (j0 the first sample's index, ob the pixel's interpolated index) a pixel
 // takes 1 - f at d == 0 and f at d == -1.
-template <int AX>
-__device__ __forceinline__ void joseph_pair(const RayEntry& e, int i, int j, int c0, float& wa, float& wb) {
+template <int AX, int PIX>
+__device__ __forceinline__ void joseph_column(const RayEntry& e, int i, int j, int c0, float (&w)[PIX]) {
     if constexpr (AX == 0) {
-        // both pixels sit on the column the ray samples at i: one intercept
+        // all pixels sit on the column the ray samples at i: one intercept
         const int64_t t = fx_at(e, i - c0);
         const float f = fx_frac(t);
         const int d = fx_index(t) - kPad - j;
-        wa = d == 0 ? 1.f - f : (d == -1 ? f : 0.f);
-        wb = d == 1 ? 1.f - f : (d == 0 ? f : 0.f);
+#pragma unroll
+        for (int q = 0; q < PIX; q++) w[q] = d == q ? 1.f - f : (d == q - 1 ? f : 0.f);
     } else if constexpr (AX == 1) {
-        // driving rows j and j + 1, interpolated index i for both
-        const int64_t ta = fx_at(e, j - c0);
-        const int64_t tb = ta + (int64_t)e.m * 2;
-        const float fa = fx_frac(ta), fb = fx_frac(tb);
-        const int da = fx_index(ta) - kPad - i, db = fx_index(tb) - kPad - i;
-        wa = da == 0 ? 1.f - fa : (da == -1 ? fa : 0.f);
-        wb = db == 0 ? 1.f - fb : (db == -1 ? fb : 0.f);
+        // driving rows j + q, interpolated index i for all
+        int64_t t = fx_at(e, j - c0);
+        const int64_t m2 = (int64_t)e.m * 2;
+#pragma unroll
+        for (int q = 0; q < PIX; q++, t += m2) {
+            const float f = fx_frac(t);
+            const int d = fx_index(t) - kPad - i;
+            w[q] = d == 0 ? 1.f - f : (d == -1 ? f : 0.f);
+        }
     } else {
         const int ax = ray_axis(e.meta);
-        const int64_t ta = fx_at(e, (ax ? j : i) - c0);
-        const int64_t tb = ax ? ta + (int64_t)e.m * 2 : ta;   // y-driven: next driving row
-        wa = joseph_weight_at(ta, ax ? i : j);
-        wb = joseph_weight_at(tb, ax ? i : j + 1);
+        int64_t t = fx_at(e, (ax ? j : i) - c0);
+        const int64_t m2 = ax ? (int64_t)e.m * 2 : 0;   // y-driven: next driving row
+#pragma unroll
+        for (int q = 0; q < PIX; q++, t += m2) w[q] = joseph_weight_at(t, ax ? i : j + q);
     }
 }
 
-// Accumulate the candidates [wlo, whi] (staged bins of one view) into both pixels.
-template <int AX, int BT>
+// Accumulate the candidates [wlo, whi] (staged bins of one view) into the pixels.
+template <int AX, int BT, int PIX>
 __device__ __forceinline__ void bp_candidates(const RayEntry* rays, const float* vals, int wlo, int whi, int i,
-                                              int j, int c0, float (&acc_a)[BT], float (&acc_b)[BT]) {
+                                              int j, int c0, float (&acc)[PIX][BT]) {
     for (int w = wlo; w <= whi; w += 2) {
         const bool two = w + 1 <= whi;
         const int w1 = two ? w + 1 : w;
@@ -464,16 +469,15 @@ __device__ __forceinline__ void bp_candidates(const RayEntry* rays, const float*
         float y0[BT], y1[BT];
         load_group<BT>(vals + w * BT, y0);
         load_group<BT>(vals + w1 * BT, y1);
-        float wa0, wb0, wa1, wb1;
-        joseph_pair<AX>(e0, i, j, c0, wa0, wb0);
-        joseph_pair<AX>(e1, i, j, c0, wa1, wb1);
+        float wt0[PIX], wt1[PIX];
+        joseph_column<AX, PIX>(e0, i, j, c0, wt0);
+        joseph_column<AX, PIX>(e1, i, j, c0, wt1);
         const float keep = two ? 1.f : 0.f;
-        wa1 *= keep;
-        wb1 *= keep;
 #pragma unroll
-        for (int q = 0; q < BT; q++) {
-            acc_a[q] = fmaf(wa1, y1[q], fmaf(wa0, y0[q], acc_a[q]));
-            acc_b[q] = fmaf(wb1, y1[q], fmaf(wb0, y0[q], acc_b[q]));
+        for (int r = 0; r < PIX; r++) {
+            const float w1r = wt1[r] * keep;
+#pragma unroll
+            for (int q = 0; q < BT; q++) acc[r][q] = fmaf(w1r, y1[q], fmaf(wt0[r], y0[q], acc[r][q]));
         }
     }
 }
@@ -486,33 +490,38 @@ __device__ __forceinline__ float bin_of(const KGeom& g, float px, float py, floa
     return fmaf(g.sdd * ap * __builtin_amdgcn_rcpf(bp), g.inv_bin, g.half_d);
 }
 
-int bp_blocks(int n) { return ((n + 15) / 16) * ((n + 31) / 32); }
+// Pixels per backprojector thread (see k_backproject).
+static int bp_pix(int) { return 2; }
+int bp_blocks(int n, int batch) { return ((n + 15) / 16) * ((n + 16 * bp_pix(batch) - 1) / (16 * bp_pix(batch))); }
 
-template <int MODE, bool REDUCE, int BT>
+template <int MODE, bool REDUCE, int BT, int PIX>
 __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __restrict__ y, BpArgs a, int batch) {
-    static_assert(kBpViews * kWave == 256 && kBpBins == kWave, "one wavefront stages one view");
-    __shared__ __align__(16) RayEntry s_ray[kBpViews][kBpBins];
-    __shared__ __align__(16) float s_val[kBpViews][kBpBins * BT];
+    constexpr int BINS = 32 * PIX;    // staged bins per view and pass
+    constexpr int TH = 16 * PIX;      // tile height
+    static_assert(kBpViews * kWave == 256 && BINS % kWave == 0, "one wavefront stages one view");
+    __shared__ __align__(16) RayEntry s_ray[kBpViews][BINS];
+    __shared__ __align__(16) float s_val[kBpViews][BINS * BT];
     __shared__ int s_axes[kBpViews];     // staged rays all x-driven (0), all y-driven (1), or both (2)
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 32;
-    const int i = i0 + tx, j = j0 + 2 * ty;      // pixels (i, j) and (i, j + 1)
+    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * TH;
+    const int i = i0 + tx, j = j0 + PIX * ty;      // pixels (i, j + r), r < PIX
     const int b0 = blockIdx.z * BT;
     const int n = g.n;
-    const bool va = i < n && j < n, vb = i < n && j + 1 < n;
     // (pixels past the image edge take an in-image neighbour's window; their sums are dropped)
     const float px = ((float)min(i, n - 1) - g.half_n) * g.pixel;
-    const float py = ((float)min(j, n - 2) - g.half_n) * g.pixel;
+    const float py = ((float)min(j, max(n - PIX, 0)) - g.half_n) * g.pixel;
     // corners of the tile's in-image pixel centres, for the tile windows
     const float cx[2] = {((float)i0 - g.half_n) * g.pixel, ((float)min(i0 + 15, n - 1) - g.half_n) * g.pixel};
-    const float cy[2] = {((float)j0 - g.half_n) * g.pixel, ((float)min(j0 + 31, n - 1) - g.half_n) * g.pixel};
+    const float cy[2] = {((float)j0 - g.half_n) * g.pixel, ((float)min(j0 + TH - 1, n - 1) - g.half_n) * g.pixel};
     // group-interleaved input [group][v][k][BT]: this thread's BT images are
     // contiguous and 4 * BT-byte aligned
     const float* yg = y + (size_t)blockIdx.z * g.n_views * g.ds * BT;
-    double tot_a[BT], tot_b[BT];
+    double tot[PIX][BT];
 #pragma unroll
-    for (int q = 0; q < BT; q++) tot_a[q] = tot_b[q] = 0.0;
+    for (int r = 0; r < PIX; r++)
+#pragma unroll
+        for (int q = 0; q < BT; q++) tot[r][q] = 0.0;
     for (int v0 = 0; v0 < g.n_views; v0 += kBpViews) {
         // Tile windows of the pass's views, computed redundantly by every
         // wavefront: lane 4 s + c takes corner c of view v0 + s.
@@ -567,8 +576,8 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
         }
         int passes = 1;
 #pragma unroll
-        for (int s = 0; s < kBpViews; s++) passes = max(passes, (nb[s] + kBpBins - 1) / kBpBins);
-        // the pair's bin interval per view (absolute bins), from its two centres
+        for (int s = 0; s < kBpViews; s++) passes = max(passes, (nb[s] + BINS - 1) / BINS);
+        // the column's bin interval per view (absolute bins), from its first and last centre
         int klo[kBpViews], khi[kBpViews];
 #pragma unroll
         for (int s = 0; s < kBpViews; s++) {
@@ -577,16 +586,18 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
             if (v0 + s < g.n_views) {
                 const float2 cs = g.views[v0 + s];
                 const float ka = bin_of(g, px, py, cs.x, cs.y);
-                const float kb = bin_of(g, px, py + g.pixel, cs.x, cs.y);
+                const float kb = bin_of(g, px, py + (PIX - 1) * g.pixel, cs.x, cs.y);
                 klo[s] = max(kb0[s], (int)ceilf(fminf(ka, kb) - hws[s] - 0.01f));
                 khi[s] = min(kb0[s] + nb[s] - 1, (int)floorf(fmaxf(ka, kb) + hws[s] + 0.01f));
             }
         }
-        float acc_a[BT], acc_b[BT];
+        float acc[PIX][BT];
 #pragma unroll
-        for (int q = 0; q < BT; q++) acc_a[q] = acc_b[q] = 0.f;
+        for (int r = 0; r < PIX; r++)
+#pragma unroll
+            for (int q = 0; q < BT; q++) acc[r][q] = 0.f;
         for (int p = 0; p < passes; p++) {
-            // stage: wavefront s loads bins kb0 + p * kBpBins + lane of view v0 + s
+            // stage: wavefront s loads bins kb0 + p * BINS + (lane, lane + 64, ...) of view v0 + s
             {
                 int my_kb0 = kb0[0], my_nb = nb[0];
 #pragma unroll
@@ -595,104 +606,95 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                         my_kb0 = kb0[s];
                         my_nb = nb[s];
                     }
-                const int w = p * kBpBins + lane;
-                const bool act = w < my_nb;
-                int ax = 0;
-                if (act) {
-                    const int v = v0 + wave, k = my_kb0 + w;
-                    const RayEntry e = g.rays[(size_t)v * g.n_bins + k];
-                    s_ray[wave][lane] = e;
-                    ax = ray_axis(e.meta);
-                    float t[BT];
-                    load_group<BT>(yg + ((size_t)v * g.ds + k) * BT, t);
-                    store_group<BT>(&s_val[wave][lane * BT], t);
+                bool any_x = false, any_y = false;
+#pragma unroll
+                for (int h = 0; h < BINS / kWave; h++) {
+                    const int slot = h * kWave + lane;
+                    const int w = p * BINS + slot;
+                    const bool act = w < my_nb;
+                    int ax = 0;
+                    if (act) {
+                        const int v = v0 + wave, k = my_kb0 + w;
+                        const RayEntry e = g.rays[(size_t)v * g.n_bins + k];
+                        s_ray[wave][slot] = e;
+                        ax = ray_axis(e.meta);
+                        float t[BT];
+                        load_group<BT>(yg + ((size_t)v * g.ds + k) * BT, t);
+                        store_group<BT>(&s_val[wave][slot * BT], t);
+                    }
+                    any_x = any_x || __ballot(act && ax == 0) != 0;
+                    any_y = any_y || __ballot(act && ax == 1) != 0;
                 }
-                const bool any_x = __ballot(act && ax == 0) != 0, any_y = __ballot(act && ax == 1) != 0;
                 if (lane == 0) s_axes[wave] = any_y ? (any_x ? 2 : 1) : 0;
             }
             __syncthreads();
 #pragma unroll
             for (int s = 0; s < kBpViews; s++) {
-                const int base = kb0[s] + p * kBpBins;
-                const int wlo = max(klo[s] - base, 0), whi = min(khi[s] - base, kBpBins - 1);
+                const int base = kb0[s] + p * BINS;
+                const int wlo = max(klo[s] - base, 0), whi = min(khi[s] - base, BINS - 1);
                 const int axes = __builtin_amdgcn_readfirstlane(s_axes[s]);   // uniform over the block
                 if (axes == 0)
-                    bp_candidates<0, BT>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc_a, acc_b);
+                    bp_candidates<0, BT, PIX>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
                 else if (axes == 1)
-                    bp_candidates<1, BT>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc_a, acc_b);
+                    bp_candidates<1, BT, PIX>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
                 else
-                    bp_candidates<2, BT>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc_a, acc_b);
+                    bp_candidates<2, BT, PIX>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
             }
             __syncthreads();
         }
 #pragma unroll
-        for (int q = 0; q < BT; q++) {
-            tot_a[q] += (double)acc_a[q];
-            tot_b[q] += (double)acc_b[q];
-        }
+        for (int r = 0; r < PIX; r++)
+#pragma unroll
+            for (int q = 0; q < BT; q++) tot[r][q] += (double)acc[r][q];
     }
     const int nblk = gridDim.x * gridDim.y;
     const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-    float ra[BT], rb[BT];     // RESIDUAL: r of both pixels for every image (0 beyond the batch)
+    float res[PIX][BT];     // RESIDUAL: r of every pixel and image (0 outside the image or batch)
 #pragma unroll
     for (int q = 0; q < BT; q++) {
-        ra[q] = rb[q] = 0.f;
+#pragma unroll
+        for (int r = 0; r < PIX; r++) res[r][q] = 0.f;
         const int b = b0 + q;
         if (b >= batch) continue;     // uniform across the block
-        const size_t ia = (size_t)b * n * n + (size_t)j * n + i, ib = ia + n;
         double part = 0.0;
-        if (MODE == BP_PLAIN) {
-            if (va) a.out[ia] = (float)tot_a[q];
-            if (vb) a.out[ib] = (float)tot_b[q];
-        } else if (MODE == BP_MATVEC) {
-            if (va) {
-                const float pv = a.aux[ia];
-                const float qv = (float)fma((double)a.mu, (double)pv, tot_a[q]);
-                a.out[ia] = qv;
-                part = (double)pv * (double)qv;
-            }
-            if (vb) {
-                const float pv = a.aux[ib];
-                const float qv = (float)fma((double)a.mu, (double)pv, tot_b[q]);
-                a.out[ib] = qv;
+#pragma unroll
+        for (int r = 0; r < PIX; r++) {
+            if (i >= n || j + r >= n) continue;
+            const size_t idx = (size_t)b * n * n + (size_t)(j + r) * n + i;
+            if (MODE == BP_PLAIN) {
+                a.out[idx] = (float)tot[r][q];
+            } else if (MODE == BP_MATVEC) {
+                const float pv = a.aux[idx];
+                const float qv = (float)fma((double)a.mu, (double)pv, tot[r][q]);
+                a.out[idx] = qv;
                 part += (double)pv * (double)qv;
-            }
-        } else if (MODE == BP_STEP) {
-            if (va) a.out[ia] = (float)fma((double)a.mu, (double)a.rhs[ia] - tot_a[q], (double)a.aux[ia]);
-            if (vb) a.out[ib] = (float)fma((double)a.mu, (double)a.rhs[ib] - tot_b[q], (double)a.aux[ib]);
-        } else {  // BP_RESIDUAL
-            if (va) {
-                const float r = (float)((double)a.out[ia] - fma((double)a.mu, (double)a.aux[ia], tot_a[q]));
-                a.out[ia] = r;
-                a.p_out[ia] = r;
-                ra[q] = r;
-                part = (double)r * (double)r;
-            }
-            if (vb) {
-                const float r = (float)((double)a.out[ib] - fma((double)a.mu, (double)a.aux[ib], tot_b[q]));
-                a.out[ib] = r;
-                a.p_out[ib] = r;
-                rb[q] = r;
-                part += (double)r * (double)r;
+            } else if (MODE == BP_STEP) {
+                a.out[idx] = (float)fma((double)a.mu, (double)a.rhs[idx] - tot[r][q], (double)a.aux[idx]);
+            } else {  // BP_RESIDUAL
+                const float rv = (float)((double)a.out[idx] - fma((double)a.mu, (double)a.aux[idx], tot[r][q]));
+                a.out[idx] = rv;
+                a.p_out[idx] = rv;
+                res[r][q] = rv;
+                part += (double)rv * (double)rv;
             }
         }
         if (REDUCE) block_partial<256>(part, a.partial + (size_t)b * nblk + blk);
     }
     if (MODE == BP_RESIDUAL && a.pad_out.base) {    // (float16 copies are built separately)
         constexpr int P = BT < 2 ? BT : 2;    // pad_group(batch)
-        store_padded_pair<BT, P>(a.pad_out.base + (size_t)b0 * 2 * n * g.line, n, g.line, i0, j0, tx, ty, ra, rb);
+        store_padded_column<BT, P, PIX>(a.pad_out.base + (size_t)b0 * 2 * n * g.line, n, g.line, i0, j0, tx, ty, res);
     }
 }
 
 template <int MODE, bool REDUCE>
 static void launch_bp_mode(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s) {
-    const int bt = image_group(batch);
-    dim3 grid((g.n + 15) / 16, (g.n + 31) / 32, (batch + bt - 1) / bt), block(256);
-    if (bt == 16) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 16>), grid, block, 0, s, g, y, a, batch);
-    else if (bt == 8) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 8>), grid, block, 0, s, g, y, a, batch);
-    else if (bt == 4) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 4>), grid, block, 0, s, g, y, a, batch);
-    else if (bt == 2) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 2>), grid, block, 0, s, g, y, a, batch);
-    else hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 1>), grid, block, 0, s, g, y, a, batch);
+    const int bt = image_group(batch), pix = bp_pix(batch);
+    dim3 grid((g.n + 15) / 16, (g.n + 16 * pix - 1) / (16 * pix), (batch + bt - 1) / bt), block(256);
+    if (bt == 16) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 16, 2>), grid, block, 0, s, g, y, a, batch);
+    else if (bt == 8) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 8, 2>), grid, block, 0, s, g, y, a, batch);
+    else if (bt == 4) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 4, 2>), grid, block, 0, s, g, y, a, batch);
+    else if (bt == 2) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 2, 2>), grid, block, 0, s, g, y, a, batch);
+    else hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 1, 2>), grid, block, 0, s, g, y, a, batch);
 }
 
 hipError_t launch_backproject(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s) {

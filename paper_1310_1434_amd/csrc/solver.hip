@@ -136,7 +136,7 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
     if (st.reg == 2) return fbs_iteration(p, B, batch, st, s);
     const KGeom kg = p->kgeom();
     const RampTables rt = p->ramp_tables();
-    const int n = p->g.n, rows = batch * p->g.n_views, nblk = tiles16(n), nblk_bp = bp_blocks(n);
+    const int n = p->g.n, rows = batch * p->g.n_views, nblk = tiles16(n), nblk_bp = bp_blocks(n, batch);
     const size_t np = (size_t)n * n;
     const int grp = image_group(batch);
     const bool tf = st.reg == 0;
