@@ -263,7 +263,7 @@ def main():
         summarize_pmc(a.summarize_pmc[0], a.summarize_pmc[1], a.batch)
         return
     if a.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {a.gpus} is not supported "
+        print(f"bench.py: measures one GPU; --gpus {a.gpus} is not supported "
               "(independent reconstructions shard across GPUs with no communication)", file=sys.stderr)
         sys.exit(2)
     import torch
