@@ -496,12 +496,15 @@ int bp_blocks(int n, int batch) { return ((n + 15) / 16) * ((n + 16 * bp_pix(bat
 
 template <int MODE, bool REDUCE, int BT, int PIX>
 __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __restrict__ y, BpArgs a, int batch) {
-    constexpr int BINS = 32 * PIX;    // staged bins per view and pass
-    constexpr int TH = 16 * PIX;      // tile height
-    static_assert(kBpViews * kWave == 256 && BINS % kWave == 0, "one wavefront stages one view");
-    __shared__ __align__(16) RayEntry s_ray[kBpViews][BINS];
-    __shared__ __align__(16) float s_val[kBpViews][BINS * BT];
-    __shared__ int s_axes[kBpViews];     // staged rays all x-driven (0), all y-driven (1), or both (2)
+    constexpr int NV = 8;                  // views per pass, two per wavefront (the same for every group size)
+    constexpr int VW = NV / 4;             // views staged per wavefront
+    constexpr int BINS = 32 * PIX;         // staged bins per view and pass
+    constexpr int TH = 16 * PIX;           // tile height
+    static_assert(BINS % kWave == 0, "whole wavefronts stage a view");
+    __shared__ __align__(16) RayEntry s_ray[NV][BINS];
+    __shared__ __align__(16) float s_val[NV][BINS * BT];
+    __shared__ int s_axes[NV];           // staged rays all x-driven (0), all y-driven (1), or both (2)
+    __shared__ int s_win[NV][3];         // tile window: first bin, bin count, half-width (float bits)
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i0 = blockIdx.x * 16, j0 = blockIdx.y * TH;
@@ -522,14 +525,15 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     for (int r = 0; r < PIX; r++)
 #pragma unroll
         for (int q = 0; q < BT; q++) tot[r][q] = 0.0;
-    for (int v0 = 0; v0 < g.n_views; v0 += kBpViews) {
-        // Tile windows of the pass's views, computed redundantly by every
-        // wavefront: lane 4 s + c takes corner c of view v0 + s.
-        float kc_lo = 3e38f, kc_hi = -3e38f, hw = 0.f;
+    for (int v0 = 0; v0 < g.n_views; v0 += NV) {
+        // Tile windows: wavefront w takes the views w + 4 h of the pass (h < VW),
+        // lane 4 h + c corner c; they reach the other wavefronts through LDS.
+        int my_kb0[VW], my_nb[VW];
         {
-            const int s = (lane >> 2) & 3, c = lane & 3;
-            const int v = v0 + s;
-            if (lane < 16 && v < g.n_views) {
+            float kc_lo = 3e38f, kc_hi = -3e38f, hw = 0.f;
+            const int h = lane >> 2, c = lane & 3;
+            const int v = v0 + wave + 4 * h;
+            if (h < VW && v < g.n_views) {
                 const float2 cs = g.views[v];
                 const float qx = cx[c & 1], qy = cy[c >> 1];
                 const float kc = bin_of(g, qx, qy, cs.x, cs.y);
@@ -557,38 +561,23 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                                  : g.sdd * dm * (bp_min + ap_max) *
                                        __builtin_amdgcn_rcpf(bp_min * (bp_min - dm)) * g.inv_bin;
             }
-        }
-        int kb0[kBpViews], nb[kBpViews];
-        float hws[kBpViews];
 #pragma unroll
-        for (int s = 0; s < kBpViews; s++) {
-            const float klo_f = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc_lo), 4 * s));
-            const float khi_f = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc_hi), 4 * s));
-            hws[s] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hw), 4 * s));
-            if (v0 + s < g.n_views) {
-                kb0[s] = max(0, (int)floorf(klo_f - hws[s] - 0.5f));
-                const int kb1 = min(g.n_bins - 1, (int)ceilf(khi_f + hws[s] + 0.5f));
-                nb[s] = max(0, kb1 - kb0[s] + 1);
-            } else {
-                kb0[s] = 0;
-                nb[s] = 0;
-            }
-        }
-        int passes = 1;
-#pragma unroll
-        for (int s = 0; s < kBpViews; s++) passes = max(passes, (nb[s] + BINS - 1) / BINS);
-        // the column's bin interval per view (absolute bins), from its first and last centre
-        int klo[kBpViews], khi[kBpViews];
-#pragma unroll
-        for (int s = 0; s < kBpViews; s++) {
-            klo[s] = 0;
-            khi[s] = -1;
-            if (v0 + s < g.n_views) {
-                const float2 cs = g.views[v0 + s];
-                const float ka = bin_of(g, px, py, cs.x, cs.y);
-                const float kb = bin_of(g, px, py + (PIX - 1) * g.pixel, cs.x, cs.y);
-                klo[s] = max(kb0[s], (int)ceilf(fminf(ka, kb) - hws[s] - 0.01f));
-                khi[s] = min(kb0[s] + nb[s] - 1, (int)floorf(fmaxf(ka, kb) + hws[s] + 0.01f));
+            for (int hh = 0; hh < VW; hh++) {
+                const float klo_f = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc_lo), 4 * hh));
+                const float khi_f = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc_hi), 4 * hh));
+                const float hws = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hw), 4 * hh));
+                my_kb0[hh] = 0;
+                my_nb[hh] = 0;
+                if (v0 + wave + 4 * hh < g.n_views) {
+                    my_kb0[hh] = max(0, (int)floorf(klo_f - hws - 0.5f));
+                    const int kb1 = min(g.n_bins - 1, (int)ceilf(khi_f + hws + 0.5f));
+                    my_nb[hh] = max(0, kb1 - my_kb0[hh] + 1);
+                }
+                if (lane == 0) {
+                    s_win[wave + 4 * hh][0] = my_kb0[hh];
+                    s_win[wave + 4 * hh][1] = my_nb[hh];
+                    s_win[wave + 4 * hh][2] = __float_as_int(hws);
+                }
             }
         }
         float acc[PIX][BT];
@@ -596,42 +585,50 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
         for (int r = 0; r < PIX; r++)
 #pragma unroll
             for (int q = 0; q < BT; q++) acc[r][q] = 0.f;
+        int passes = 1;
         for (int p = 0; p < passes; p++) {
-            // stage: wavefront s loads bins kb0 + p * BINS + (lane, lane + 64, ...) of view v0 + s
-            {
-                int my_kb0 = kb0[0], my_nb = nb[0];
+            // stage: wavefront w loads bins kb0 + p * BINS + (lane, lane + 64, ...) of its views
 #pragma unroll
-                for (int s = 1; s < kBpViews; s++)
-                    if (wave == s) {
-                        my_kb0 = kb0[s];
-                        my_nb = nb[s];
-                    }
+            for (int hh = 0; hh < VW; hh++) {
+                const int sv = wave + 4 * hh;
                 bool any_x = false, any_y = false;
 #pragma unroll
-                for (int h = 0; h < BINS / kWave; h++) {
-                    const int slot = h * kWave + lane;
+                for (int hb = 0; hb < BINS / kWave; hb++) {
+                    const int slot = hb * kWave + lane;
                     const int w = p * BINS + slot;
-                    const bool act = w < my_nb;
+                    const bool act = w < my_nb[hh];
                     int ax = 0;
                     if (act) {
-                        const int v = v0 + wave, k = my_kb0 + w;
+                        const int v = v0 + sv, k = my_kb0[hh] + w;
                         const RayEntry e = g.rays[(size_t)v * g.n_bins + k];
-                        s_ray[wave][slot] = e;
+                        s_ray[sv][slot] = e;
                         ax = ray_axis(e.meta);
                         float t[BT];
                         load_group<BT>(yg + ((size_t)v * g.ds + k) * BT, t);
-                        store_group<BT>(&s_val[wave][slot * BT], t);
+                        store_group<BT>(&s_val[sv][slot * BT], t);
                     }
                     any_x = any_x || __ballot(act && ax == 0) != 0;
                     any_y = any_y || __ballot(act && ax == 1) != 0;
                 }
-                if (lane == 0) s_axes[wave] = any_y ? (any_x ? 2 : 1) : 0;
+                if (lane == 0) s_axes[sv] = any_y ? (any_x ? 2 : 1) : 0;
             }
             __syncthreads();
 #pragma unroll
-            for (int s = 0; s < kBpViews; s++) {
-                const int base = kb0[s] + p * BINS;
-                const int wlo = max(klo[s] - base, 0), whi = min(khi[s] - base, BINS - 1);
+            for (int s = 0; s < NV; s++) {
+                // the view's window (uniform over the block), and this column's
+                // bin interval from its first and last centre
+                const int kb0 = __builtin_amdgcn_readfirstlane(s_win[s][0]);
+                const int nbs = __builtin_amdgcn_readfirstlane(s_win[s][1]);
+                if (p == 0) passes = max(passes, (nbs + BINS - 1) / BINS);
+                if (v0 + s >= g.n_views) continue;
+                const float hws = __int_as_float(__builtin_amdgcn_readfirstlane(s_win[s][2]));
+                const float2 cs = g.views[v0 + s];
+                const float ka = bin_of(g, px, py, cs.x, cs.y);
+                const float kb = bin_of(g, px, py + (PIX - 1) * g.pixel, cs.x, cs.y);
+                const int klo = max(kb0, (int)ceilf(fminf(ka, kb) - hws - 0.01f));
+                const int khi = min(kb0 + nbs - 1, (int)floorf(fmaxf(ka, kb) + hws + 0.01f));
+                const int base = kb0 + p * BINS;
+                const int wlo = max(klo - base, 0), whi = min(khi - base, BINS - 1);
                 const int axes = __builtin_amdgcn_readfirstlane(s_axes[s]);   // uniform over the block
                 if (axes == 0)
                     bp_candidates<0, BT, PIX>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
