@@ -28,8 +28,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "mixed_f16": 2500.0, "mixed_bf16": 2500.0}
-# VALU issue peak: 256 CUs x 4 SIMD x 16 lanes per clock x 2.4 GHz (non-packed lane operations)
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# VALU issue peak: 256 CUs x 4 SIMD x 32 lanes per clock x 2.4 GHz (non-packed lane
+# operations; a wave64 float32 operation issues in two cycles, so the published
+# float32 vector rate, 157.3 TFLOP/s, is 78.6 T fused multiply-adds per second)
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 # essential VALU lane operations of one Joseph sample (ray-step): advance the
 # fixed-point intercept, convert its fraction, form the two weights, form the
 # sample address, two fused multiply-adds

@@ -458,8 +458,9 @@ __device__ __forceinline__ void joseph_column(const RayEntry& e, int i, int j, i
     }
 }
 
-// Accumulate the candidates [wlo, whi] (staged bins of one view) into the pixels.
-template <int AX, int BT, int PIX>
+// Accumulate the candidates [wlo, whi] (staged bins of one view, SV floats per
+// slot) into the pixels, two at a time.
+template <int AX, int BT, int PIX, int SV>
 __device__ __forceinline__ void bp_candidates(const RayEntry* rays, const float* vals, int wlo, int whi, int i,
                                               int j, int c0, float (&acc)[PIX][BT]) {
     for (int w = wlo; w <= whi; w += 2) {
@@ -467,8 +468,8 @@ __device__ __forceinline__ void bp_candidates(const RayEntry* rays, const float*
         const int w1 = two ? w + 1 : w;
         const RayEntry e0 = rays[w], e1 = rays[w1];
         float y0[BT], y1[BT];
-        load_group<BT>(vals + w * BT, y0);
-        load_group<BT>(vals + w1 * BT, y1);
+        load_group<BT>(vals + w * SV, y0);
+        load_group<BT>(vals + w1 * SV, y1);
         float wt0[PIX], wt1[PIX];
         joseph_column<AX, PIX>(e0, i, j, c0, wt0);
         joseph_column<AX, PIX>(e1, i, j, c0, wt1);
@@ -478,6 +479,55 @@ __device__ __forceinline__ void bp_candidates(const RayEntry* rays, const float*
             const float w1r = wt1[r] * keep;
 #pragma unroll
             for (int q = 0; q < BT; q++) acc[r][q] = fmaf(w1r, y1[q], fmaf(wt0[r], y0[q], acc[r][q]));
+        }
+    }
+}
+
+// The same with the axis choice (uniform over the block) inside the candidate
+// loop: one loop, so the accumulators keep one set of registers across views
+// (the per-axis loops make the compiler move them between register sets at
+// every view), and the next pair is read at the end of an iteration.  Faster
+// with 16-image groups; the per-axis loops are faster with fewer images.  Both
+// perform the same operations in the same order.
+constexpr int kBpInLoopMin = 16;
+template <int PIX>
+__device__ __forceinline__ void joseph_pair(int axes, const RayEntry& e0, const RayEntry& e1, int i, int j, int c0,
+                                            float (&wt0)[PIX], float (&wt1)[PIX]) {
+    if (axes == 0) {
+        joseph_column<0, PIX>(e0, i, j, c0, wt0);
+        joseph_column<0, PIX>(e1, i, j, c0, wt1);
+    } else if (axes == 1) {
+        joseph_column<1, PIX>(e0, i, j, c0, wt0);
+        joseph_column<1, PIX>(e1, i, j, c0, wt1);
+    } else {
+        joseph_column<2, PIX>(e0, i, j, c0, wt0);
+        joseph_column<2, PIX>(e1, i, j, c0, wt1);
+    }
+}
+template <int BT, int PIX, int SV>
+__device__ __forceinline__ void bp_candidates_any(int axes, const RayEntry* rays, const float* vals, int wlo, int whi,
+                                                  int i, int j, int c0, float (&acc)[PIX][BT]) {
+    if (wlo > whi) return;
+    RayEntry e0 = rays[wlo], e1 = rays[min(wlo + 1, whi)];
+    float y0[BT], y1[BT];
+    load_group<BT>(vals + wlo * SV, y0);
+    load_group<BT>(vals + min(wlo + 1, whi) * SV, y1);
+    for (int w = wlo; w <= whi; w += 2) {
+        float wt0[PIX], wt1[PIX];
+        joseph_pair<PIX>(axes, e0, e1, i, j, c0, wt0, wt1);
+        const float keep = w + 1 <= whi ? 1.f : 0.f;
+#pragma unroll
+        for (int r = 0; r < PIX; r++) {
+            const float w1r = wt1[r] * keep;
+#pragma unroll
+            for (int q = 0; q < BT; q++) acc[r][q] = fmaf(w1r, y1[q], fmaf(wt0[r], y0[q], acc[r][q]));
+        }
+        if (w + 2 <= whi) {
+            const int m1 = min(w + 3, whi);
+            e0 = rays[w + 2];
+            e1 = rays[m1];
+            load_group<BT>(vals + (w + 2) * SV, y0);
+            load_group<BT>(vals + m1 * SV, y1);
         }
     }
 }
@@ -502,7 +552,10 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     constexpr int TH = 16 * PIX;           // tile height
     static_assert(BINS % kWave == 0, "whole wavefronts stage a view");
     __shared__ __align__(16) RayEntry s_ray[NV][BINS];
-    __shared__ __align__(16) float s_val[NV][BINS * BT];
+    // slot stride: BT floats, padded by 4 from 8 images up so that the 16-byte
+    // reads of 8 consecutive slots fall in distinct LDS banks
+    constexpr int SV = BT >= 8 ? BT + 4 : BT;
+    __shared__ __align__(16) float s_val[NV][BINS * SV];
     __shared__ int s_axes[NV];           // staged rays all x-driven (0), all y-driven (1), or both (2)
     __shared__ int s_win[NV][3];         // tile window: first bin, bin count, half-width (float bits)
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -605,7 +658,7 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                         ax = ray_axis(e.meta);
                         float t[BT];
                         load_group<BT>(yg + ((size_t)v * g.ds + k) * BT, t);
-                        store_group<BT>(&s_val[sv][slot * BT], t);
+                        store_group<BT>(&s_val[sv][slot * SV], t);
                     }
                     any_x = any_x || __ballot(act && ax == 0) != 0;
                     any_y = any_y || __ballot(act && ax == 1) != 0;
@@ -630,12 +683,14 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                 const int base = kb0 + p * BINS;
                 const int wlo = max(klo - base, 0), whi = min(khi - base, BINS - 1);
                 const int axes = __builtin_amdgcn_readfirstlane(s_axes[s]);   // uniform over the block
-                if (axes == 0)
-                    bp_candidates<0, BT, PIX>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
+                if constexpr (BT >= kBpInLoopMin)
+                    bp_candidates_any<BT, PIX, SV>(axes, s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
+                else if (axes == 0)
+                    bp_candidates<0, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
                 else if (axes == 1)
-                    bp_candidates<1, BT, PIX>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
+                    bp_candidates<1, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
                 else
-                    bp_candidates<2, BT, PIX>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
+                    bp_candidates<2, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
             }
             __syncthreads();
         }
