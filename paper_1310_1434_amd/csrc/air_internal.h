@@ -122,10 +122,11 @@ struct RampTables {
     float out_scale;           // kappa * 2^-12 for the 16-bit modes
     const float* wsq;          // [ds] D^(1/2) of a cosine-weighted C (applied before and after R), or null
 };
-// scale: 0 = C y;  RAMP_POST = S C y;  RAMP_PRE | RAMP_POST = S C S y  (S = diag(step)).
+// scale: 0 = C y;  RAMP_POST = S C y  (S = diag(step); S C S y takes a projection
+// that is already scaled: launch_project(..., scaled = true)).
 // Input rows [batch * n_views][ds].  Output: the same layout when grp == 0, else
 // group-interleaved with G = grp (the backprojector's input).
-enum { RAMP_PRE = 1, RAMP_POST = 2 };
+enum { RAMP_POST = 2 };
 hipError_t launch_ramp(int prec, const RampTables& t, const float* y, float* yf, int rows, int ds, int scale,
                        int grp, hipStream_t s);
 

@@ -343,13 +343,13 @@ air_status air_normal_apply(air_plan p, const float* x, float* out, int32_t batc
     const PadBuf pad = plan_pad(p, p->at<float>(p->off_pad), p->at<float>(p->off_pscale));
     float* s1 = p->at<float>(p->off_s1);
     float* s2 = p->at<float>(p->off_s2);
-    // A^T C A x = J^T (S C S) J x;  A^T A x = J^T S^2 J x
+    // A^T C A x = J^T (S C S) J x;  A^T A x = J^T S^2 J x  (the projector applies the first S)
     if (air_status e = build_pad(p, x, pad, p->at<double>(p->off_ppart), batch, s)) return e;
-    AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, false, s));
+    AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, true, s));
     const int grp = image_group(batch);
     if (filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), s1, s2, batch * p->g.n_views, p->ds,
-                                              RAMP_PRE | RAMP_POST, grp, s));
-    else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 2, grp, s));
+                                              RAMP_POST, grp, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 1, grp, s));
     const float* src = s2;
     BpArgs a{};
     a.mode = BP_MATVEC;

@@ -18,7 +18,8 @@ namespace air {
 //   meta = lo | (hi + 1) << 15 | axis << 30
 // The path length per driving step, s = pixel |d| / |d_drive|, is kept in a
 // separate per-ray array: A = S J with J the bare interpolation weights, and
-// the normal operator A^T C A = J^T (S C S) J applies S inside the ramp stage.
+// the normal operator A^T C A = J^T (S C S) J applies the first S in the
+// projector's epilogue and the second in the ramp's.
 // Integer arithmetic makes the intercept exact and associative: the forward
 // projector advances it by 2m per step and the backprojector evaluates it
 // directly, and both get the same bits.  Resolution 2^-32 pixel (the slope's

@@ -86,17 +86,9 @@ __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, f
     const RampRow ar = ramp_row(m, batch, n_views, ds, grp);
     const bool mvalid = m < mrows && ar.valid;
     const float* arow = y + (mvalid ? ((size_t)ar.b * n_views + ar.v) * ds : 0);
-    const float* srow = step + (mvalid ? (size_t)ar.v * ds : 0);
     f4_t acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < ds; k0 += 16) {
         float4 av = *reinterpret_cast<const float4*>(arow + k0 + 4 * slot);
-        if (SCALE & RAMP_PRE) {
-            const float4 sv = *reinterpret_cast<const float4*>(srow + k0 + 4 * slot);
-            av.x *= sv.x;
-            av.y *= sv.y;
-            av.z *= sv.z;
-            av.w *= sv.w;
-        }
         if (wsq) {      // cosine-weighted C: D^(1/2) before R
             const float4 wv = *reinterpret_cast<const float4*>(wsq + k0 + 4 * slot);
             av.x *= wv.x;
@@ -156,17 +148,10 @@ __global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y,
     const RampRow ar = ramp_row(m, batch, t.n_views, ds, grp);
     const bool mvalid = m < mrows && ar.valid;
     const float* arow = y + (mvalid ? ((size_t)ar.b * t.n_views + ar.v) * ds : 0);
-    const float* srow = t.step + (mvalid ? (size_t)ar.v * ds : 0);
     f4_t accA0 = {0.f, 0.f, 0.f, 0.f}, accA1 = accA0, accB0 = accA0, accB1 = accA0;
     for (int k0 = 0; k0 < ds; k0 += 32) {
         float4 a0 = *reinterpret_cast<const float4*>(arow + k0 + 8 * slot);
         float4 a1 = *reinterpret_cast<const float4*>(arow + k0 + 8 * slot + 4);
-        if (SCALE & RAMP_PRE) {
-            const float4 s0 = *reinterpret_cast<const float4*>(srow + k0 + 8 * slot);
-            const float4 s1 = *reinterpret_cast<const float4*>(srow + k0 + 8 * slot + 4);
-            a0.x *= s0.x; a0.y *= s0.y; a0.z *= s0.z; a0.w *= s0.w;
-            a1.x *= s1.x; a1.y *= s1.y; a1.z *= s1.z; a1.w *= s1.w;
-        }
         if (t.wsq) {    // cosine-weighted C: D^(1/2) before R
             const float4 w0 = *reinterpret_cast<const float4*>(t.wsq + k0 + 8 * slot);
             const float4 w1 = *reinterpret_cast<const float4*>(t.wsq + k0 + 8 * slot + 4);
@@ -278,7 +263,6 @@ hipError_t launch_ramp(int prec, const RampTables& t, const float* y, float* yf,
     switch (scale) {
     case 0: return launch_ramp_scaled<0>(prec, t, y, yf, rows, ds, grp, s);
     case RAMP_POST: return launch_ramp_scaled<RAMP_POST>(prec, t, y, yf, rows, ds, grp, s);
-    case RAMP_PRE | RAMP_POST: return launch_ramp_scaled<RAMP_PRE | RAMP_POST>(prec, t, y, yf, rows, ds, grp, s);
     default: return hipErrorInvalidValue;
     }
 }
