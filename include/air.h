@@ -196,7 +196,14 @@ air_status air_solve_workspace_size(air_plan plan, int32_t batch, size_t* bytes)
  * (split Bregman) or ||X_new - X_old||_2 (forward-backward).
  * ws: device, >= air_solve_workspace_size(plan, batch) bytes, 256-byte
  * aligned; it is scratch for this call only.  The plan's own workspace is
- * not used, so batch may exceed max_batch. */
+ * not used, so batch may exceed max_batch.
+ * A batch of 8 or more runs as two sub-batches (the first ceil(batch / 2)
+ * images, then the rest) on two streams that the plan creates on first use
+ * (default priority): they wait on an event recorded on `stream`, and
+ * `stream` waits on an event recorded on each, so the call stays ordered on
+ * `stream` (and can be captured there).  While kernel timing is enabled the
+ * whole batch runs on `stream`.  Results are the same bits either way.  Calls
+ * on one plan must come from one host thread at a time. */
 air_status air_solve(air_plan plan, const float* Y, float* X, int32_t batch, const air_solve_params* p,
                      double* resid, void* ws, size_t ws_bytes, hipStream_t stream);
 

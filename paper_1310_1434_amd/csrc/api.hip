@@ -399,11 +399,70 @@ air_status air_framelet(air_plan p, const float* in, float* out, int32_t batch, 
 
 extern "C" {
 
+// A solve of at least kSplitMin images runs as two sub-batches, each on its own
+// stream: one sub-batch's projections (bound by the gather issue rate) then
+// overlap the other's backprojections (bound by VALU and LDS).  Measured at
+// C2: 2 x 8 images 1.10x and 2 x 16 images 1.19x the throughput of one
+// batch; every image gets the same bits either way.  Kernel timing keeps one
+// stream, so the per-kernel times are those of kernels running alone.
+constexpr int kSplitMin = 8;
+static int solve_parts(const air_plan_s* p, int batch) { return batch >= kSplitMin && !p->timing ? 2 : 1; }
+static int part_size(int batch, int parts, int i) { return parts == 1 ? batch : (i == 0 ? (batch + 1) / 2 : batch / 2); }
+static size_t part_offset(const air_plan_s* p, int batch, int parts, int i) {
+    return i == 0 ? 0 : (solve_layout(p, part_size(batch, parts, 0)).total + 255) / 256 * 256;
+}
+static size_t solve_bytes(const air_plan_s* p, int batch) {
+    size_t one = solve_layout(p, batch).total;
+    if (batch < kSplitMin) return one;
+    const size_t two = part_offset(p, batch, 2, 1) + solve_layout(p, part_size(batch, 2, 1)).total;
+    return std::max(one, two);    // (kernel timing may choose one part)
+}
+
 air_status air_solve_workspace_size(air_plan p, int32_t batch, size_t* bytes) {
     if (air_status st = check_plan(p, false)) return st;
     if (air_status st = check_batch(p, batch, false)) return st;
     if (!bytes) return fail(AIR_E_INVALID, "bytes is null");
-    *bytes = solve_layout(p, batch).total;
+    *bytes = solve_bytes(p, batch);
+    return AIR_OK;
+}
+
+// The two sub-batch streams of the current device (default priority), created
+// once per device and kept until the process ends.  All plans share them: each
+// stream is bound to a hardware queue when it is created, and two streams
+// that end up on one queue run one after the other (measured: per-plan stream
+// pairs, created after other streams, lost the overlap).
+static hipError_t device_sub_streams(hipStream_t (&out)[2]) {
+    static std::mutex mu;
+    static hipStream_t streams[64][2] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    for (int i = 0; i < 2; i++)
+        if (!streams[dev][i] && (e = hipStreamCreateWithFlags(&streams[dev][i], hipStreamNonBlocking)) != hipSuccess)
+            return e;
+    out[0] = streams[dev][0];
+    out[1] = streams[dev][1];
+    return hipSuccess;
+}
+
+// One sub-batch: images [b0, b0 + nb) of the call, workspace at ws.
+static air_status solve_part(air_plan p, const float* Y, float* X, int b0, int nb, const air_solve_params* prm,
+                             double* resid, char* ws, hipStream_t s) {
+    const size_t np = (size_t)p->g.n * p->g.n, nyv = (size_t)p->g.n_views * p->g.n_bins;
+    SolveBufs B = solve_bufs(p, solve_layout(p, nb), ws, X + b0 * np, nb);
+    if (resid) {
+        B.resid = resid + (size_t)b0 * prm->n_outer;
+        B.resid_stride = prm->n_outer;
+    } else {
+        B.iters = nullptr;          // residual norms go to scratch, one slot per image
+    }
+    const SolveSetup setup{prm->reg, prm->filter, prm->lambda, prm->mu, prm->n_cg};
+    if (air_status st = solve_init(p, B, Y + b0 * nyv, nb, setup, s)) return st;
+    const int n_out = prm->reg == 1 ? 1 : prm->n_outer;
+    for (int k = 0; k < n_out; k++)
+        if (air_status st = solve_outer(p, B, nb, setup, s)) return st;
     return AIR_OK;
 }
 
@@ -418,21 +477,31 @@ air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const 
     if (!(prm->lambda >= 0.0) || !std::isfinite(prm->lambda)) return fail(AIR_E_INVALID, "lambda must be >= 0");
     if (prm->reg != 1 && (!(prm->mu > 0.0) || !std::isfinite(prm->mu))) return fail(AIR_E_INVALID, "mu must be > 0");
     if (prm->n_outer < 0 || prm->n_cg < 0) return fail(AIR_E_INVALID, "iteration counts must be >= 0");
-    const SolveLayout L = solve_layout(p, batch);
-    if (ws_bytes < L.total) return fail(AIR_E_NOMEM, "workspace smaller than air_solve_workspace_size");
-    SolveBufs B = solve_bufs(p, L, static_cast<char*>(ws), X, batch);
-    if (resid) {
-        B.resid = resid;
-        B.resid_stride = prm->n_outer;
-    } else {
-        B.iters = nullptr;          // residual norms go to scratch, one slot per image
+    if (ws_bytes < solve_bytes(p, batch)) return fail(AIR_E_NOMEM, "workspace smaller than air_solve_workspace_size");
+    char* w = static_cast<char*>(ws);
+    const int parts = solve_parts(p, batch);
+    if (parts == 1) return solve_part(p, Y, X, 0, batch, prm, resid, w, s);
+    // fork: both sub-streams wait for the caller's stream; join: the caller's
+    // stream waits for both (also after a failed launch, so that nothing of
+    // this call is still running on the workspace once the stream moves on)
+    hipStream_t sub[2];
+    AIR_HIP(device_sub_streams(sub));
+    std::lock_guard<std::mutex> lock(p->fork_mu);
+    for (int i = 0; i < 2; i++)
+        if (!p->join_ev[i]) AIR_HIP(hipEventCreateWithFlags(&p->join_ev[i], hipEventDisableTiming));
+    if (!p->fork_ev) AIR_HIP(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
+    AIR_HIP(hipEventRecord(p->fork_ev, s));
+    air_status result = AIR_OK;
+    int b0 = 0;
+    for (int i = 0; i < 2; i++) {
+        const int nb = part_size(batch, 2, i);
+        AIR_HIP(hipStreamWaitEvent(sub[i], p->fork_ev, 0));
+        if (result == AIR_OK) result = solve_part(p, Y, X, b0, nb, prm, resid, w + part_offset(p, batch, 2, i), sub[i]);
+        AIR_HIP(hipEventRecord(p->join_ev[i], sub[i]));
+        AIR_HIP(hipStreamWaitEvent(s, p->join_ev[i], 0));
+        b0 += nb;
     }
-    const SolveSetup setup{prm->reg, prm->filter, prm->lambda, prm->mu, prm->n_cg};
-    if (air_status st = solve_init(p, B, Y, batch, setup, s)) return st;
-    const int n_out = prm->reg == 1 ? 1 : prm->n_outer;
-    for (int k = 0; k < n_out; k++)
-        if (air_status st = solve_outer(p, B, batch, setup, s)) return st;
-    return AIR_OK;
+    return result;
 }
 
 }  // extern "C"

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -66,6 +67,11 @@ struct air_plan_s {
     bool timing = false;
     std::vector<Timed> pending;
     std::vector<hipEvent_t> pool;
+    // air_solve's concurrent sub-batches: the events that fork the device's
+    // two sub-batch streams from, and join them back to, the caller's stream;
+    // created on first use, guarded by fork_mu.
+    hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
+    std::mutex fork_mu;
 
     ~air_plan_s() {
         for (const Timed& t : pending) {
@@ -73,6 +79,9 @@ struct air_plan_s {
             (void)hipEventDestroy(t.b);
         }
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        for (int i = 0; i < 2; i++)
+            if (join_ev[i]) (void)hipEventDestroy(join_ev[i]);
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
     }
     hipEvent_t take_event() {
         if (!pool.empty()) {

@@ -275,6 +275,33 @@ def test_solve_batch_invariance_and_determinism(air, torch_mod):
         assert torch_mod.equal(r1[0], rb[b])
 
 
+@pytest.mark.parametrize("reg", [0, 1, 2])
+def test_solve_split_batch_matches_single(air, torch_mod, reg):
+    """Batches of 8 or more run as two sub-batches on two internal streams
+    (6 + 5 images here): every image, start image and residual row is the same
+    bits as its solve alone, and the call is ordered on the caller's stream
+    (its input is written by a kernel on that stream just before the call)."""
+    w = synth.workload("c1", n_outer=3)
+    n = w.geom.n
+    ys = np.stack([synth.make_case(w, s)["y"] for s in range(11)]).astype(np.float32)
+    x0 = np.random.default_rng(5).uniform(0, 0.02, (11, n, n)).astype(np.float32)
+    plan = air.Plan(w.geom)
+    lam, mu = (w.lam, w.mu) if reg != 2 else (0.005, 1.0)
+    side = torch_mod.cuda.Stream()
+    with torch_mod.cuda.stream(side):
+        Y = dev(torch_mod, ys) * 1.0           # written on `side`, read by the solve on `side`
+        X0 = dev(torch_mod, x0) * 1.0
+        xb, rb = plan.solve(Y, lam, mu, w.n_outer, w.n_cg, reg=reg, x0=X0)
+        xb = xb * 1.0
+    side.synchronize()
+    for b in (0, 5, 6, 10):
+        x1, r1 = plan.solve(dev(torch_mod, ys[b:b + 1]), lam, mu, w.n_outer, w.n_cg, reg=reg,
+                            x0=dev(torch_mod, x0[b:b + 1]))
+        assert torch_mod.equal(x1[0], xb[b]), b
+        if reg != 1:
+            assert torch_mod.equal(r1[0], rb[b]), b
+
+
 @pytest.mark.parametrize("prec", ["mixed_f16", "mixed_bf16"])
 def test_solve_mixed_precision_c1(air, torch_mod, orc, record, prec):
     w = synth.workload("c1")
