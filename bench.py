@@ -135,7 +135,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, batch: int):
     cw = max(write.get("__amd_rocclr_copyBuffer", [0.0]))
     sf = copy_bytes / (cf * 1024.0) if cf else None
     sw = copy_bytes / (cw * 1024.0) if cw else None
-    names = {"k_project": "air::k_project<true", "k_backproject": "air::k_backproject<1, true",
+    names = {"k_project": "air::k_project<2>", "k_backproject": "air::k_backproject<1, true",
              "k_ramp_f32": "air::k_ramp_f32<2>"}
     out = {"batch": batch, "source_hash": kernel_source_hash(), "copy_fetch_kib": cf, "copy_write_kib": cw,
            "fetch_scale": sf, "write_scale": sw, "kernels": {}}

@@ -71,14 +71,14 @@ hipError_t launch_pad16(const KGeom& g, const float* x, PadBuf pad, int batch, h
 
 // ---- kernel launchers (kernels_*.hip) -------------------------------------------------
 hipError_t launch_pad(const KGeom& g, const float* x, PadBuf pad, int batch, hipStream_t s);
-// y = J x (scaled = false: bare interpolation weights) or y = A x = S J x (scaled = true).
-hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, bool scaled, hipStream_t s);
+// y = A x = S J x (rows [batch * n_views][ds]; bins past n_bins zero).
+hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, hipStream_t s);
 // Backprojector input layout: group-interleaved [ceil(batch / G)][n_views][ds][G]
 // with G = image_group(batch), so that the images a backprojector thread serves
 // are contiguous and each group is one dense block (sized for roundup(batch, 16)).  Lanes of the last group
 // beyond the batch are never written (and their results never stored).
-// out (group-interleaved, G = grp) = y (rows [batch * n_views][ds]) * step^power (power 1 or 2).
-hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, int power, int grp, hipStream_t s);
+// out (group-interleaved, G = grp) = S y (y: rows [batch * n_views][ds]).
+hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, int grp, hipStream_t s);
 
 // Backprojection epilogue modes (per pixel, acc = (J^T y)_pixel, J the bare
 // interpolation weights; callers fold the path lengths into y, which is in the

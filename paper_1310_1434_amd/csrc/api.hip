@@ -283,10 +283,10 @@ air_status air_project(air_plan p, const float* x, float* y, int32_t batch, hipS
     const PadBuf pad = plan_pad(p, p->at<float>(p->off_pad), p->at<float>(p->off_pscale));
     if (air_status e = build_pad(p, x, pad, p->at<double>(p->off_ppart), batch, s)) return e;
     if (p->direct(y)) {
-        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, y, batch, true, s));
+        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, y, batch, s));
     } else {
         float* s1 = p->at<float>(p->off_s1);
-        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, true, s));
+        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, s));
         AIR_K(AIR_K_OTHER, launch_repack(s1, p->ds, y, p->g.n_bins, batch * p->g.n_views, p->g.n_bins, p->g.n_bins, s));
     }
     return AIR_OK;
@@ -323,7 +323,7 @@ air_status air_filtered_backproject(air_plan p, const float* y, float* x, int32_
     const int grp = image_group(batch);
     if (filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, s2, batch * p->g.n_views, p->ds,
                                               RAMP_POST, grp, s));
-    else AIR_K(AIR_K_OTHER, launch_scale(p->kgeom(), src, s2, batch, 1, grp, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(p->kgeom(), src, s2, batch, grp, s));
     BpArgs a{};
     a.mode = BP_PLAIN;
     a.out = x;
@@ -345,11 +345,11 @@ air_status air_normal_apply(air_plan p, const float* x, float* out, int32_t batc
     float* s2 = p->at<float>(p->off_s2);
     // A^T C A x = J^T (S C S) J x;  A^T A x = J^T S^2 J x  (the projector applies the first S)
     if (air_status e = build_pad(p, x, pad, p->at<double>(p->off_ppart), batch, s)) return e;
-    AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, true, s));
+    AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, s));
     const int grp = image_group(batch);
     if (filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), s1, s2, batch * p->g.n_views, p->ds,
                                               RAMP_POST, grp, s));
-    else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, 1, grp, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, grp, s));
     const float* src = s2;
     BpArgs a{};
     a.mode = BP_MATVEC;

@@ -210,7 +210,7 @@ __device__ __forceinline__ bool proj_block(const KGeom& g, int chunks, int& v, i
 typedef float float2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 typedef float float4_a8 __attribute__((ext_vector_type(4), aligned(8)));
 
-template <bool SCALED, int P>
+template <int P>
 __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __restrict__ pad,
                                                          float* __restrict__ y, int chunks, int batch) {
     static_assert(P == 1 || P == 2, "images per thread");
@@ -257,12 +257,12 @@ __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __
         }
     }
     if (k >= g.ds) return;
-    const float sv = (SCALED && ray) ? g.step[(size_t)v * g.ds + k] : 1.f;
+    const float sv = ray ? g.step[(size_t)v * g.ds + k] : 0.f;
 #pragma unroll
     for (int q = 0; q < P; q++) {
         if (b0 + q >= batch) break;
         float out = 0.f;
-        if (ray) out = SCALED ? acc[q] * sv : acc[q];
+        if (ray) out = acc[q] * sv;
         y[((size_t)(b0 + q) * g.n_views + v) * g.ds + k] = out;
     }
 }
@@ -294,7 +294,7 @@ __device__ __forceinline__ void load_half_pair(const uint16_t* p, float (&s0)[P]
     }
 }
 
-template <bool SCALED, int P>
+template <int P>
 __global__ __launch_bounds__(kProjBlock) void k_project16(KGeom g, const uint16_t* __restrict__ pad,
                                                            const float* __restrict__ scale, float* __restrict__ y,
                                                            int chunks, int batch) {
@@ -334,60 +334,58 @@ __global__ __launch_bounds__(kProjBlock) void k_project16(KGeom g, const uint16_
         }
     }
     if (k >= g.ds) return;
-    const float sv = (SCALED && ray) ? g.step[(size_t)v * g.ds + k] : 1.f;
+    const float sv = ray ? g.step[(size_t)v * g.ds + k] : 0.f;
 #pragma unroll
     for (int q = 0; q < P; q++) {
         const int b = b0 + q;
         if (b >= batch) break;
         float out = 0.f;
-        if (ray) out = (SCALED ? acc[q] * sv : acc[q]) / scale[b];    // exact: scale is a power of two
+        if (ray) out = acc[q] * sv / scale[b];    // exact: scale is a power of two
         y[((size_t)b * g.n_views + v) * g.ds + k] = out;
     }
 }
 
-template <bool SCALED>
 static void launch_project_g(const KGeom& g, PadBuf pad, float* y, int batch, hipStream_t s) {
     if (pad.half) {
         const int chunks = (g.ds + kProjBlock - 1) / kProjBlock;
         const int pg = pad_group16(batch);
         dim3 grid(2 * g.v_half * chunks, (batch + pg - 1) / pg), block(kProjBlock);
         if (pg == 4)
-            hipLaunchKernelGGL((k_project16<SCALED, 4>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
+            hipLaunchKernelGGL((k_project16<4>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
         else if (pg == 2)
-            hipLaunchKernelGGL((k_project16<SCALED, 2>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
+            hipLaunchKernelGGL((k_project16<2>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
         else
-            hipLaunchKernelGGL((k_project16<SCALED, 1>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
+            hipLaunchKernelGGL((k_project16<1>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
         return;
     }
     const int chunks = (g.ds + kProjBlock - 1) / kProjBlock;
     const int pg = pad_group(batch);
     dim3 grid(2 * g.v_half * chunks, (batch + pg - 1) / pg), block(kProjBlock);
-    if (pg == 2) hipLaunchKernelGGL((k_project<SCALED, 2>), grid, block, 0, s, g, pad.base, y, chunks, batch);
-    else hipLaunchKernelGGL((k_project<SCALED, 1>), grid, block, 0, s, g, pad.base, y, chunks, batch);
+    if (pg == 2) hipLaunchKernelGGL((k_project<2>), grid, block, 0, s, g, pad.base, y, chunks, batch);
+    else hipLaunchKernelGGL((k_project<1>), grid, block, 0, s, g, pad.base, y, chunks, batch);
 }
 
-hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, bool scaled, hipStream_t s) {
-    if (scaled) launch_project_g<true>(g, pad, y, batch, s);
-    else launch_project_g<false>(g, pad, y, batch, s);
+hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, hipStream_t s) {
+    launch_project_g(g, pad, y, batch, s);
     return hipGetLastError();
 }
 
-// out[b / grp][v][k][b % grp] = y[b][v][k] * step[v][k]^power  (power 1: S y, power 2: S^2 y).
+// out[b / grp][v][k][b % grp] = y[b][v][k] * step[v][k]  (S y).
 __global__ __launch_bounds__(256) void k_scale(KGeom g, const float* __restrict__ y, float* __restrict__ out,
-                                               size_t count, int power, int grp) {
+                                               size_t count, int grp) {
     const size_t per_batch = (size_t)g.n_views * g.ds;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) {
         const size_t b = i / per_batch, vk = i - b * per_batch;
         const float sv = g.step[vk];
         const size_t gi = b / grp;
-        out[(gi * per_batch + vk) * grp + (b - gi * grp)] = power == 2 ? y[i] * sv * sv : y[i] * sv;
+        out[(gi * per_batch + vk) * grp + (b - gi * grp)] = y[i] * sv;
     }
 }
 
-hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, int power, int grp, hipStream_t s) {
+hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, int grp, hipStream_t s) {
     const size_t count = (size_t)batch * g.n_views * g.ds;
     const size_t blocks = (count + 255) / 256 < 8192 ? (count + 255) / 256 : 8192;
-    hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, s, g, y, out, count, power, grp);
+    hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, s, g, y, out, count, grp);
     return hipGetLastError();
 }
 

@@ -62,7 +62,7 @@ air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch,
     if (air_status e = stage_sino(p, Y, batch, B.s1, &src, s)) return e;
     const int grp = image_group(batch);
     if (st.filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, B.s2, rows, p->ds, RAMP_POST, grp, s));
-    else AIR_K(AIR_K_OTHER, launch_scale(kg, src, B.s2, batch, 1, grp, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(kg, src, B.s2, batch, grp, s));
     BpArgs a{};
     a.mode = BP_PLAIN;
     a.out = B.g;
@@ -107,10 +107,10 @@ static air_status fbs_iteration(air_plan p, const SolveBufs& B, int batch, const
     const int grp = image_group(batch);
     const PadBuf pad = plan_pad(p, B.pad, B.pscale);
     if (air_status e = build_pad(p, B.X, pad, B.part, batch, s)) return e;
-    AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, true, s));
+    AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, s));
     if (st.filter)
         AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), B.s1, B.s2, rows, p->ds, RAMP_POST, grp, s));
-    else AIR_K(AIR_K_OTHER, launch_scale(kg, B.s1, B.s2, batch, 1, grp, s));
+    else AIR_K(AIR_K_OTHER, launch_scale(kg, B.s1, B.s2, batch, grp, s));
     BpArgs a{};
     a.mode = BP_STEP;
     a.mu = (float)st.mu;
@@ -149,7 +149,7 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
     auto filtered = [&]() -> air_status {
         if (st.filter)
             AIR_K(AIR_K_RAMP, launch_ramp(p->prec, rt, B.s1, B.s2, rows, p->ds, RAMP_POST, grp, s));
-        else AIR_K(AIR_K_OTHER, launch_scale(kg, B.s1, B.s2, batch, 1, grp, s));
+        else AIR_K(AIR_K_OTHER, launch_scale(kg, B.s1, B.s2, batch, grp, s));
         return AIR_OK;
     };
     if (tf) AIR_K(AIR_K_FRAMELET, launch_tf_rhs(n, B.g, B.e, (float)st.mu, B.r, batch, s));
@@ -157,7 +157,7 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
     // r = rhs - M X, p = r, rho = r.r (the padded copies of X are rebuilt here,
     // so they never outlive a step and follow the current batch's grouping)
     if (air_status e = build_pad(p, B.X, pad, B.part, batch, s)) return e;
-    AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, true, s));
+    AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, s));
     if (air_status e = filtered()) return e;
     {
         BpArgs a{};
@@ -174,7 +174,7 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
             if (air_status e = build_pad(p, B.p, pad, B.part, batch, s)) return e;
     }
     for (int it = 0; it < st.n_cg; it++) {
-        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, true, s));
+        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, s));
         if (air_status e = filtered()) return e;
         BpArgs a{};
         a.mode = BP_MATVEC;
