@@ -122,8 +122,8 @@ struct RampTables {
     float out_scale;           // kappa * 2^-12 for the 16-bit modes
     const float* wsq;          // [ds] D^(1/2) of a cosine-weighted C (applied before and after R), or null
 };
-// scale: 0 = C y;  RAMP_POST = S C y  (S = diag(step); S C S y takes a projection
-// that is already scaled: launch_project(..., scaled = true)).
+// scale: 0 = C y;  RAMP_POST = S C y  (S = diag(step); the projector's output
+// is already S J x, so S C S J x is RAMP_POST applied to it).
 // Input rows [batch * n_views][ds].  Output: the same layout when grp == 0, else
 // group-interleaved with G = grp (the backprojector's input).
 enum { RAMP_POST = 2 };

@@ -402,8 +402,8 @@ hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, i
 // interval (between the projections of the first and last centre, which bound
 // the others) is widened by 0.01 bin.  For each candidate the thread
 // re-evaluates the forward projector's own fixed-point intercept and float32
-// weights, so the result is the exact transpose of k_project (unscaled) up to
-// summation order.  An x-driven ray crosses all PIX pixels at the same
+// weights, so the result is the exact transpose of J (k_project before its
+// step scaling) up to summation order.  An x-driven ray crosses all PIX pixels at the same
 // intercept, so one evaluation gives every weight; a y-driven ray needs one
 // more 64-bit add per pixel.  A larger window only adds candidates of weight
 // exactly zero, so every pixel gets the same bits whatever PIX and BT.
