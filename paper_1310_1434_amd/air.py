@@ -257,7 +257,8 @@ class Plan:
         splitting of Eq. (6) (reg=2, mu = the step).
 
         Returns (X [B, n, n], resid [B, n_outer] float64 or None); asynchronous
-        on the current stream."""
+        on the current stream (a batch of 8 or more runs as two halves on two
+        library streams forked from and joined back to it; same results)."""
         b = y.shape[0]
         x = torch.zeros((b, self.n, self.n), device=self.device) if x0 is None else x0.clone()
         need = self.solve_workspace_bytes(b)
