@@ -402,8 +402,9 @@ extern "C" {
 // A solve of at least kSplitMin images runs as two sub-batches, each on its own
 // stream: one sub-batch's projections (bound by the gather issue rate) then
 // overlap the other's backprojections (bound by VALU and LDS).  Measured at
-// C2: 2 x 8 images 1.10x and 2 x 16 images 1.19x the throughput of one
-// batch; every image gets the same bits either way.  Kernel timing keeps one
+// C2: 16 images as 2 x 8 run at 1.10x the throughput of one 16-image batch,
+// 32 as 2 x 16 at 1.19x two 16-image batches in turn; every image gets the
+// same bits either way.  Kernel timing keeps one
 // stream, so the per-kernel times are those of kernels running alone.
 constexpr int kSplitMin = 8;
 static int solve_parts(const air_plan_s* p, int batch) { return batch >= kSplitMin && !p->timing ? 2 : 1; }
