@@ -114,11 +114,11 @@ struct RampTables {
     const float* taps32;       // [2 ds] kappa r(m) at index m + ds
     const float* step;         // [n_views][ds] path lengths (for the scaled variants)
     int n_views;
-    const uint4* frag_a;       // 16-bit fragments, first split term (f16 hi / bf16 t1)
-    const uint4* frag_b;       // second split term (f16 lo / bf16 t2)
-    const uint4* frag_c;       // third split term (bf16 t3), or null
-    int n_frag;                // fragments per term (indexed by (k0 - n0 - dmin) / 16)
-    int dmin;
+    // 16-bit split terms of T(d) = r(|d|) 2^12 (f16: hi, lo 2^11; bf16: three
+    // terms), as [term][shift s < 4][j < tab_j] entries of 4 values
+    // T(4 j + s + i - kRampZero - ds), i < 4 (zero outside |d| < n_bins)
+    const uint2* tab16;
+    int n_terms, tab_j;
     float out_scale;           // kappa * 2^-12 for the 16-bit modes
     const float* wsq;          // [ds] D^(1/2) of a cosine-weighted C (applied before and after R), or null
 };
@@ -127,6 +127,10 @@ struct RampTables {
 // Input rows [batch * n_views][ds].  Output: the same layout when grp == 0, else
 // group-interleaved with G = grp (the backprojector's input).
 enum { RAMP_POST = 2 };
+// Zero entries below the 16-bit tables' index 0 (columns of a last, partial
+// column tile past ds read them; up to 128 columns per tile).
+constexpr int kRampZero = 128;
+inline int ramp_tab_j(int ds) { return (2 * ds + kRampZero + 3) / 4 + 1; }
 hipError_t launch_ramp(int prec, const RampTables& t, const float* y, float* yf, int rows, int ds, int scale,
                        int grp, hipStream_t s);
 

@@ -18,7 +18,7 @@ air_status fail(air_status st, const std::string& msg) {
 
 namespace {
 
-// float -> IEEE half, round to nearest even (host side, for the filter fragments)
+// float -> IEEE half, round to nearest even (host side, for the 16-bit filter tables)
 uint16_t f32_to_f16(float f) {
     uint32_t x;
     std::memcpy(&x, &f, 4);
@@ -180,31 +180,26 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
         }
         if (prec != AIR_FP32) {
             p->n_terms = prec == AIR_MIXED_F16 ? 2 : 3;
-            p->dmin = -(ds - 16);
-            p->n_frag = (2 * ds - 48) / 16 + 1;
-            for (int t = 0; t < p->n_terms; t++) p->frag[t].assign((size_t)p->n_frag * 64 * 8, 0);
-            for (int f = 0; f < p->n_frag; f++) {
-                const int delta = p->dmin + 16 * f;
-                for (int l = 0; l < 64; l++) {
-                    for (int i = 0; i < 8; i++) {
-                        const int d = std::abs(delta + 8 * (l / 16) + i - (l % 16));
+            const int tj = ramp_tab_j(ds);
+            p->tab16.assign((size_t)p->n_terms * 4 * tj * 4, 0);
+            for (int sh = 0; sh < 4; sh++)
+                for (int j = 0; j < tj; j++)
+                    for (int i = 0; i < 4; i++) {
+                        const int d = std::abs(4 * j + sh + i - kRampZero - ds);
                         const float T = d < g.n_bins ? (float)(r[d] * 4096.0) : 0.f;
-                        const size_t at = ((size_t)f * 64 + l) * 8 + i;
+                        uint16_t term[3];
                         if (prec == AIR_MIXED_F16) {
-                            const uint16_t h = f32_to_f16(T);
-                            p->frag[0][at] = h;
-                            p->frag[1][at] = f32_to_f16((T - f16_to_f32(h)) * 2048.f);
+                            term[0] = f32_to_f16(T);
+                            term[1] = f32_to_f16((T - f16_to_f32(term[0])) * 2048.f);
                         } else {
-                            const uint16_t c1 = f32_to_bf16(T);
-                            const float r1 = T - bf16_to_f32(c1);
-                            const uint16_t c2 = f32_to_bf16(r1);
-                            p->frag[0][at] = c1;
-                            p->frag[1][at] = c2;
-                            p->frag[2][at] = f32_to_bf16(r1 - bf16_to_f32(c2));
+                            term[0] = f32_to_bf16(T);
+                            const float r1 = T - bf16_to_f32(term[0]);
+                            term[1] = f32_to_bf16(r1);
+                            term[2] = f32_to_bf16(r1 - bf16_to_f32(term[1]));
                         }
+                        for (int u = 0; u < p->n_terms; u++)
+                            p->tab16[(((size_t)u * 4 + sh) * tj + j) * 4 + i] = term[u];
                     }
-                }
-            }
         }
         // workspace layout
         Carver c;
@@ -214,7 +209,7 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
         p->off_views = c.take(p->views.size() * sizeof(float));
         p->off_taps = c.take(p->taps32.size() * sizeof(float));
         p->off_vorder = c.take(p->vorder.size() * sizeof(int32_t));
-        for (int t = 0; t < p->n_terms; t++) p->off_frag[t] = c.take(p->frag[t].size() * sizeof(uint16_t));
+        if (!p->tab16.empty()) p->off_tab16 = c.take(p->tab16.size() * sizeof(uint16_t));
         if (p->cos_weight) p->off_wsq = c.take(p->wsq.size() * sizeof(float));
         const size_t mb = (size_t)max_batch;
         p->off_pad = c.take((mb + 7) / 8 * 8 * 2 * g.n * p->line * sizeof(float));   // grouped padded copies
@@ -254,8 +249,8 @@ air_status air_plan_bind_workspace(air_plan p, void* dev, size_t bytes, hipStrea
                            hipMemcpyHostToDevice, s));
     AIR_HIP(hipMemcpyAsync(ws + p->off_vorder, p->vorder.data(), p->vorder.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, s));
-    for (int t = 0; t < p->n_terms; t++)
-        AIR_HIP(hipMemcpyAsync(ws + p->off_frag[t], p->frag[t].data(), p->frag[t].size() * sizeof(uint16_t),
+    if (!p->tab16.empty())
+        AIR_HIP(hipMemcpyAsync(ws + p->off_tab16, p->tab16.data(), p->tab16.size() * sizeof(uint16_t),
                                hipMemcpyHostToDevice, s));
     if (p->cos_weight)
         AIR_HIP(hipMemcpyAsync(ws + p->off_wsq, p->wsq.data(), p->wsq.size() * sizeof(float), hipMemcpyHostToDevice, s));

@@ -133,108 +133,139 @@ __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, f
 }
 
 // ---------------------------------------------------------------------------- 16-bit splits
-// Fragment f of a split term holds, for lane l, the 8 values T16(delta + 8 (l/16) + i - l%16),
-// i = 0..7, with delta = dmin + 16 f (delta = k0 - n0 of the tile).
-template <int PREC, int SCALE>
+// v_mfma_f32_16x16x16 (f16 / bf16): lane l supplies row (or column) l % 16 at
+// k slots 4 (l / 16) + i, i < 4, mapped to the actual k = k0 + 4 (l / 16) + i,
+// so its sinogram operand is one contiguous float4.  Its Toeplitz operand,
+// T(k - n) for those four k, is four consecutive values of a split-term
+// table, read from LDS as one 8-byte entry of the table copy shifted by
+// (first index) mod 4.  For each chunk of KC k the block stages the part of
+// the tables its columns need (all terms, all shifts: a few KB, so any
+// detector size fits); NG 16-column tiles per wavefront let each sinogram load
+// feed 3 NG (f16) or 6 NG (bf16) MFMAs.
+typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+template <int PREC, int SCALE, int NG>
 __global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y, float* __restrict__ yf,
                                                     RampTables t, int rows, int ds, int grp) {
+    constexpr int NT = PREC == AIR_MIXED_F16 ? 2 : 3;
+    constexpr int KC = 512;                         // k per staged chunk
+    constexpr int JW = (KC + 16 * NG) / 4 + 2;      // table entries per shift and chunk
+    static_assert(kRampZero >= 16 * NG, "zero margin covers a partial column tile");
+    __shared__ uint2 tab[NT * 4 * JW];              // [term][shift][entry]
     const int batch = rows / t.n_views, mrows = ramp_tile_rows(batch, t.n_views, grp);
     int rt, ct;
-    if (!ramp_block((mrows + 63) / 64, ds / 32, rt, ct)) return;
+    if (!ramp_block((mrows + 63) / 64, (ds + 16 * NG - 1) / (16 * NG), rt, ct)) return;   // (uniform)
+    const int tj = t.tab_j;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = rt * 64 + w * 16 + (lane & 15);
-    const int slot = lane >> 4;                 // k slots 8 slot .. 8 slot + 7
-    const int n0 = ct * 32;
+    const int slot = lane >> 4;                 // k slots 4 slot .. 4 slot + 3
+    const int n0 = ct * 16 * NG;
+    const int ng = min(NG, (ds - n0) / 16);     // column tiles inside ds (uniform)
+    const int ncol = n0 + (lane & 15);
     const RampRow ar = ramp_row(m, batch, t.n_views, ds, grp);
     const bool mvalid = m < mrows && ar.valid;
     const float* arow = y + (mvalid ? ((size_t)ar.b * t.n_views + ar.v) * ds : 0);
-    f4_t accA0 = {0.f, 0.f, 0.f, 0.f}, accA1 = accA0, accB0 = accA0, accB1 = accA0;
-    for (int k0 = 0; k0 < ds; k0 += 32) {
-        float4 a0 = *reinterpret_cast<const float4*>(arow + k0 + 8 * slot);
-        float4 a1 = *reinterpret_cast<const float4*>(arow + k0 + 8 * slot + 4);
-        if (t.wsq) {    // cosine-weighted C: D^(1/2) before R
-            const float4 w0 = *reinterpret_cast<const float4*>(t.wsq + k0 + 8 * slot);
-            const float4 w1 = *reinterpret_cast<const float4*>(t.wsq + k0 + 8 * slot + 4);
-            a0.x *= w0.x; a0.y *= w0.y; a0.z *= w0.z; a0.w *= w0.w;
-            a1.x *= w1.x; a1.y *= w1.y; a1.z *= w1.z; a1.w *= w1.w;
-        }
-        if (!mvalid) {
-            a0 = make_float4(0.f, 0.f, 0.f, 0.f);
-            a1 = a0;
-        }
-        const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-        const int f0 = (k0 - n0 - t.dmin) >> 4;      // fragment of the first n tile
-        const int f1 = f0 - 1;                        // n0 + 16: delta - 16
-        if (PREC == AIR_MIXED_F16) {
-            h8_t hi, lo;
+    f4_t accA[NG], accB[NG];
 #pragma unroll
-            for (int i = 0; i < 8; i++) {
-                const _Float16 h = (_Float16)av[i];
-                hi[i] = h;
-                lo[i] = (_Float16)((av[i] - (float)h) * 2048.f);
-            }
-            const uint4 bh0 = t.frag_a[(size_t)f0 * 64 + lane], bl0 = t.frag_b[(size_t)f0 * 64 + lane];
-            const uint4 bh1 = t.frag_a[(size_t)f1 * 64 + lane], bl1 = t.frag_b[(size_t)f1 * 64 + lane];
-            const h8_t Bh0 = __builtin_bit_cast(h8_t, bh0), Bl0 = __builtin_bit_cast(h8_t, bl0);
-            const h8_t Bh1 = __builtin_bit_cast(h8_t, bh1), Bl1 = __builtin_bit_cast(h8_t, bl1);
-            accA0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, Bh0, accA0, 0, 0, 0);
-            accA1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, Bh1, accA1, 0, 0, 0);
-            accB0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, Bl0, accB0, 0, 0, 0);
-            accB1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, Bl1, accB1, 0, 0, 0);
-            accB0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo, Bh0, accB0, 0, 0, 0);
-            accB1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo, Bh1, accB1, 0, 0, 0);
-        } else {
-            b8_t s1, s2, s3;
+    for (int c = 0; c < NG; c++) {
+        accA[c] = (f4_t){0.f, 0.f, 0.f, 0.f};
+        accB[c] = accA[c];
+    }
+    float4 an = *reinterpret_cast<const float4*>(arow + 4 * slot);
+    for (int kc = 0; kc < ds; kc += KC) {
+        // entries j_lo .. j_lo + JW - 1 hold every table index x = k - n + ds + kRampZero
+        // (plus 3) of k in [kc, kc + KC) and n in [n0, n0 + 16 NG); past the tables'
+        // end the last entry is repeated (only for k beyond ds, never used)
+        const int j_lo = (kc - n0 - 16 * NG + ds + kRampZero) >> 2;
+        __syncthreads();                        // the previous chunk's reads are done
+        for (int e0 = 0; e0 < NT * 4 * JW; e0 += 4 * 256) {
+            uint2 u[4];
 #pragma unroll
-            for (int i = 0; i < 8; i++) {
-                const __bf16 c1 = (__bf16)av[i];
-                const float r1 = av[i] - (float)c1;
-                const __bf16 c2 = (__bf16)r1;
-                const __bf16 c3 = (__bf16)(r1 - (float)c2);
-                s1[i] = c1; s2[i] = c2; s3[i] = c3;
+            for (int h = 0; h < 4; h++) {
+                const int e = min(e0 + h * 256 + (int)threadIdx.x, NT * 4 * JW - 1);
+                const int us = e / JW, jj = e - us * JW;     // us = term * 4 + shift
+                u[h] = t.tab16[(size_t)us * tj + min(j_lo + jj, tj - 1)];
             }
-            const b8_t B10 = __builtin_bit_cast(b8_t, t.frag_a[(size_t)f0 * 64 + lane]);
-            const b8_t B20 = __builtin_bit_cast(b8_t, t.frag_b[(size_t)f0 * 64 + lane]);
-            const b8_t B30 = __builtin_bit_cast(b8_t, t.frag_c[(size_t)f0 * 64 + lane]);
-            const b8_t B11 = __builtin_bit_cast(b8_t, t.frag_a[(size_t)f1 * 64 + lane]);
-            const b8_t B21 = __builtin_bit_cast(b8_t, t.frag_b[(size_t)f1 * 64 + lane]);
-            const b8_t B31 = __builtin_bit_cast(b8_t, t.frag_c[(size_t)f1 * 64 + lane]);
-            accA0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s1, B10, accA0, 0, 0, 0);
-            accA1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s1, B11, accA1, 0, 0, 0);
-            accB0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s1, B20, accB0, 0, 0, 0);
-            accB1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s1, B21, accB1, 0, 0, 0);
-            accB0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s2, B10, accB0, 0, 0, 0);
-            accB1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s2, B11, accB1, 0, 0, 0);
-            accB0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s1, B30, accB0, 0, 0, 0);
-            accB1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s1, B31, accB1, 0, 0, 0);
-            accB0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s2, B20, accB0, 0, 0, 0);
-            accB1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s2, B21, accB1, 0, 0, 0);
-            accB0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s3, B10, accB0, 0, 0, 0);
-            accB1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s3, B11, accB1, 0, 0, 0);
+#pragma unroll
+            for (int h = 0; h < 4; h++) tab[min(e0 + h * 256 + (int)threadIdx.x, NT * 4 * JW - 1)] = u[h];
+        }
+        __syncthreads();
+        const int kend = min(kc + KC, ds);
+        for (int k0 = kc; k0 < kend; k0 += 16) {
+            float4 a = an;
+            if (k0 + 16 < ds) an = *reinterpret_cast<const float4*>(arow + k0 + 16 + 4 * slot);
+            if (t.wsq) {    // cosine-weighted C: D^(1/2) before R
+                const float4 wv = *reinterpret_cast<const float4*>(t.wsq + k0 + 4 * slot);
+                a.x *= wv.x; a.y *= wv.y; a.z *= wv.z; a.w *= wv.w;
+            }
+            if (!mvalid) a = make_float4(0.f, 0.f, 0.f, 0.f);
+            const float av[4] = {a.x, a.y, a.z, a.w};
+            // staged entry of T(k0 + 4 slot - ncol) for column tile 0; tile c is 16 lower
+            const int x0 = k0 + 4 * slot - ncol + ds + kRampZero - 4 * j_lo;
+            if constexpr (PREC == AIR_MIXED_F16) {
+                h4_t hi, lo;
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const _Float16 h = (_Float16)av[i];
+                    hi[i] = h;
+                    lo[i] = (_Float16)((av[i] - (float)h) * 2048.f);
+                }
+#pragma unroll
+                for (int c = 0; c < NG; c++) {
+                    const int x = x0 - 16 * c, e = (x & 3) * JW + (x >> 2);
+                    const h4_t Bh = __builtin_bit_cast(h4_t, tab[e]);
+                    const h4_t Bl = __builtin_bit_cast(h4_t, tab[4 * JW + e]);
+                    accA[c] = __builtin_amdgcn_mfma_f32_16x16x16f16(hi, Bh, accA[c], 0, 0, 0);
+                    accB[c] = __builtin_amdgcn_mfma_f32_16x16x16f16(hi, Bl, accB[c], 0, 0, 0);
+                    accB[c] = __builtin_amdgcn_mfma_f32_16x16x16f16(lo, Bh, accB[c], 0, 0, 0);
+                }
+            } else {
+                s4_t s1, s2, s3;
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const __bf16 c1 = (__bf16)av[i];
+                    const float r1 = av[i] - (float)c1;
+                    const __bf16 c2 = (__bf16)r1;
+                    const __bf16 c3 = (__bf16)(r1 - (float)c2);
+                    s1[i] = __builtin_bit_cast(short, c1);
+                    s2[i] = __builtin_bit_cast(short, c2);
+                    s3[i] = __builtin_bit_cast(short, c3);
+                }
+#pragma unroll
+                for (int c = 0; c < NG; c++) {
+                    const int x = x0 - 16 * c, e = (x & 3) * JW + (x >> 2);
+                    const s4_t B1 = __builtin_bit_cast(s4_t, tab[e]);
+                    const s4_t B2 = __builtin_bit_cast(s4_t, tab[4 * JW + e]);
+                    const s4_t B3 = __builtin_bit_cast(s4_t, tab[8 * JW + e]);
+                    accA[c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(s1, B1, accA[c], 0, 0, 0);
+                    accB[c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(s1, B2, accB[c], 0, 0, 0);
+                    accB[c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(s2, B1, accB[c], 0, 0, 0);
+                    accB[c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(s1, B3, accB[c], 0, 0, 0);
+                    accB[c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(s2, B2, accB[c], 0, 0, 0);
+                    accB[c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(s3, B1, accB[c], 0, 0, 0);
+                }
+            }
         }
     }
     const float cross = (PREC == AIR_MIXED_F16) ? (1.f / 2048.f) : 1.f;
     const int rbase = rt * 64 + w * 16 + 4 * (lane >> 4);
-    const int ncol = n0 + (lane & 15);
     const int cs = grp ? grp : 1;
 #pragma unroll
     for (int r = 0; r < 4; r++) {
         const int row = rbase + r;
         const RampRow orow = ramp_row(row, batch, t.n_views, ds, grp);
         if (row < mrows && orow.valid) {
-            float o0 = t.out_scale * fmaf(accB0[r], cross, accA0[r]);
-            float o1 = t.out_scale * fmaf(accB1[r], cross, accA1[r]);
-            if (t.wsq) {    // and D^(1/2) after
-                o0 *= t.wsq[ncol];
-                o1 *= t.wsq[ncol + 16];
+            const float* so = t.step + (size_t)orow.v * ds;
+#pragma unroll
+            for (int c = 0; c < NG; c++) {
+                if (c >= ng) break;
+                const int col = ncol + 16 * c;
+                float o = t.out_scale * fmaf(accB[c][r], cross, accA[c][r]);
+                if (t.wsq) o *= t.wsq[col];     // and D^(1/2) after
+                if (SCALE & RAMP_POST) o *= so[col];
+                yf[orow.out + (size_t)col * cs] = o;
             }
-            if (SCALE & RAMP_POST) {
-                const float* so = t.step + (size_t)orow.v * ds;
-                o0 *= so[ncol];
-                o1 *= so[ncol + 16];
-            }
-            yf[orow.out + (size_t)ncol * cs] = o0;
-            yf[orow.out + (size_t)(ncol + 16) * cs] = o1;
         }
     }
 }
@@ -248,10 +279,21 @@ static hipError_t launch_ramp_scaled(int prec, const RampTables& t, const float*
     if (prec == AIR_FP32) {
         hipLaunchKernelGGL(k_ramp_f32<SCALE>, grid, block, 2 * ds * sizeof(float), s, y, yf, t.taps32, t.step,
                            t.wsq, t.n_views, rows, ds, grp);
-    } else if (prec == AIR_MIXED_F16) {
-        hipLaunchKernelGGL((k_ramp_split<AIR_MIXED_F16, SCALE>), grid, block, 0, s, y, yf, t, rows, ds, grp);
-    } else if (prec == AIR_MIXED_BF16) {
-        hipLaunchKernelGGL((k_ramp_split<AIR_MIXED_BF16, SCALE>), grid, block, 0, s, y, yf, t, rows, ds, grp);
+    } else if (prec == AIR_MIXED_F16 || prec == AIR_MIXED_BF16) {
+        // widest column tiles (up to 128 columns) that still give at least three blocks per CU
+        const int rt8 = 8 * ((row_tiles + 7) / 8);
+        const size_t lds = 0;
+        const int ng = rt8 * ((ds + 127) / 128) >= 768 ? 8 : rt8 * ((ds + 63) / 64) >= 768 ? 4 : 2;
+        const dim3 g2(rt8 * ((ds + 16 * ng - 1) / (16 * ng)));
+        if (prec == AIR_MIXED_F16) {
+            if (ng == 8) hipLaunchKernelGGL((k_ramp_split<AIR_MIXED_F16, SCALE, 8>), g2, block, lds, s, y, yf, t, rows, ds, grp);
+            else if (ng == 4) hipLaunchKernelGGL((k_ramp_split<AIR_MIXED_F16, SCALE, 4>), g2, block, lds, s, y, yf, t, rows, ds, grp);
+            else hipLaunchKernelGGL((k_ramp_split<AIR_MIXED_F16, SCALE, 2>), g2, block, lds, s, y, yf, t, rows, ds, grp);
+        } else {
+            if (ng == 8) hipLaunchKernelGGL((k_ramp_split<AIR_MIXED_BF16, SCALE, 8>), g2, block, lds, s, y, yf, t, rows, ds, grp);
+            else if (ng == 4) hipLaunchKernelGGL((k_ramp_split<AIR_MIXED_BF16, SCALE, 4>), g2, block, lds, s, y, yf, t, rows, ds, grp);
+            else hipLaunchKernelGGL((k_ramp_split<AIR_MIXED_BF16, SCALE, 2>), g2, block, lds, s, y, yf, t, rows, ds, grp);
+        }
     } else {
         return hipErrorInvalidValue;
     }

@@ -52,10 +52,10 @@ struct air_plan_s {
     int ramp_window = 0;           // 0 Ram-Lak, 1 Shepp-Logan, 2 Hann
     bool cos_weight = false;       // symmetric fan-beam cosine weighting of C
     std::vector<float> wsq;        // [ds] sqrt of the cosine weights (0 in the padding), if cos_weight
-    std::vector<uint16_t> frag[3];
-    int n_terms = 0, n_frag = 0, dmin = 0;
+    std::vector<uint16_t> tab16;   // 16-bit split tap tables (RampTables::tab16)
+    int n_terms = 0;
     // workspace layout (bytes)
-    size_t off_rays = 0, off_step = 0, off_views = 0, off_taps = 0, off_frag[3] = {0, 0, 0}, off_wsq = 0,
+    size_t off_rays = 0, off_step = 0, off_views = 0, off_taps = 0, off_tab16 = 0, off_wsq = 0,
            off_vorder = 0;
     size_t off_pad = 0, off_s1 = 0, off_s2 = 0, off_pscale = 0, off_ppart = 0, total = 0;
     char* ws = nullptr;
@@ -121,11 +121,9 @@ struct air_plan_s {
         t.taps32 = reinterpret_cast<const float*>(ws + off_taps);
         t.step = reinterpret_cast<const float*>(ws + off_step);
         t.n_views = g.n_views;
-        t.frag_a = n_terms > 0 ? reinterpret_cast<const uint4*>(ws + off_frag[0]) : nullptr;
-        t.frag_b = n_terms > 1 ? reinterpret_cast<const uint4*>(ws + off_frag[1]) : nullptr;
-        t.frag_c = n_terms > 2 ? reinterpret_cast<const uint4*>(ws + off_frag[2]) : nullptr;
-        t.n_frag = n_frag;
-        t.dmin = dmin;
+        t.tab16 = n_terms > 0 ? reinterpret_cast<const uint2*>(ws + off_tab16) : nullptr;
+        t.n_terms = n_terms;
+        t.tab_j = ramp_tab_j(ds);
         t.out_scale = (float)(kappa / 4096.0);
         t.wsq = cos_weight ? reinterpret_cast<const float*>(ws + off_wsq) : nullptr;
         return t;
