@@ -101,6 +101,26 @@ def test_ramp_parity(air, torch_mod, orc, record, name, prec):
     assert rel(yf, ref) < 1e-5, (name, prec, rel(yf, ref))
 
 
+@pytest.mark.parametrize("prec", ["mixed_f16", "mixed_bf16"])
+def test_split_ramp_column_tiles(air, torch_mod, orc, record, prec):
+    """The 16-bit ramp kernels cover 32, 64 or 128 columns per block depending
+    on the launch size (C2: batch 1, 8 and 16).  A column's sums do not depend
+    on the tile width, so every image's output is the same bits in each, and
+    it matches the oracle."""
+    g = geom("c2")
+    ys = np.stack([sino_for("c2", s % 3) * (1 + 0.1 * s) for s in range(16)]).astype(np.float32)
+    plan = air.Plan(g, max_batch=16, precision=prec)
+    y16 = host(plan.ramp(dev(torch_mod, ys)))
+    y8 = host(plan.ramp(dev(torch_mod, ys[:8])))
+    y1 = host(plan.ramp(dev(torch_mod, ys[5:6])))[0]
+    assert np.array_equal(y16[:8], y8)
+    assert np.array_equal(y16[5], y1)
+    for b in (0, 15):
+        e = rel(y16[b], orc.ramp(orc.Geom(g), ys[b].astype(np.float64)))
+        record(f"rel_l2_C_{prec}_b16", e)
+        assert e < 1e-5, (b, e)
+
+
 @pytest.mark.parametrize("filt", [0, 1])
 @pytest.mark.parametrize("name", ["c1", "ragged", "fine", "c2"])
 def test_filtered_backproject_parity(air, torch_mod, orc, record, name, filt):
