@@ -484,10 +484,14 @@ __device__ __forceinline__ void bp_candidates(const RayEntry* rays, const float*
 // The same with the axis choice (uniform over the block) inside the candidate
 // loop: one loop, so the accumulators keep one set of registers across views
 // (the per-axis loops make the compiler move them between register sets at
-// every view), and the next pair is read at the end of an iteration.  Faster
-// with 16-image groups; the per-axis loops are faster with fewer images.  Both
+// every view), and the next pair is read at the end of an iteration.  Used
+// from 8-image groups: with 8 images it needs 126 VGPRs against 167, which
+// leaves room on each CU for the kernels of the other sub-batch stream of a
+// split solve (8-image halves of a 16-image batch), though on its own the
+// 8-image kernel is about 5% slower than the per-axis loops; with 16 images it
+// is faster alone too, with 4 or fewer the per-axis loops win either way.  Both
 // perform the same operations in the same order.
-constexpr int kBpInLoopMin = 16;
+constexpr int kBpInLoopMin = 8;
 template <int PIX>
 __device__ __forceinline__ void joseph_pair(int axes, const RayEntry& e0, const RayEntry& e1, int i, int j, int c0,
                                             float (&wt0)[PIX], float (&wt1)[PIX]) {
