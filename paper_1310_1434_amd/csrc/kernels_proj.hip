@@ -189,6 +189,9 @@ __device__ __forceinline__ int64_t fx_at(const RayEntry& e, int a_minus_c0) {
     return e.tc + prod * 2;
 }
 
+// the same as one 32x32->64 multiply-add: a2 = 2 (a - c0)
+__device__ __forceinline__ int64_t fx_at2(const RayEntry& e, int a2) { return e.tc + (int64_t)a2 * (int64_t)e.m; }
+
 // Index of the first of the two samples in a padded line of n + 4: clamping
 // into [0, n + 2] only ever moves samples onto the zero padding, so an
 // out-of-range step contributes exactly zero (no range test needed).
@@ -408,12 +411,11 @@ hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, i
 // more 64-bit add per pixel.  A larger window only adds candidates of weight
 // exactly zero, so every pixel gets the same bits whatever PIX and BT.
 //
-// Views are processed kBpViews at a time.  Per view, the tile's bins (the
-// union of its pixels' intervals, at most 64 PIX / 2 per pass) and their
-// sinogram values are staged in shared memory by one wavefront, so all
-// candidates are read from LDS.  The terms of a pass are summed in float32,
-// across passes in float64.  No atomics.
-constexpr int kBpViews = 4;    // views per pass = wavefronts per block
+// Views are processed eight at a time, two per wavefront.  Per view, the
+// tile's bins (the union of its pixels' intervals, at most 32 PIX per pass),
+// their sinogram values, the tile window and the view's direction are staged
+// in shared memory by one wavefront, so the per-view work reads only LDS.  The
+// terms of a pass are summed in float32, across passes in float64.  No atomics.
 
 // Joseph weight of the sample at fixed-point intercept t for interpolated index ob.
 __device__ __forceinline__ float joseph_weight_at(int64_t t, int ob) {
@@ -424,35 +426,38 @@ __device__ __forceinline__ float joseph_weight_at(int64_t t, int ob) {
     return (ob == j0) ? (1.f - f) : ((ob == j0 + 1) ? f : 0.f);
 }
 
-// Weights of ray e for the pixels (i, j + q), q < PIX.  AX: 0 = the ray is
-// x-driven, 1 = y-driven, 2 = either (read from the table).  With d = j0 - ob
-// (j0 the first sample's index, ob the pixel's interpolated index) a pixel
-// takes 1 - f at d == 0 and f at d == -1.
+// Weights of ray e for the pixels (i, j + q), q < PIX, or all zero if !use.
+// AX: 0 = the ray is x-driven, 1 = y-driven, 2 = either (read from the
+// table).  With d = j0 - ob (j0 the first sample's index, ob the pixel's
+// interpolated index) a pixel takes 1 - f at d == 0 and f at d == -1.
 template <int AX, int PIX>
-__device__ __forceinline__ void joseph_column(const RayEntry& e, int i, int j, int c0, float (&w)[PIX]) {
+__device__ __forceinline__ void joseph_column(const RayEntry& e, bool use, int i, int j, int c0, float (&w)[PIX]) {
     if constexpr (AX == 0) {
         // all pixels sit on the column the ray samples at i: one intercept
-        const int64_t t = fx_at(e, i - c0);
-        const float f = fx_frac(t);
+        const int64_t t = fx_at2(e, 2 * (i - c0));
+        const float f = fx_frac(t), g = 1.f - f;
         const int d = fx_index(t) - kPad - j;
+        bool at[PIX + 1];     // at[k]: the first sample is on row j + k - 1
 #pragma unroll
-        for (int q = 0; q < PIX; q++) w[q] = d == q ? 1.f - f : (d == q - 1 ? f : 0.f);
+        for (int k = 0; k <= PIX; k++) at[k] = use && d == k - 1;
+#pragma unroll
+        for (int q = 0; q < PIX; q++) w[q] = at[q + 1] ? g : (at[q] ? f : 0.f);
     } else if constexpr (AX == 1) {
         // driving rows j + q, interpolated index i for all
-        int64_t t = fx_at(e, j - c0);
+        int64_t t = fx_at2(e, 2 * (j - c0));
         const int64_t m2 = (int64_t)e.m * 2;
 #pragma unroll
         for (int q = 0; q < PIX; q++, t += m2) {
             const float f = fx_frac(t);
             const int d = fx_index(t) - kPad - i;
-            w[q] = d == 0 ? 1.f - f : (d == -1 ? f : 0.f);
+            w[q] = (use && d == 0) ? 1.f - f : ((use && d == -1) ? f : 0.f);
         }
     } else {
         const int ax = ray_axis(e.meta);
-        int64_t t = fx_at(e, (ax ? j : i) - c0);
+        int64_t t = fx_at2(e, 2 * ((ax ? j : i) - c0));
         const int64_t m2 = ax ? (int64_t)e.m * 2 : 0;   // y-driven: next driving row
 #pragma unroll
-        for (int q = 0; q < PIX; q++, t += m2) w[q] = joseph_weight_at(t, ax ? i : j + q);
+        for (int q = 0; q < PIX; q++, t += m2) w[q] = use ? joseph_weight_at(t, ax ? i : j + q) : 0.f;
     }
 }
 
@@ -469,15 +474,12 @@ __device__ __forceinline__ void bp_candidates(const RayEntry* rays, const float*
         load_group<BT>(vals + w * SV, y0);
         load_group<BT>(vals + w1 * SV, y1);
         float wt0[PIX], wt1[PIX];
-        joseph_column<AX, PIX>(e0, i, j, c0, wt0);
-        joseph_column<AX, PIX>(e1, i, j, c0, wt1);
-        const float keep = two ? 1.f : 0.f;
+        joseph_column<AX, PIX>(e0, true, i, j, c0, wt0);
+        joseph_column<AX, PIX>(e1, two, i, j, c0, wt1);
 #pragma unroll
-        for (int r = 0; r < PIX; r++) {
-            const float w1r = wt1[r] * keep;
+        for (int r = 0; r < PIX; r++)
 #pragma unroll
-            for (int q = 0; q < BT; q++) acc[r][q] = fmaf(w1r, y1[q], fmaf(wt0[r], y0[q], acc[r][q]));
-        }
+            for (int q = 0; q < BT; q++) acc[r][q] = fmaf(wt1[r], y1[q], fmaf(wt0[r], y0[q], acc[r][q]));
     }
 }
 
@@ -493,17 +495,17 @@ __device__ __forceinline__ void bp_candidates(const RayEntry* rays, const float*
 // perform the same operations in the same order.
 constexpr int kBpInLoopMin = 8;
 template <int PIX>
-__device__ __forceinline__ void joseph_pair(int axes, const RayEntry& e0, const RayEntry& e1, int i, int j, int c0,
-                                            float (&wt0)[PIX], float (&wt1)[PIX]) {
+__device__ __forceinline__ void joseph_pair(int axes, const RayEntry& e0, const RayEntry& e1, bool two, int i, int j,
+                                            int c0, float (&wt0)[PIX], float (&wt1)[PIX]) {
     if (axes == 0) {
-        joseph_column<0, PIX>(e0, i, j, c0, wt0);
-        joseph_column<0, PIX>(e1, i, j, c0, wt1);
+        joseph_column<0, PIX>(e0, true, i, j, c0, wt0);
+        joseph_column<0, PIX>(e1, two, i, j, c0, wt1);
     } else if (axes == 1) {
-        joseph_column<1, PIX>(e0, i, j, c0, wt0);
-        joseph_column<1, PIX>(e1, i, j, c0, wt1);
+        joseph_column<1, PIX>(e0, true, i, j, c0, wt0);
+        joseph_column<1, PIX>(e1, two, i, j, c0, wt1);
     } else {
-        joseph_column<2, PIX>(e0, i, j, c0, wt0);
-        joseph_column<2, PIX>(e1, i, j, c0, wt1);
+        joseph_column<2, PIX>(e0, true, i, j, c0, wt0);
+        joseph_column<2, PIX>(e1, two, i, j, c0, wt1);
     }
 }
 template <int BT, int PIX, int SV>
@@ -516,14 +518,11 @@ __device__ __forceinline__ void bp_candidates_any(int axes, const RayEntry* rays
     load_group<BT>(vals + min(wlo + 1, whi) * SV, y1);
     for (int w = wlo; w <= whi; w += 2) {
         float wt0[PIX], wt1[PIX];
-        joseph_pair<PIX>(axes, e0, e1, i, j, c0, wt0, wt1);
-        const float keep = w + 1 <= whi ? 1.f : 0.f;
+        joseph_pair<PIX>(axes, e0, e1, w + 1 <= whi, i, j, c0, wt0, wt1);
 #pragma unroll
-        for (int r = 0; r < PIX; r++) {
-            const float w1r = wt1[r] * keep;
+        for (int r = 0; r < PIX; r++)
 #pragma unroll
-            for (int q = 0; q < BT; q++) acc[r][q] = fmaf(w1r, y1[q], fmaf(wt0[r], y0[q], acc[r][q]));
-        }
+            for (int q = 0; q < BT; q++) acc[r][q] = fmaf(wt1[r], y1[q], fmaf(wt0[r], y0[q], acc[r][q]));
         if (w + 2 <= whi) {
             const int m1 = min(w + 3, whi);
             e0 = rays[w + 2];
@@ -559,7 +558,8 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     constexpr int SV = BT >= 8 ? BT + 4 : BT;
     __shared__ __align__(16) float s_val[NV][BINS * SV];
     __shared__ int s_axes[NV];           // staged rays all x-driven (0), all y-driven (1), or both (2)
-    __shared__ int s_win[NV][3];         // tile window: first bin, bin count, half-width (float bits)
+    __shared__ __align__(16) int s_win[NV][4];   // tile window: first bin, bin count, half-width (float bits)
+    __shared__ __align__(8) float2 s_cs[NV];      // the views' (cos, sin)
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i0 = blockIdx.x * 16, j0 = blockIdx.y * TH;
@@ -586,10 +586,11 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
         int my_kb0[VW], my_nb[VW];
         {
             float kc_lo = 3e38f, kc_hi = -3e38f, hw = 0.f;
+            float2 cs = make_float2(1.f, 0.f);
             const int h = lane >> 2, c = lane & 3;
             const int v = v0 + wave + 4 * h;
             if (h < VW && v < g.n_views) {
-                const float2 cs = g.views[v];
+                cs = g.views[v];
                 const float qx = cx[c & 1], qy = cy[c >> 1];
                 const float kc = bin_of(g, qx, qy, cs.x, cs.y);
                 const float m = fmaxf(fabsf(cs.x), fabsf(cs.y));
@@ -621,6 +622,8 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                 const float klo_f = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc_lo), 4 * hh));
                 const float khi_f = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc_hi), 4 * hh));
                 const float hws = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hw), 4 * hh));
+                const float csx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cs.x), 4 * hh));
+                const float csy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cs.y), 4 * hh));
                 my_kb0[hh] = 0;
                 my_nb[hh] = 0;
                 if (v0 + wave + 4 * hh < g.n_views) {
@@ -632,6 +635,7 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                     s_win[wave + 4 * hh][0] = my_kb0[hh];
                     s_win[wave + 4 * hh][1] = my_nb[hh];
                     s_win[wave + 4 * hh][2] = __float_as_int(hws);
+                    s_cs[wave + 4 * hh] = make_float2(csx, csy);
                 }
             }
         }
@@ -677,7 +681,8 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                 if (p == 0) passes = max(passes, (nbs + BINS - 1) / BINS);
                 if (v0 + s >= g.n_views) continue;
                 const float hws = __int_as_float(__builtin_amdgcn_readfirstlane(s_win[s][2]));
-                const float2 cs = g.views[v0 + s];
+                const float2 cs = make_float2(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_cs[s].x))),
+                                              __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_cs[s].y))));
                 const float ka = bin_of(g, px, py, cs.x, cs.y);
                 const float kb = bin_of(g, px, py + (PIX - 1) * g.pixel, cs.x, cs.y);
                 const int klo = max(kb0, (int)ceilf(fminf(ka, kb) - hws - 0.01f));
