@@ -417,19 +417,12 @@ hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, i
 // in shared memory by one wavefront, so the per-view work reads only LDS.  The
 // terms of a pass are summed in float32, across passes in float64.  No atomics.
 
-// Joseph weight of the sample at fixed-point intercept t for interpolated index ob.
-__device__ __forceinline__ float joseph_weight_at(int64_t t, int ob) {
-    const float f = fx_frac(t);
-    const int j0 = fx_index(t) - kPad;
-    // ob in {j0, j0 + 1} implies -1 <= t < n: exactly the samples the forward
-    // projector takes with non-zero weight, so no range test is needed
-    return (ob == j0) ? (1.f - f) : ((ob == j0 + 1) ? f : 0.f);
-}
-
 // Weights of ray e for the pixels (i, j + q), q < PIX, or all zero if !use.
 // AX: 0 = the ray is x-driven, 1 = y-driven, 2 = either (read from the
 // table).  With d = j0 - ob (j0 the first sample's index, ob the pixel's
-// interpolated index) a pixel takes 1 - f at d == 0 and f at d == -1.
+// interpolated index) a pixel takes 1 - f at d == 0 and f at d == -1.  Only
+// a sample with -1 <= j0 < n can match an in-image pixel: exactly the samples
+// the forward projector weights, so no range test is needed.
 template <int AX, int PIX>
 __device__ __forceinline__ void joseph_column(const RayEntry& e, bool use, int i, int j, int c0, float (&w)[PIX]) {
     if constexpr (AX == 0) {
@@ -442,22 +435,19 @@ __device__ __forceinline__ void joseph_column(const RayEntry& e, bool use, int i
         for (int k = 0; k <= PIX; k++) at[k] = use && d == k - 1;
 #pragma unroll
         for (int q = 0; q < PIX; q++) w[q] = at[q + 1] ? g : (at[q] ? f : 0.f);
-    } else if constexpr (AX == 1) {
-        // driving rows j + q, interpolated index i for all
-        int64_t t = fx_at2(e, 2 * (j - c0));
-        const int64_t m2 = (int64_t)e.m * 2;
-#pragma unroll
-        for (int q = 0; q < PIX; q++, t += m2) {
-            const float f = fx_frac(t);
-            const int d = fx_index(t) - kPad - i;
-            w[q] = (use && d == 0) ? 1.f - f : ((use && d == -1) ? f : 0.f);
-        }
     } else {
-        const int ax = ray_axis(e.meta);
-        int64_t t = fx_at2(e, 2 * ((ax ? j : i) - c0));
-        const int64_t m2 = ax ? (int64_t)e.m * 2 : 0;   // y-driven: next driving row
+        // y-driven (AX == 1, or AX == 2 and the table says so): driving row
+        // j + q, interpolated index i; x-driven: driving column i, index j + q
+        const bool ydrv = AX == 1 || ray_axis(e.meta);
 #pragma unroll
-        for (int q = 0; q < PIX; q++, t += m2) w[q] = use ? joseph_weight_at(t, ax ? i : j + q) : 0.f;
+        for (int q = 0; q < PIX; q++) {
+            const int64_t t = fx_at2(e, 2 * ((ydrv ? j + q : i) - c0));
+            const float f = fx_frac(t);
+            float g = 1.f - f;
+            asm volatile("" : "+v"(g));    // keep the selection branch-free (1 - f is not sunk into a branch)
+            const int d = fx_index(t) - kPad - (ydrv ? i : j + q);
+            w[q] = (use && d == 0) ? g : ((use && d == -1) ? f : 0.f);
+        }
     }
 }
 
