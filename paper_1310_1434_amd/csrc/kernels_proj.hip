@@ -523,9 +523,11 @@ __device__ __forceinline__ void bp_candidates_any(int axes, const RayEntry* rays
     }
 }
 
-// Continuous detector bin of the projection of point (px, py) in view (c, s).
+// Continuous detector bin of the projection of point (px, py) in view (c, s);
+// BEAM: 0 parallel, 1 fan (g.beam, fixed per launch).
+template <int BEAM>
 __device__ __forceinline__ float bin_of(const KGeom& g, float px, float py, float c, float s) {
-    if (g.beam == 0) return fmaf(fmaf(px, c, py * s), g.inv_bin, g.half_d);
+    if constexpr (BEAM == 0) return fmaf(fmaf(px, c, py * s), g.inv_bin, g.half_d);
     const float ap = fmaf(py, c, -px * s);
     const float bp = g.sod - fmaf(px, c, py * s);
     return fmaf(g.sdd * ap * __builtin_amdgcn_rcpf(bp), g.inv_bin, g.half_d);
@@ -535,7 +537,9 @@ __device__ __forceinline__ float bin_of(const KGeom& g, float px, float py, floa
 static int bp_pix(int) { return 2; }
 int bp_blocks(int n, int batch) { return ((n + 15) / 16) * ((n + 16 * bp_pix(batch) - 1) / (16 * bp_pix(batch))); }
 
-template <int MODE, bool REDUCE, int BT, int PIX>
+// The beam type is a template parameter: as a run-time test it cost three
+// uniform branches per view (about 5% of the launch).
+template <int MODE, bool REDUCE, int BT, int PIX, int BEAM>
 __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __restrict__ y, BpArgs a, int batch) {
     constexpr int NV = 8;                  // views per pass, two per wavefront (the same for every group size)
     constexpr int VW = NV / 4;             // views staged per wavefront
@@ -547,9 +551,10 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     // reads of 8 consecutive slots fall in distinct LDS banks
     constexpr int SV = BT >= 8 ? BT + 4 : BT;
     __shared__ __align__(16) float s_val[NV][BINS * SV];
-    __shared__ int s_axes[NV];           // staged rays all x-driven (0), all y-driven (1), or both (2)
-    __shared__ __align__(16) int s_win[NV][4];   // tile window: first bin, bin count, half-width (float bits)
-    __shared__ __align__(8) float2 s_cs[NV];      // the views' (cos, sin)
+    // per view: tile window (first bin, bin count, half-width as float bits),
+    // whether the staged rays are all x-driven (0), all y-driven (1) or both
+    // (2), and (cos, sin) as float bits; read together, with one wait
+    __shared__ __align__(16) int s_view[NV][8];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i0 = blockIdx.x * 16, j0 = blockIdx.y * TH;
@@ -582,10 +587,10 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
             if (h < VW && v < g.n_views) {
                 cs = g.views[v];
                 const float qx = cx[c & 1], qy = cy[c >> 1];
-                const float kc = bin_of(g, qx, qy, cs.x, cs.y);
+                const float kc = bin_of<BEAM>(g, qx, qy, cs.x, cs.y);
                 const float m = fmaxf(fabsf(cs.x), fabsf(cs.y));
                 float bp_min = 1.f, ap_max = 0.f;
-                if (g.beam != 0) {
+                if constexpr (BEAM != 0) {
                     ap_max = fabsf(fmaf(qy, cs.x, -qx * cs.y));
                     bp_min = g.sod - fmaf(qx, cs.x, qy * cs.y);
                 }
@@ -603,9 +608,10 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                 // so |du| <= sdd pixel m (bp + |ap|) / (bp (bp - pixel m)), which
                 // grows with |ap| and falls with bp over the tile
                 const float dm = g.pixel * m;
-                hw = g.beam == 0 ? dm * g.inv_bin
-                                 : g.sdd * dm * (bp_min + ap_max) *
-                                       __builtin_amdgcn_rcpf(bp_min * (bp_min - dm)) * g.inv_bin;
+                if constexpr (BEAM == 0)
+                    hw = dm * g.inv_bin;
+                else
+                    hw = g.sdd * dm * (bp_min + ap_max) * __builtin_amdgcn_rcpf(bp_min * (bp_min - dm)) * g.inv_bin;
             }
 #pragma unroll
             for (int hh = 0; hh < VW; hh++) {
@@ -622,10 +628,10 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                     my_nb[hh] = max(0, kb1 - my_kb0[hh] + 1);
                 }
                 if (lane == 0) {
-                    s_win[wave + 4 * hh][0] = my_kb0[hh];
-                    s_win[wave + 4 * hh][1] = my_nb[hh];
-                    s_win[wave + 4 * hh][2] = __float_as_int(hws);
-                    s_cs[wave + 4 * hh] = make_float2(csx, csy);
+                    *reinterpret_cast<int4*>(&s_view[wave + 4 * hh][0]) =
+                        make_int4(my_kb0[hh], my_nb[hh], __float_as_int(hws), 0);
+                    *reinterpret_cast<int2*>(&s_view[wave + 4 * hh][4]) =
+                        make_int2(__float_as_int(csx), __float_as_int(csy));
                 }
             }
         }
@@ -659,27 +665,29 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                     any_x = any_x || __ballot(act && ax == 0) != 0;
                     any_y = any_y || __ballot(act && ax == 1) != 0;
                 }
-                if (lane == 0) s_axes[sv] = any_y ? (any_x ? 2 : 1) : 0;
+                if (lane == 0) s_view[sv][3] = any_y ? (any_x ? 2 : 1) : 0;
             }
             __syncthreads();
 #pragma unroll
             for (int s = 0; s < NV; s++) {
                 // the view's window (uniform over the block), and this column's
                 // bin interval from its first and last centre
-                const int kb0 = __builtin_amdgcn_readfirstlane(s_win[s][0]);
-                const int nbs = __builtin_amdgcn_readfirstlane(s_win[s][1]);
+                const int4 vw = *reinterpret_cast<const int4*>(&s_view[s][0]);
+                const int2 vc = *reinterpret_cast<const int2*>(&s_view[s][4]);
+                const int kb0 = __builtin_amdgcn_readfirstlane(vw.x);
+                const int nbs = __builtin_amdgcn_readfirstlane(vw.y);
                 if (p == 0) passes = max(passes, (nbs + BINS - 1) / BINS);
                 if (v0 + s >= g.n_views) continue;
-                const float hws = __int_as_float(__builtin_amdgcn_readfirstlane(s_win[s][2]));
-                const float2 cs = make_float2(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_cs[s].x))),
-                                              __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_cs[s].y))));
-                const float ka = bin_of(g, px, py, cs.x, cs.y);
-                const float kb = bin_of(g, px, py + (PIX - 1) * g.pixel, cs.x, cs.y);
+                const float hws = __int_as_float(__builtin_amdgcn_readfirstlane(vw.z));
+                const float2 cs = make_float2(__int_as_float(__builtin_amdgcn_readfirstlane(vc.x)),
+                                              __int_as_float(__builtin_amdgcn_readfirstlane(vc.y)));
+                const float ka = bin_of<BEAM>(g, px, py, cs.x, cs.y);
+                const float kb = bin_of<BEAM>(g, px, py + (PIX - 1) * g.pixel, cs.x, cs.y);
                 const int klo = max(kb0, (int)ceilf(fminf(ka, kb) - hws - 0.01f));
                 const int khi = min(kb0 + nbs - 1, (int)floorf(fmaxf(ka, kb) + hws + 0.01f));
                 const int base = kb0 + p * BINS;
                 const int wlo = max(klo - base, 0), whi = min(khi - base, BINS - 1);
-                const int axes = __builtin_amdgcn_readfirstlane(s_axes[s]);   // uniform over the block
+                const int axes = __builtin_amdgcn_readfirstlane(vw.w);   // uniform over the block
                 if constexpr (BT >= kBpInLoopMin)
                     bp_candidates_any<BT, PIX, SV>(axes, s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
                 else if (axes == 0)
@@ -735,15 +743,21 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     }
 }
 
-template <int MODE, bool REDUCE>
-static void launch_bp_mode(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s) {
+template <int MODE, bool REDUCE, int BEAM>
+static void launch_bp_beam(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s) {
     const int bt = image_group(batch), pix = bp_pix(batch);
     dim3 grid((g.n + 15) / 16, (g.n + 16 * pix - 1) / (16 * pix), (batch + bt - 1) / bt), block(256);
-    if (bt == 16) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 16, 2>), grid, block, 0, s, g, y, a, batch);
-    else if (bt == 8) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 8, 2>), grid, block, 0, s, g, y, a, batch);
-    else if (bt == 4) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 4, 2>), grid, block, 0, s, g, y, a, batch);
-    else if (bt == 2) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 2, 2>), grid, block, 0, s, g, y, a, batch);
-    else hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 1, 2>), grid, block, 0, s, g, y, a, batch);
+    if (bt == 16) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 16, 2, BEAM>), grid, block, 0, s, g, y, a, batch);
+    else if (bt == 8) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 8, 2, BEAM>), grid, block, 0, s, g, y, a, batch);
+    else if (bt == 4) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 4, 2, BEAM>), grid, block, 0, s, g, y, a, batch);
+    else if (bt == 2) hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 2, 2, BEAM>), grid, block, 0, s, g, y, a, batch);
+    else hipLaunchKernelGGL((k_backproject<MODE, REDUCE, 1, 2, BEAM>), grid, block, 0, s, g, y, a, batch);
+}
+
+template <int MODE, bool REDUCE>
+static void launch_bp_mode(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s) {
+    if (g.beam == 0) launch_bp_beam<MODE, REDUCE, 0>(g, y, a, batch, s);
+    else launch_bp_beam<MODE, REDUCE, 1>(g, y, a, batch, s);
 }
 
 hipError_t launch_backproject(const KGeom& g, const float* y, const BpArgs& a, int batch, hipStream_t s) {
