@@ -395,9 +395,10 @@ hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, i
 // ---------------------------------------------------------------------------- adjoint J^T
 // One thread per column of PIX vertically adjacent pixels (i, j .. j + PIX - 1)
 // and up to BT images; 16 x 16 PIX pixels per block.  PIX = 2 throughout: four
-// pixels per thread share more intercept work, but at 512^2 and one image the
-// grid then holds a single block per CU and runs slower (measured 0.90 against
-// 0.75 ms).  For every view the thread takes the bins whose rays
+// pixels per thread share more intercept work but halve the wavefronts (1.24
+// against 0.82 ms at 512^2 and 8 images), one pixel doubles them but also the
+// LDS reads per pixel (1.38 against 0.99 ms at 16 images).  For every view the
+// thread takes the bins whose rays
 // can give any of its pixels a non-zero Joseph weight: any sample that touches
 // a pixel lies in the diamond |dx| + |dy| < pixel around its centre, so its ray
 // meets the detector within hw bins of the centre's own projection k_c, where
@@ -407,8 +408,8 @@ hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, i
 // re-evaluates the forward projector's own fixed-point intercept and float32
 // weights, so the result is the exact transpose of J (k_project before its
 // step scaling) up to summation order.  An x-driven ray crosses all PIX pixels at the same
-// intercept, so one evaluation gives every weight; a y-driven ray needs one
-// more 64-bit add per pixel.  A larger window only adds candidates of weight
+// intercept, so one evaluation gives every weight; a y-driven ray needs its
+// own intercept (one multiply-add) per pixel.  A larger window only adds candidates of weight
 // exactly zero, so every pixel gets the same bits whatever PIX and BT.
 //
 // Views are processed eight at a time, two per wavefront.  Per view, the
@@ -477,7 +478,7 @@ __device__ __forceinline__ void bp_candidates(const RayEntry* rays, const float*
 // loop: one loop, so the accumulators keep one set of registers across views
 // (the per-axis loops make the compiler move them between register sets at
 // every view), and the next pair is read at the end of an iteration.  Used
-// from 8-image groups: with 8 images it needs 126 VGPRs against 167, which
+// from 8-image groups: with 8 images it needs 127 VGPRs against 167, which
 // leaves room on each CU for the kernels of the other sub-batch stream of a
 // split solve (8-image halves of a 16-image batch), though on its own the
 // 8-image kernel is about 5% slower than the per-axis loops; with 16 images it
