@@ -551,11 +551,27 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     // slot stride: BT floats, padded by 4 from 8 images up so that the 16-byte
     // reads of 8 consecutive slots fall in distinct LDS banks
     constexpr int SV = BT >= 8 ? BT + 4 : BT;
+    // A group of views whose staged rays are all x-driven runs one loop
+    // with no axis test.  One whose rays are all y-driven runs the same
+    // loop over horizontal pixel tuples instead, which then share each
+    // intercept as vertical ones do for x-driven rays; the tuple sums
+    // reach the vertical owners through LDS.  Every pixel takes the same
+    // terms in the same order either way.  Groups of both kinds, and
+    // windows wider than one pass, take the per-view axis test.  Only
+    // up to 4 images: the extra loops raise 8-image groups from 127 to
+    // 165 VGPRs and 16-image ones from 195 to 243, and the halves of a
+    // two-stream solve (8 or 16 images) then leave less room for the
+    // other stream's kernels (slower overall, though an 8-image launch
+    // alone is 13% faster).
+    constexpr bool kModes = BT <= 4;
     __shared__ __align__(16) float s_val[NV][BINS * SV];
     // per view: tile window (first bin, bin count, half-width as float bits),
     // whether the staged rays are all x-driven (0), all y-driven (1) or both
     // (2), and (cos, sin) as float bits; read together, with one wait
     __shared__ __align__(16) int s_view[NV][8];
+    // per view: 1 if any staged ray is x-driven, 2 if any is y-driven, 4 if the
+    // window needs more than one staging pass
+    __shared__ __align__(16) int s_flags[NV];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i0 = blockIdx.x * 16, j0 = blockIdx.y * TH;
@@ -565,6 +581,11 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     // (pixels past the image edge take an in-image neighbour's window; their sums are dropped)
     const float px = ((float)min(i, n - 1) - g.half_n) * g.pixel;
     const float py = ((float)min(j, max(n - PIX, 0)) - g.half_n) * g.pixel;
+    // the same thread's horizontal tuple (ih + q, jh), q < PIX, used for views
+    // whose rays are all y-driven (see below)
+    const int ih = i0 + PIX * (threadIdx.x % (16 / PIX)), jh = j0 + threadIdx.x / (16 / PIX);
+    const float pxh = ((float)min(ih, max(n - PIX, 0)) - g.half_n) * g.pixel;
+    const float pyh = ((float)min(jh, n - 1) - g.half_n) * g.pixel;
     // corners of the tile's in-image pixel centres, for the tile windows
     const float cx[2] = {((float)i0 - g.half_n) * g.pixel, ((float)min(i0 + 15, n - 1) - g.half_n) * g.pixel};
     const float cy[2] = {((float)j0 - g.half_n) * g.pixel, ((float)min(j0 + TH - 1, n - 1) - g.half_n) * g.pixel};
@@ -666,9 +687,75 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                     any_x = any_x || __ballot(act && ax == 0) != 0;
                     any_y = any_y || __ballot(act && ax == 1) != 0;
                 }
-                if (lane == 0) s_view[sv][3] = any_y ? (any_x ? 2 : 1) : 0;
+                if (lane == 0) {
+                    s_view[sv][3] = any_y ? (any_x ? 2 : 1) : 0;
+                    if constexpr (kModes) s_flags[sv] = (any_x ? 1 : 0) | (any_y ? 2 : 0) | (my_nb[hh] > BINS ? 4 : 0);
+                }
             }
             __syncthreads();
+            int mode = 0;
+            if (kModes && p == 0) {
+                const int4 fa = *reinterpret_cast<const int4*>(&s_flags[0]);
+                const int4 fb = *reinterpret_cast<const int4*>(&s_flags[4]);
+                const int f = __builtin_amdgcn_readfirstlane(fa.x | fa.y | fa.z | fa.w | fb.x | fb.y | fb.z | fb.w);
+                if (!(f & 4)) mode = (f & 2) == 0 ? 1 : ((f & 1) == 0 ? 2 : 0);
+            }
+            static_assert(NV == 8, "flags read as two int4");
+            // this view's candidate slots [wlo, whi] for centres (xa, ya) and (xa + dx, ya + dy)
+            auto slots = [&](int s, float xa, float ya, float dx, float dy, int& wlo, int& whi) {
+                const int4 vw = *reinterpret_cast<const int4*>(&s_view[s][0]);
+                const int2 vc = *reinterpret_cast<const int2*>(&s_view[s][4]);
+                const int kb0 = __builtin_amdgcn_readfirstlane(vw.x);
+                const int nbs = __builtin_amdgcn_readfirstlane(vw.y);
+                const float hws = __int_as_float(__builtin_amdgcn_readfirstlane(vw.z));
+                const float2 cs = make_float2(__int_as_float(__builtin_amdgcn_readfirstlane(vc.x)),
+                                              __int_as_float(__builtin_amdgcn_readfirstlane(vc.y)));
+                const float ka = bin_of<BEAM>(g, xa, ya, cs.x, cs.y);
+                const float kb = bin_of<BEAM>(g, xa + dx, ya + dy, cs.x, cs.y);
+                const int klo = max(kb0, (int)ceilf(fminf(ka, kb) - hws - 0.01f));
+                const int khi = min(kb0 + nbs - 1, (int)floorf(fmaxf(ka, kb) + hws + 0.01f));
+                wlo = max(klo - kb0, 0);
+                whi = min(khi - kb0, BINS - 1);
+            };
+            if (mode == 1) {
+#pragma unroll
+                for (int s = 0; s < NV; s++) {
+                    if (v0 + s >= g.n_views) continue;
+                    int wlo, whi;
+                    slots(s, px, py, 0.f, (PIX - 1) * g.pixel, wlo, whi);
+                    if constexpr (BT >= kBpInLoopMin)
+                        bp_candidates_any<BT, PIX, SV>(0, s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
+                    else
+                        bp_candidates<0, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
+                }
+                __syncthreads();
+                continue;
+            }
+            if (mode == 2) {
+                // acc (still zero: first and only pass) first holds the tuple sums
+#pragma unroll
+                for (int s = 0; s < NV; s++) {
+                    if (v0 + s >= g.n_views) continue;
+                    int wlo, whi;
+                    slots(s, pxh, pyh, (PIX - 1) * g.pixel, 0.f, wlo, whi);
+                    // the x-driven loop with the roles of rows and columns exchanged
+                    if constexpr (BT >= kBpInLoopMin)
+                        bp_candidates_any<BT, PIX, SV>(0, s_ray[s], s_val[s], wlo, whi, jh, ih, g.c0, acc);
+                    else
+                        bp_candidates<0, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, jh, ih, g.c0, acc);
+                }
+                __syncthreads();
+                // tuple sums -> [row][column][image] in the value buffer -> vertical owners
+                float* xb = &s_val[0][0];
+                static_assert(NV * BINS * SV >= 16 * TH * BT, "exchange fits the value buffer");
+#pragma unroll
+                for (int q = 0; q < PIX; q++) store_group<BT>(xb + ((jh - j0) * 16 + (ih - i0) + q) * BT, acc[q]);
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < PIX; r++) load_group<BT>(xb + ((j - j0 + r) * 16 + (i - i0)) * BT, acc[r]);
+                __syncthreads();
+                continue;
+            }
 #pragma unroll
             for (int s = 0; s < NV; s++) {
                 // the view's window (uniform over the block), and this column's
