@@ -219,6 +219,34 @@ def test_backprojection_batch_matches_single(air, torch_mod, batch):
         assert np.array_equal(host(plan.project(dev(torch_mod, xs[b:b + 1])))[0], yb[b])
 
 
+@pytest.mark.parametrize("g", [Geometry("parallel", n=45, pixel=1.0, n_views=96, n_bins=70, bin=1.0),
+                               Geometry("fan", n=45, pixel=1.0, n_views=240, n_bins=90, bin=1.0, sod=150.0, sdd=250.0)],
+                         ids=["parallel", "fan"])
+def test_backprojection_single_axis_groups_match_general_path(air, torch_mod, g):
+    """Groups of up to four images run eight views whose staged rays share one
+    axis through a loop with no axis test (y-driven ones over horizontal pixel
+    pairs, handed back through LDS); 8-image groups always take the general
+    path.  Every pixel gets the same bits either way, also on tiles cut by the
+    image edge (n = 45)."""
+    plan = air.Plan(g, max_batch=8)
+    axis, _, _ = plan.tables()
+    groups = [set(np.unique(axis[v:v + 8]).tolist()) for v in range(0, g.n_views, 8)]
+    assert {0} in groups and {1} in groups and {0, 1} in groups   # all three kinds of view group occur
+    rng = np.random.default_rng(5)
+    ys = rng.standard_normal((8, g.n_views, g.n_bins)).astype(np.float32)
+    for filt in (0, 1):
+        x8 = host(plan.filtered_backproject(dev(torch_mod, ys), filter=filt))
+        x4 = host(plan.filtered_backproject(dev(torch_mod, ys[:4]), filter=filt))
+        assert np.array_equal(x4, x8[:4]), filt
+        for b in (0, 5):
+            x1 = host(plan.filtered_backproject(dev(torch_mod, ys[b:b + 1]), filter=filt))[0]
+            assert np.array_equal(x1, x8[b]), (filt, b)
+    xs = rng.uniform(0, 0.03, (8, g.n, g.n)).astype(np.float32)
+    z8 = host(plan.normal_apply(dev(torch_mod, xs), 0.5))
+    z1 = host(plan.normal_apply(dev(torch_mod, xs[2:3]), 0.5))[0]
+    assert np.array_equal(z1, z8[2])
+
+
 def test_batch_above_plan_limit_is_rejected(air, torch_mod):
     plan = air.Plan(geom("small_par"), max_batch=1)
     x = torch_mod.zeros((2, 40, 40), device="cuda")
