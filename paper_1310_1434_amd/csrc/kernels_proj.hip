@@ -564,6 +564,7 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     // other stream's kernels (slower overall, though an 8-image launch
     // alone is 13% faster).
     constexpr bool kModes = BT <= 4;
+    static_assert(!kModes || BT < kBpInLoopMin, "single-axis groups use the per-axis loop");
     __shared__ __align__(16) float s_val[NV][BINS * SV];
     // per view: tile window (first bin, bin count, half-width as float bits),
     // whether the staged rays are all x-driven (0), all y-driven (1) or both
@@ -723,10 +724,7 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                     if (v0 + s >= g.n_views) continue;
                     int wlo, whi;
                     slots(s, px, py, 0.f, (PIX - 1) * g.pixel, wlo, whi);
-                    if constexpr (BT >= kBpInLoopMin)
-                        bp_candidates_any<BT, PIX, SV>(0, s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
-                    else
-                        bp_candidates<0, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
+                    bp_candidates<0, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
                 }
                 __syncthreads();
                 continue;
@@ -739,10 +737,7 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                     int wlo, whi;
                     slots(s, pxh, pyh, (PIX - 1) * g.pixel, 0.f, wlo, whi);
                     // the x-driven loop with the roles of rows and columns exchanged
-                    if constexpr (BT >= kBpInLoopMin)
-                        bp_candidates_any<BT, PIX, SV>(0, s_ray[s], s_val[s], wlo, whi, jh, ih, g.c0, acc);
-                    else
-                        bp_candidates<0, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, jh, ih, g.c0, acc);
+                    bp_candidates<0, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, jh, ih, g.c0, acc);
                 }
                 __syncthreads();
                 // tuple sums -> [row][column][image] in the value buffer -> vertical owners
