@@ -443,23 +443,24 @@ static hipError_t device_sub_streams(hipStream_t (&out)[2]) {
     return hipSuccess;
 }
 
-// One sub-batch: images [b0, b0 + nb) of the call, workspace at ws.
-static air_status solve_part(air_plan p, const float* Y, float* X, int b0, int nb, const air_solve_params* prm,
-                             double* resid, char* ws, hipStream_t s) {
+static SolveSetup solve_setup(const air_solve_params* prm) {
+    return SolveSetup{prm->reg, prm->filter, prm->lambda, prm->mu, prm->n_cg};
+}
+static int solve_outer_count(const air_solve_params* prm) { return prm->reg == 1 ? 1 : prm->n_outer; }
+
+// Images [b0, b0 + nb) of a solve: buffers in ws, and the start (g = A'^T Y,
+// d = b = 0) enqueued on s.
+static air_status part_begin(air_plan p, const float* Y, float* X, int b0, int nb, const air_solve_params* prm,
+                             double* resid, char* ws, hipStream_t s, SolveBufs& B) {
     const size_t np = (size_t)p->g.n * p->g.n, nyv = (size_t)p->g.n_views * p->g.n_bins;
-    SolveBufs B = solve_bufs(p, solve_layout(p, nb), ws, X + b0 * np, nb);
+    B = solve_bufs(p, solve_layout(p, nb), ws, X + b0 * np, nb);
     if (resid) {
         B.resid = resid + (size_t)b0 * prm->n_outer;
         B.resid_stride = prm->n_outer;
     } else {
         B.iters = nullptr;          // residual norms go to scratch, one slot per image
     }
-    const SolveSetup setup{prm->reg, prm->filter, prm->lambda, prm->mu, prm->n_cg};
-    if (air_status st = solve_init(p, B, Y + b0 * nyv, nb, setup, s)) return st;
-    const int n_out = prm->reg == 1 ? 1 : prm->n_outer;
-    for (int k = 0; k < n_out; k++)
-        if (air_status st = solve_outer(p, B, nb, setup, s)) return st;
-    return AIR_OK;
+    return solve_init(p, B, Y + b0 * nyv, nb, solve_setup(prm), s);
 }
 
 air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const air_solve_params* prm,
@@ -476,7 +477,13 @@ air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const 
     if (ws_bytes < solve_bytes(p, batch)) return fail(AIR_E_NOMEM, "workspace smaller than air_solve_workspace_size");
     char* w = static_cast<char*>(ws);
     const int parts = solve_parts(p, batch);
-    if (parts == 1) return solve_part(p, Y, X, 0, batch, prm, resid, w, s);
+    if (parts == 1) {
+        SolveBufs B;
+        if (air_status st = part_begin(p, Y, X, 0, batch, prm, resid, w, s, B)) return st;
+        for (int k = 0; k < solve_outer_count(prm); k++)
+            if (air_status st = solve_outer(p, B, batch, solve_setup(prm), s)) return st;
+        return AIR_OK;
+    }
     // fork: both sub-streams wait for the caller's stream; join: the caller's
     // stream waits for both (also after a failed launch, so that nothing of
     // this call is still running on the workspace once the stream moves on)
@@ -487,15 +494,24 @@ air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const 
         if (!p->join_ev[i]) AIR_HIP(hipEventCreateWithFlags(&p->join_ev[i], hipEventDisableTiming));
     if (!p->fork_ev) AIR_HIP(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
     AIR_HIP(hipEventRecord(p->fork_ev, s));
+    // the two parts' outer iterations are enqueued alternately, so that both
+    // streams have queued work from the start whatever the depth of their
+    // queues (with the default depth this measured the same as enqueuing one
+    // part whole and then the other)
     air_status result = AIR_OK;
-    int b0 = 0;
-    for (int i = 0; i < 2; i++) {
-        const int nb = part_size(batch, 2, i);
+    SolveBufs B[2];
+    int nb[2];
+    for (int i = 0, b0 = 0; i < 2; b0 += nb[i], i++) {
+        nb[i] = part_size(batch, 2, i);
         AIR_HIP(hipStreamWaitEvent(sub[i], p->fork_ev, 0));
-        if (result == AIR_OK) result = solve_part(p, Y, X, b0, nb, prm, resid, w + part_offset(p, batch, 2, i), sub[i]);
+        if (result == AIR_OK)
+            result = part_begin(p, Y, X, b0, nb[i], prm, resid, w + part_offset(p, batch, 2, i), sub[i], B[i]);
+    }
+    for (int k = 0; k < solve_outer_count(prm) && result == AIR_OK; k++)
+        for (int i = 0; i < 2 && result == AIR_OK; i++) result = solve_outer(p, B[i], nb[i], solve_setup(prm), sub[i]);
+    for (int i = 0; i < 2; i++) {
         AIR_HIP(hipEventRecord(p->join_ev[i], sub[i]));
         AIR_HIP(hipStreamWaitEvent(s, p->join_ev[i], 0));
-        b0 += nb;
     }
     return result;
 }
