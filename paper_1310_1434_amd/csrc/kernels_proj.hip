@@ -551,6 +551,14 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     // slot stride: BT floats, padded by 4 from 8 images up so that the 16-byte
     // reads of 8 consecutive slots fall in distinct LDS banks
     constexpr int SV = BT >= 8 ? BT + 4 : BT;
+    __shared__ __align__(16) float s_val[NV][BINS * SV];
+    // per view: tile window (first bin, bin count, half-width as float bits),
+    // whether the staged rays are all x-driven (0), all y-driven (1) or both
+    // (2), and (cos, sin) as float bits; read together, with one wait
+    __shared__ __align__(16) int s_view[NV][8];
+    // per view: 1 if any staged ray is x-driven, 2 if any is y-driven, 4 if the
+    // window needs more than one staging pass
+    __shared__ __align__(16) int s_flags[NV];
     // A group of views whose staged rays are all x-driven runs one loop
     // with no axis test.  One whose rays are all y-driven runs the same
     // loop over horizontal pixel tuples instead, which then share each
@@ -565,14 +573,6 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     // alone is 13% faster).
     constexpr bool kModes = BT <= 4;
     static_assert(!kModes || BT < kBpInLoopMin, "single-axis groups use the per-axis loop");
-    __shared__ __align__(16) float s_val[NV][BINS * SV];
-    // per view: tile window (first bin, bin count, half-width as float bits),
-    // whether the staged rays are all x-driven (0), all y-driven (1) or both
-    // (2), and (cos, sin) as float bits; read together, with one wait
-    __shared__ __align__(16) int s_view[NV][8];
-    // per view: 1 if any staged ray is x-driven, 2 if any is y-driven, 4 if the
-    // window needs more than one staging pass
-    __shared__ __align__(16) int s_flags[NV];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i0 = blockIdx.x * 16, j0 = blockIdx.y * TH;
@@ -582,8 +582,8 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     // (pixels past the image edge take an in-image neighbour's window; their sums are dropped)
     const float px = ((float)min(i, n - 1) - g.half_n) * g.pixel;
     const float py = ((float)min(j, max(n - PIX, 0)) - g.half_n) * g.pixel;
-    // the same thread's horizontal tuple (ih + q, jh), q < PIX, used for views
-    // whose rays are all y-driven (see below)
+    // the same thread's horizontal tuple (ih + q, jh), q < PIX, used for view
+    // groups whose rays are all y-driven (kModes)
     const int ih = i0 + PIX * (threadIdx.x % (16 / PIX)), jh = j0 + threadIdx.x / (16 / PIX);
     const float pxh = ((float)min(ih, max(n - PIX, 0)) - g.half_n) * g.pixel;
     const float pyh = ((float)min(jh, n - 1) - g.half_n) * g.pixel;
