@@ -575,7 +575,21 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     static_assert(!kModes || BT < kBpInLoopMin, "single-axis groups use the per-axis loop");
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * TH;
+    // tiles -> XCDs: blocks go to the eight XCDs round-robin; when the tile grid
+    // splits into eight equal rectangles, each XCD gets one of them, so the
+    // tiles sharing an L2 are neighbours and stage overlapping windows
+    int bx = blockIdx.x, by = blockIdx.y;
+    {
+        const int gx = gridDim.x, gy = gridDim.y;
+        if (gx % 4 == 0 && gy % 2 == 0) {
+            const int L = by * gx + bx, T = gx * gy;
+            const int t = (L % 8) * (T / 8) + L / 8;
+            const int rw = gx / 4, rh = gy / 2, r = t / (rw * rh), u = t % (rw * rh);
+            bx = (r % 4) * rw + u % rw;
+            by = (r / 4) * rh + u / rw;
+        }
+    }
+    const int i0 = bx * 16, j0 = by * TH;
     const int i = i0 + tx, j = j0 + PIX * ty;      // pixels (i, j + r), r < PIX
     const int b0 = blockIdx.z * BT;
     const int n = g.n;
@@ -788,7 +802,7 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
             for (int q = 0; q < BT; q++) tot[r][q] += (double)acc[r][q];
     }
     const int nblk = gridDim.x * gridDim.y;
-    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    const int blk = by * gridDim.x + bx;
     float res[PIX][BT];     // RESIDUAL: r of every pixel and image (0 outside the image or batch)
 #pragma unroll
     for (int q = 0; q < BT; q++) {
