@@ -7,14 +7,27 @@ framelet shrinkage), from the noisy sinograms already resident in HBM.
 
     python bench.py [--steps K] [--warmup W] [--batch B]
 
-Prints one JSON line: recon/s (float32 path) with p50/p99 step latency, the
-same for the mixed-precision ramp, projector GRays/s, the roofline position of
-the dominant kernel (HIP-event timing inside this run) and the FP64 CPU oracle
-timed on a bounded sample of the same workload.
+Prints one JSON line with
+  value / p50_ms / p99_ms   recon/s and step latency of the float32 path (the
+                            batch runs as two sub-batches on two streams),
+  mixed                     the same for the mixed-precision path,
+  rel_l2_vs_oracle          image 0 (seed 0) of the last timed step of each path
+                            against the stored FP64 oracle reconstruction,
+  c2_25                     the same scan with 25% of the views (180),
+  served                    continuous-batching serving of the mixed-geometry
+                            request stream (Poisson arrivals at 40/s, both
+                            paths; p50/p99 arrival-to-result latency; a short
+                            rate sweep of the mixed path),
+  kernel_ms / roofline      HIP-event times of every kernel in a solve of the
+                            timed configuration, and the dominant kernel on its
+                            roofline (kernel_ms_alone / roofline_alone: the
+                            same with every kernel running alone),
+  cpu_baseline              the FP64 CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
+import copy
 import hashlib
 import json
 import os
@@ -28,15 +41,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "mixed_f16": 2500.0, "mixed_bf16": 2500.0}
-# VALU issue peak: 256 CUs x 4 SIMD x 32 lanes per clock x 2.4 GHz (non-packed lane
-# operations; a wave64 float32 operation issues in two cycles, so the published
-# float32 vector rate, 157.3 TFLOP/s, is 78.6 T fused multiply-adds per second)
+# Published float32 vector peak: 256 CUs x 4 SIMD x 32 lanes per clock x 2.4 GHz
+# = 78.6 T lane operations per second, 157.3 TFLOP/s counting a fused
+# multiply-add as two flops (packed float32 is not used).
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
-# essential VALU lane operations of one Joseph sample (ray-step): advance the
-# fixed-point intercept, convert its fraction, form the two weights, form the
-# sample address, two fused multiply-adds
-VALU_OPS_PER_SAMPLE = 7
+# Work of the projectors per Joseph sample (ray-step): two fused multiply-adds
+# per image (the two interpolation taps), plus the index work a thread shares
+# over its group of images (advance the intercept, convert its fraction, the
+# two weights, the sample address: 5 lane operations per group).
+FMA_PER_SAMPLE_IMAGE = 2
+SHARED_OPS_PER_SAMPLE_GROUP = 5
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
 def parse():
@@ -45,18 +62,24 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2_25", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2_25", "c5", "c3_gemm"],
+                    help="c3_gemm: the ramp GEMM alone at the 736 x 736 filter x 11,520-row measurement shape")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-quarter", action="store_true", help="skip the 25%%-data (180-view) leg")
     ap.add_argument("--kernel-timing-only", action="store_true",
                     help="skip the timed steps; run only the instrumented pass (for profiler runs)")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="profiler runs only: the instrumented pass runs every kernel alone")
     ap.add_argument("--outer", type=int, default=0,
                     help="profiler runs only: Bregman iterations of the instrumented pass (0 = the workload's)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="profiler runs only: also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--serve", action="store_true",
-                    help="run the continuous-batching serving benchmark instead (Poisson arrivals, mixed geometries)")
-    ap.add_argument("--serve-requests", type=int, default=120)
+                    help="run only the continuous-batching serving benchmark (Poisson arrivals, mixed geometries)")
+    ap.add_argument("--serve-requests", type=int, default=330)
+    ap.add_argument("--serve-warmup", type=int, default=30, help="first requests left out of the latency figures")
     ap.add_argument("--serve-rate", type=float, default=40.0, help="offered load, requests per second")
     ap.add_argument("--serve-capacity", type=int, default=8, help="slots per geometry group")
     ap.add_argument("--serve-precision", default="mixed_f16", choices=["fp32", "mixed_f16", "mixed_bf16"])
@@ -72,26 +95,35 @@ def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1310_1434_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".cuh", ".h")):
+        if f.endswith((".hip", ".h")):
             h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
+def rel_l2(x, ref) -> float:
+    x = np.asarray(x, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return float(np.linalg.norm((x - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+
 def timed_steps(torch, plan, y, w, steps, warmup, ws):
+    """W untimed steps, then K timed steps between two synchronisations; returns
+    (wall seconds, per-step event latencies in ms, the last step's images)."""
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         plan.solve(y, w.lam, w.mu, w.n_outer, w.n_cg, workspace=ws, with_resid=False)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    x = None
     t0 = time.perf_counter()
     ev[0].record(stream)
     for k in range(steps):
-        plan.solve(y, w.lam, w.mu, w.n_outer, w.n_cg, workspace=ws, with_resid=False)
+        x, _ = plan.solve(y, w.lam, w.mu, w.n_outer, w.n_cg, workspace=ws, with_resid=False)
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lat = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
-    return wall, lat
+    return wall, lat, x
 
 
 def ray_steps(plan) -> int:
@@ -99,19 +131,118 @@ def ray_steps(plan) -> int:
     return int(np.maximum(hi - lo + 1, 0).sum())
 
 
+def image_group(batch: int) -> int:
+    """Images per backprojector thread (the library's own choice for a launch of `batch`)."""
+    best, cost = 1, 3 * batch
+    for g in (2, 4, 8, 16):
+        c = -(-batch // g) * (2 + g)
+        if c < cost:
+            best, cost = g, c
+    return best
+
+
+def golden_image(name: str):
+    path = os.path.join(GOLDEN, name + ".npz")
+    return np.load(path)["x"] if os.path.exists(path) else None
+
+
+def instrumented(torch, air, plan, y, w, ws, mode, n_outer):
+    """One solve with every kernel bracketed by HIP events on its launch stream."""
+    plan.kernel_timing(mode)
+    plan.solve(y, w.lam, w.mu, n_outer, w.n_cg, workspace=ws, with_resid=False)
+    torch.cuda.synchronize()
+    kt = plan.collect_kernel_timing()
+    plan.kernel_timing("off")
+    return {k: {"avg_ms": (v[0] / v[1]) if v[1] else 0.0, "launches": v[1], "total_ms": v[0]} for k, v in kt.items()}
+
+
+def roofline(kernel_ms, g, B, n_outer, n_cg, rsteps, precision, label):
+    """The dominant kernel of an instrumented solve on its roofline.  Images per
+    launch follow from the launch count (a split batch launches each operator
+    once per sub-batch)."""
+    dom = max(("project", "backproject", "ramp"), key=lambda k: kernel_ms[k]["total_ms"])
+    km = kernel_ms[dom]
+    t = km["avg_ms"] * 1e-3
+    applies = {"project": n_outer * (1 + n_cg), "backproject": 1 + n_outer * (1 + n_cg),
+               "ramp": 1 + n_outer * (1 + n_cg)}[dom]
+    ipl = B * applies / km["launches"]
+    if dom == "ramp":
+        flops = 2.0 * ipl * g.n_views * g.n_bins * g.n_bins
+        peak = MFMA_PEAK_TFLOPS["fp32" if precision == "fp32" else precision]
+        achieved = flops / t / 1e12
+        return {"kernel": "k_ramp_" + ("f32" if precision == "fp32" else "split"), "config": label, "bound": "mfma",
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "images_per_launch": ipl, "avg_launch_ms": t * 1e3}
+    flops = 2.0 * FMA_PER_SAMPLE_IMAGE * ipl * rsteps
+    achieved = flops / t / 1e12
+    G = image_group(int(round(ipl))) if dom == "backproject" else (4 if precision != "fp32" else 2)
+    groups = -(-int(round(ipl)) // G)
+    lane_ops = (FMA_PER_SAMPLE_IMAGE * ipl + SHARED_OPS_PER_SAMPLE_GROUP * groups) * rsteps
+    return {"kernel": "k_" + dom, "config": label, "bound": "alu", "achieved": achieved,
+            "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+            "work": f"{FMA_PER_SAMPLE_IMAGE} FMA (4 flop) per Joseph sample per image, {rsteps} samples per image, "
+                    f"{ipl:g} images per launch",
+            "valu_issue_frac": lane_ops / t / (VALU_PEAK_TOPS * 1e12),
+            "valu_issue_work": f"the FMAs plus {SHARED_OPS_PER_SAMPLE_GROUP} shared index operations per sample "
+                               f"per group of {G} images, against {VALU_PEAK_TOPS:.1f} T lane operations/s",
+            "images_per_launch": ipl, "avg_launch_ms": t * 1e3, "ray_steps_per_image": rsteps}
+
+
+def traffic_for(kernel_instance: str, batch: int):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources at this batch."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    tr = json.load(open(TRAFFIC_FILE))
+    if tr.get("source_hash") != kernel_source_hash() or tr.get("batch") != batch:
+        return None
+    ent = tr.get("kernels", {}).get(kernel_instance)
+    return ent["bytes_per_launch"] if ent else None
+
+
 def cpu_baseline(w, y0):
-    """FP64 oracle on 2 of the 50 Bregman iterations of one case, scaled to a full solve."""
+    """FP64 oracle on the host's cores, bounded: solves of 1 and 3 Bregman
+    iterations of one C2 case give the cost per iteration and the one-off set-up
+    (g = A'^T Y), from which the 50-iteration solve is extrapolated; plus the
+    time per apply of A and A'^T on all cores and on one, and a full C1 solve."""
     import oracle
+    import synth
     oracle.build(force=False)
+    cores = oracle.num_threads()
     g = oracle.Geom(w.geom)
-    k = 2
-    t = time.perf_counter()
-    oracle.solve(g, y0.astype(np.float64), w.lam, w.mu, k, w.n_cg)
-    dt = time.perf_counter() - t
-    per_recon = dt * w.n_outer / k
-    return {"value": 1.0 / per_recon, "unit": "recon/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"FP64 oracle, {k} of {w.n_outer} Bregman iterations (x{w.n_cg} CG) of one "
-                      f"{w.geom.n}^2 x {w.geom.n_views}-view case in {dt:.2f} s, scaled x{w.n_outer // k}"}
+    y = y0.astype(np.float64)
+
+    def clock(f):
+        t = time.perf_counter()
+        f()
+        return time.perf_counter() - t
+
+    t1 = clock(lambda: oracle.solve(g, y, w.lam, w.mu, 1, w.n_cg))
+    t3 = clock(lambda: oracle.solve(g, y, w.lam, w.mu, 3, w.n_cg))
+    per_outer = (t3 - t1) / 2.0
+    setup = t1 - per_outer
+    full = setup + w.n_outer * per_outer
+    x = np.zeros((w.geom.n, w.geom.n)) + 0.01
+    per_apply = {"cores": cores}
+    per_apply["A_s"] = min(clock(lambda: oracle.project(g, x)) for _ in range(2))
+    per_apply["AtC_s"] = min(clock(lambda: oracle.filtered_backproject(g, y, 1)) for _ in range(2))
+    oracle.set_threads(1)
+    try:
+        per_apply["A_s_1core"] = clock(lambda: oracle.project(g, x))
+        per_apply["AtC_s_1core"] = clock(lambda: oracle.filtered_backproject(g, y, 1))
+    finally:
+        oracle.set_threads(cores)
+    w1 = synth.workload("c1")
+    y1 = synth.make_case(w1, 0)["y"].astype(np.float32).astype(np.float64)
+    t_c1 = clock(lambda: oracle.solve(oracle.Geom(w1.geom), y1, w1.lam, w1.mu, w1.n_outer, w1.n_cg))
+    return {"value": 1.0 / full, "unit": "recon/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle on {cores} threads, one {w.geom.n}^2 x {w.geom.n_views}-view case: solves of 1 and "
+                      f"3 Bregman iterations (x{w.n_cg} CG) took {t1:.2f} s and {t3:.2f} s, i.e. {per_outer:.2f} s per "
+                      f"iteration and {setup:.2f} s of set-up; value is the {w.n_outer}-iteration solve extrapolated "
+                      f"from them ({full:.1f} s)",
+            "extrapolated": True, "per_apply": per_apply,
+            "c1_solve_s": t_c1, "c1_solve": f"{w1.geom.n}^2 x {w1.geom.n_views} views, {w1.n_outer} x {w1.n_cg}, "
+                                             f"measured whole on {cores} threads"}
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str, batch: int):
@@ -125,7 +256,9 @@ def summarize_pmc(fetch_dir: str, write_dir: str, batch: int):
         vals = {}
         for f in files:
             for r in csv.DictReader(open(f)):
-                name = r["Kernel_Name"]
+                # "void air::k_x<...>(args)" -> "air::k_x<...>"
+                name = r["Kernel_Name"].split("(")[0].strip()
+                name = name[5:] if name.startswith("void ") else name
                 vals.setdefault(name, []).append(float(r["Counter_Value"]))
         return vals
 
@@ -135,18 +268,16 @@ def summarize_pmc(fetch_dir: str, write_dir: str, batch: int):
     cw = max(write.get("__amd_rocclr_copyBuffer", [0.0]))
     sf = copy_bytes / (cf * 1024.0) if cf else None
     sw = copy_bytes / (cw * 1024.0) if cw else None
-    names = {"k_project": "air::k_project<2>", "k_backproject": "air::k_backproject<1, true",
-             "k_ramp_f32": "air::k_ramp_f32<2>"}
     out = {"batch": batch, "source_hash": kernel_source_hash(), "copy_fetch_kib": cf, "copy_write_kib": cw,
            "fetch_scale": sf, "write_scale": sw, "kernels": {}}
-    for short, prefix in names.items():
-        fk = [v for k, vs in fetch.items() if k.startswith(prefix) or prefix in k for v in vs]
-        wk = [v for k, vs in write.items() if k.startswith(prefix) or prefix in k for v in vs]
-        if fk and wk and sf and sw:
-            fb = sum(fk) / len(fk) * 1024.0 * sf
-            wb = sum(wk) / len(wk) * 1024.0 * sw
-            out["kernels"][short] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
-                                     "dispatches": len(fk)}
+    for name in sorted(set(fetch) & set(write)):
+        if not name.startswith("air::") or not sf or not sw:
+            continue
+        fk, wk = fetch[name], write[name]
+        fb = sum(fk) / len(fk) * 1024.0 * sf
+        wb = sum(wk) / len(wk) * 1024.0 * sw
+        out["kernels"][name] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
+                                "dispatches": len(fk)}
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     json.dump(out, open(TRAFFIC_FILE, "w"), indent=1)
     print(json.dumps(out, indent=1))
@@ -185,28 +316,92 @@ def serving_workload(n_requests: int, rate: float, seed: int = 0):
     return reqs
 
 
-def serve_bench(a):
-    import torch
+
+def serve_run(torch, reqs, precision, rate, base_rate, capacity, warmup):
+    """Serve `reqs`, generated at base_rate requests/s, at `rate` (arrival times
+    scaled by base_rate / rate) on a fresh executor; latency figures leave out
+    the first `warmup` requests."""
     from paper_1310_1434_amd.serve import GpuExecutor, Server, geometry_key, latency_stats
 
-    reqs = serving_workload(a.serve_requests, a.serve_rate)
-    ex = GpuExecutor(lam=0.005, mu=1.0, n_cg=5, max_outer=50, capacity=a.serve_capacity,
-                     precision=a.serve_precision)
+    reqs = [copy.copy(r) for r in reqs]
+    for r in reqs:
+        r.arrival *= base_rate / rate
+    ex = GpuExecutor(lam=0.005, mu=1.0, n_cg=5, max_outer=50, capacity=capacity, precision=precision)
     for r in reqs:                    # ray tables are built before the clock starts
         ex.plan(geometry_key(r.geom), r.geom)
+    torch.cuda.synchronize()
     free, _ = torch.cuda.mem_get_info()
-    srv = Server(ex, int(0.8 * free), a.serve_capacity)
+    srv = Server(ex, int(0.8 * free) + ex.resident_bytes(), capacity)
     t = time.perf_counter()
     done = srv.run(reqs)
     wall = time.perf_counter() - t
     ok = [r for r in done if r.error is None]
-    st = latency_stats(done)
-    return {"requests": len(reqs), "offered_rate_per_s": a.serve_rate, "completed": len(ok),
-            "failed": len(done) - len(ok), "recon_per_s": len(ok) / wall, "wall_s": wall,
-            "p50_latency_s": st.get("p50_s"), "p99_latency_s": st.get("p99_s"), "max_latency_s": st.get("max_s"),
-            "geometry_groups": len({geometry_key(r.geom) for r in reqs}), "slots_per_group": a.serve_capacity,
-            "precision": a.serve_precision, "steps": srv.steps,
-            "mean_bregman_iterations": float(np.mean([r.n_outer for r in reqs]))}
+    st = latency_stats([r for r in done if r.rid >= warmup])
+    out = {"precision": precision, "requests": len(reqs), "warmup_requests": warmup,
+           "offered_rate_per_s": rate, "completed": len(ok),
+           "failed": len(done) - len(ok), "recon_per_s": len(ok) / wall, "wall_s": wall,
+           "p50_s": st.get("p50_s"), "p99_s": st.get("p99_s"), "max_s": st.get("max_s"),
+           "geometry_groups": len({geometry_key(r.geom) for r in reqs}), "slots_per_group": capacity,
+           "steps": srv.steps}
+    del srv, ex
+    torch.cuda.synchronize()
+    return out
+
+
+def serve_leg(torch, a):
+    """The serving mix at 40 requests/s on both paths, then the mixed path at 20
+    and 30 requests/s on the first 150 requests.  A rate counts as stable when
+    results keep up with arrivals: the stream is served at >= 95% of the offered
+    rate (a finite stream beyond capacity drains at the capacity instead)."""
+    reqs = serving_workload(a.serve_requests, a.serve_rate)
+    print(f"bench: serving leg, {len(reqs)} requests", file=sys.stderr, flush=True)
+    out = {"workload": f"{len(reqs)} requests: n in {{256, 512, 768}}, views in {{180, 360, 720, 1440}}, "
+                       "100% or 25%, I0 U[1e4, 1e5], 20-50 Bregman x 5 CG, Poisson arrivals",
+           "stable_if": "served rate >= 0.95 x offered rate"}
+    for prec in ("fp32", "mixed_f16"):
+        out[prec] = serve_run(torch, reqs, prec, a.serve_rate, a.serve_rate, a.serve_capacity, a.serve_warmup)
+    sweep = []
+    for rate in (20.0, 30.0):
+        sub = reqs[:150]
+        sweep.append(serve_run(torch, sub, "mixed_f16", rate, a.serve_rate, a.serve_capacity, 15))
+    sweep.append(out["mixed_f16"])
+    out["rate_sweep_mixed"] = [{k: s[k] for k in ("offered_rate_per_s", "recon_per_s", "p50_s", "p99_s")} for s in sweep]
+    stable = [s["offered_rate_per_s"] for s in sweep if s["recon_per_s"] >= 0.95 * s["offered_rate_per_s"]]
+    out["max_stable_rate_per_s"] = max(stable) if stable else None
+    return out
+
+
+def c3_gemm_bench(a):
+    """The ramp GEMM alone at the C3 measurement shape: a 736 x 736 Toeplitz filter
+    times 11,520 sinogram rows (180 views x 64 images of the 512^2 fan geometry's
+    detector), in each precision, timed with HIP events over many launches."""
+    import torch
+    import synth
+    from paper_1310_1434_amd import air
+
+    g = synth.workload("c2_25").geom
+    rows_imgs = 64
+    y = torch.rand((rows_imgs, g.n_views, g.n_bins), device="cuda")
+    out = {"workload": "c3_ramp_gemm_736x736_x_11520", "shape": [rows_imgs * g.n_views, g.n_bins, g.n_bins]}
+    for prec in ("fp32", "mixed_f16", "mixed_bf16"):
+        plan = air.Plan(g, max_batch=rows_imgs, precision=prec)
+        yf = plan.ramp(y)
+        torch.cuda.synchronize()
+        plan.kernel_timing("on")
+        for _ in range(20):
+            plan.ramp(y, out=yf)
+        torch.cuda.synchronize()
+        kt = plan.collect_kernel_timing()
+        plan.kernel_timing("off")
+        ms = kt["ramp"][0] / kt["ramp"][1]
+        terms = {"fp32": 1, "mixed_f16": 3, "mixed_bf16": 6}[prec]
+        flops = 2.0 * rows_imgs * g.n_views * g.n_bins * g.n_bins
+        peak = MFMA_PEAK_TFLOPS[prec]
+        out[prec] = {"avg_launch_ms": ms, "achieved_tflops": flops / (ms * 1e-3) / 1e12,
+                     "achieved_tflops_all_terms": terms * flops / (ms * 1e-3) / 1e12, "peak_tflops": peak,
+                     "frac": flops / (ms * 1e-3) / 1e12 / peak,
+                     "frac_all_terms": terms * flops / (ms * 1e-3) / 1e12 / peak, "products": terms}
+    return out
 
 
 def quality_bench(a):
@@ -247,40 +442,56 @@ def quality_bench(a):
     return out
 
 
+
+def c2_leg(torch, air, w, B, steps, warmup, precisions, golden):
+    """Timed solves of B cases of workload w in each precision; image 0 (seed 0)
+    of the last step against the stored oracle image."""
+    import synth
+    ys = np.stack([synth.make_case(w, s)["y"] for s in range(B)]).astype(np.float32)
+    y = torch.from_numpy(ys).cuda()
+    ref = golden_image(golden)
+    res = {}
+    plans = {}
+    for prec in precisions:
+        plan = air.Plan(w.geom, max_batch=B, precision=prec)
+        ws = torch.empty(plan.solve_workspace_bytes(B), dtype=torch.uint8, device="cuda")
+        wall, lat, x = timed_steps(torch, plan, y, w, steps, warmup, ws)
+        r = {"value": B * steps / wall, "ms_per_step": 1e3 * wall / steps,
+             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
+        if ref is not None:
+            r["rel_l2_vs_oracle"] = rel_l2(x[0].cpu().numpy(), ref)
+        res[prec] = r
+        plans[prec] = (plan, ws)
+    return res, plans, y, ys
+
+
 def main():
     a = parse()
-    if a.quality:
-        if a.gpus != 1:
-            print("bench.py: one GPU only", file=sys.stderr)
-            sys.exit(2)
-        print(json.dumps({"quality": quality_bench(a)}), flush=True)
-        return
-    if a.serve:
-        if a.gpus != 1:
-            print("bench.py: one GPU only", file=sys.stderr)
-            sys.exit(2)
-        print(json.dumps({"serving": serve_bench(a)}), flush=True)
-        return
+    if a.gpus != 1:
+        print(f"bench.py: measures one GPU; --gpus {a.gpus} is not supported (independent reconstructions "
+              "shard across GPUs with no communication; this build runs on one GPU)", file=sys.stderr)
+        sys.exit(2)
     if a.summarize_pmc:
         summarize_pmc(a.summarize_pmc[0], a.summarize_pmc[1], a.batch)
         return
-    if a.gpus != 1:
-        print(f"bench.py: measures one GPU; --gpus {a.gpus} is not supported "
-              "(independent reconstructions shard across GPUs with no communication)", file=sys.stderr)
-        sys.exit(2)
+    if a.quality:
+        print(json.dumps({"quality": quality_bench(a)}), flush=True)
+        return
+    if a.workload == "c3_gemm":
+        print(json.dumps({"c3_gemm": c3_gemm_bench(a)}), flush=True)
+        return
     import torch
     import synth
     from paper_1310_1434_amd import air
+    if a.serve:
+        print(json.dumps({"served": serve_leg(torch, a)}), flush=True)
+        return
 
     w = synth.workload(a.workload)
     B = a.batch
-    ys = np.stack([synth.make_case(w, s)["y"] for s in range(B)]).astype(np.float32)
-    y = torch.from_numpy(ys).cuda()
     g = w.geom
-    plan = air.Plan(g, max_batch=B, precision="fp32")
-    ws = torch.empty(plan.solve_workspace_bytes(B), dtype=torch.uint8, device="cuda")
-    rsteps = ray_steps(plan)
-
+    golden = {"c2": "c2_fan_512_720_seed0", "c2_25": "c2_fan_512_180_seed0"}.get(a.workload, "")
+    precisions = ["fp32"] + ([] if a.no_mixed else ["mixed_f16"])
     out = {"metric": "recon/s + p99 latency, 512^2x720-view AIR, mixed vs FP32; proj GRays/s",
            "unit": "recon/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -288,82 +499,68 @@ def main():
            "config": {"workload": w.name, "beam": g.beam, "n": g.n, "views": g.n_views, "bins": g.n_bins,
                       "batch": B, "n_outer": w.n_outer, "n_cg": w.n_cg, "lambda": w.lam, "mu": w.mu,
                       "precision": "fp32"}}
+    if a.kernel_timing_only:
+        ys = np.stack([synth.make_case(w, s)["y"] for s in range(B)]).astype(np.float32)
+        y = torch.from_numpy(ys).cuda()
+        plans = {}
+        for prec in precisions:
+            plan = air.Plan(g, max_batch=B, precision=prec)
+            plans[prec] = (plan, torch.empty(plan.solve_workspace_bytes(B), dtype=torch.uint8, device="cuda"))
+    else:
+        res, plans, y, ys = c2_leg(torch, air, w, B, a.steps, a.warmup, precisions, golden)
+        f = res["fp32"]
+        out.update({"value": f["value"], "ms_per_step": f["ms_per_step"], "p50_ms": f["p50_ms"],
+                    "p99_ms": f["p99_ms"]})
+        out["rel_l2_vs_oracle"] = {p: res[p].get("rel_l2_vs_oracle") for p in precisions}
+        out["rel_l2_vs_oracle"]["reference"] = (f"image 0 (seed 0) of the last timed step against the FP64 oracle's "
+                                                f"reconstruction tests/golden/{golden}.npz" if golden else None)
+        if "mixed_f16" in res:
+            out["mixed"] = dict(precision="mixed_f16 (ramp as f16 hi/lo MFMA, float16 image copies in the forward "
+                                          "projector)", **res["mixed_f16"])
+        if a.workload == "c2" and not a.no_quarter:
+            w25 = synth.workload("c2_25")
+            r25, _, _, _ = c2_leg(torch, air, w25, B, a.steps, min(a.warmup, 2), precisions, "c2_fan_512_180_seed0")
+            out["c2_25"] = {"workload": w25.name, "views": w25.geom.n_views, "batch": B, **r25}
+            torch.cuda.synchronize()
 
-    if not a.kernel_timing_only:
-        wall, lat = timed_steps(torch, plan, y, w, a.steps, a.warmup, ws)
-        out["value"] = B * a.steps / wall
-        out["ms_per_step"] = 1e3 * wall / a.steps
-        out["p50_ms"] = float(np.percentile(lat, 50))
-        out["p99_ms"] = float(np.percentile(lat, 99))
-        if not a.no_mixed:
-            mp = air.Plan(g, max_batch=B, precision="mixed_f16")
-            wall_m, lat_m = timed_steps(torch, mp, y, w, a.steps, a.warmup, ws)
-            out["mixed"] = {"precision": "mixed_f16 (ramp as f16 hi/lo MFMA, float16 image copies in the forward projector)",
-                            "value": B * a.steps / wall_m,
-                            "ms_per_step": 1e3 * wall_m / a.steps, "p50_ms": float(np.percentile(lat_m, 50)),
-                            "p99_ms": float(np.percentile(lat_m, 99))}
-            del mp
-
-    # instrumented pass: one more step with every kernel bracketed by HIP events
+    # instrumented passes: every kernel bracketed by HIP events on its launch stream
     n_outer = a.outer if (a.kernel_timing_only and a.outer > 0) else w.n_outer
-    plan.kernel_timing(True)
-    plan.solve(y, w.lam, w.mu, n_outer, w.n_cg, workspace=ws, with_resid=False)
-    kt = plan.collect_kernel_timing()
-    plan.kernel_timing(False)
-    kernel_ms = {k: {"avg_ms": (v[0] / v[1]) if v[1] else 0.0, "launches": v[1], "total_ms": v[0]}
-                 for k, v in kt.items()}
-    out["kernel_ms"] = kernel_ms
-    if a.kernel_timing_only and not a.no_mixed:
-        # the same instrumented pass on the mixed path (large configurations, where a
-        # full timed solve would take minutes, are reported per outer iteration)
-        mp = air.Plan(g, max_batch=B, precision="mixed_f16")
-        mp.kernel_timing(True)
-        mp.solve(y, w.lam, w.mu, n_outer, w.n_cg, workspace=ws, with_resid=False)
-        ktm = mp.collect_kernel_timing()
-        mp.kernel_timing(False)
-        out["mixed_kernel_ms"] = {k: {"avg_ms": (v[0] / v[1]) if v[1] else 0.0, "launches": v[1], "total_ms": v[0]}
-                                  for k, v in ktm.items()}
-        del mp
+    plan, ws = plans["fp32"]
+    rsteps = ray_steps(plan)
+    mode = "one_stream" if a.one_stream else "on"
+    km = instrumented(torch, air, plan, y, w, ws, mode, n_outer)
+    out["kernel_ms"] = km
+    out["kernel_ms_config"] = ("every kernel alone (one stream)" if a.one_stream else
+                               "as timed: a batch of 8 or more runs as two sub-batches on two streams")
+    out["roofline"] = roofline(km, g, B, n_outer, w.n_cg, rsteps, "fp32", out["kernel_ms_config"])
+    if not a.one_stream and not a.kernel_timing_only:
+        kma = instrumented(torch, air, plan, y, w, ws, "one_stream", n_outer)
+        out["kernel_ms_alone"] = kma
+        out["roofline_alone"] = roofline(kma, g, B, n_outer, w.n_cg, rsteps, "fp32", "every kernel alone")
+    if "mixed_f16" in plans:
+        mp, mws = plans["mixed_f16"]
+        out["mixed_kernel_ms"] = instrumented(torch, air, mp, y, w, mws, mode, n_outer)
     if a.kernel_timing_only:
         for key in ("kernel_ms", "mixed_kernel_ms"):
             if key in out:
                 tot = sum(v["total_ms"] for v in out[key].values())
                 out[key.replace("kernel_ms", "gpu_ms_per_outer_iteration")] = tot / max(n_outer, 1)
-    rays = B * g.n_views * g.n_bins
-    t_proj = kernel_ms["project"]["avg_ms"] * 1e-3
-    t_bp = kernel_ms["backproject"]["avg_ms"] * 1e-3
-    out["proj_grays_s"] = rays / t_proj / 1e9 if t_proj else None
-    out["backproj_grays_s"] = rays / t_bp / 1e9 if t_bp else None
-
-    # Roofline of the dominant kernel.  The projectors' HBM traffic is small
-    # (the images live in L2/MALL), so they are placed on the VALU issue
-    # roofline: algorithmic work = VALU_OPS_PER_SAMPLE lane operations per
-    # Joseph sample, ray-steps per image from the index tables.
-    dom = max(("project", "backproject", "ramp"), key=lambda k: kernel_ms[k]["total_ms"])
-    t_dom = kernel_ms[dom]["avg_ms"] * 1e-3
-    if dom == "ramp":
-        flops = 2.0 * B * g.n_views * g.n_bins * g.n_bins
-        achieved = flops / t_dom / 1e12
-        roof = {"kernel": "k_ramp_f32", "bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK_TFLOPS["fp32"],
-                "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK_TFLOPS["fp32"]}
-    else:
-        ops = VALU_OPS_PER_SAMPLE * B * float(rsteps)
-        achieved = ops / t_dom / 1e12
-        roof = {"kernel": "k_project" if dom == "project" else "k_backproject", "bound": "alu",
-                "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (VALU lane ops)",
-                "frac": achieved / VALU_PEAK_TOPS, "ops_per_launch": ops, "avg_launch_ms": t_dom * 1e3,
-                "ray_steps_per_image": rsteps}
-    roof["traffic"] = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE))
-        ent = tr.get("kernels", {}).get(roof["kernel"])
-        if ent and tr.get("source_hash") == kernel_source_hash() and tr.get("batch") == B:
-            roof["traffic"] = ent["bytes_per_launch"]
-    out["roofline"] = roof
-    # the same kernels measured as an explicit sparse matrix would be (4 bytes per nonzero)
-    out["sparse_equivalent_gbs"] = {
-        "project": B * (8.0 * rsteps + 4.0 * g.n_views * g.n_bins) / t_proj / 1e9 if t_proj else None,
-        "backproject": B * (8.0 * rsteps + 4.0 * g.n * g.n) / t_bp / 1e9 if t_bp else None}
+    # the roofline kernel's HBM traffic from the committed counter summary
+    inst = None
+    roof = out["roofline"]
+    if roof["kernel"] == "k_backproject":
+        bt = image_group(int(round(roof["images_per_launch"])))
+        inst = f"air::k_backproject<1, true, {bt}, 2, {1 if g.beam == 'fan' else 0}>"
+    elif roof["kernel"] == "k_project":
+        inst = f"air::k_project<{2 if roof['images_per_launch'] >= 2 else 1}>"
+    roof["traffic"] = traffic_for(inst, B) if inst else None
+    roof["traffic_kernel"] = inst
+    rays_launch = g.n_views * g.n_bins
+    for kind, key in (("project", "proj_grays_s"), ("backproject", "backproj_grays_s")):
+        k = km[kind]
+        ipl = B * (n_outer * (1 + w.n_cg) + (kind == "backproject")) / k["launches"] if k["launches"] else 0
+        out[key] = ipl * rays_launch / (k["avg_ms"] * 1e-3) / 1e9 if k["avg_ms"] else None
+    out["grays_note"] = "rays per launch / launch duration in the instrumented solve (kernel_ms_config)"
     out["kernel_source_hash"] = kernel_source_hash()
 
     if a.calibrate_copy:
@@ -373,7 +570,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = src.numel() * 4
-    if not a.no_cpu_baseline:
+    del plans
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if a.workload == "c2" and not (a.no_serve or a.kernel_timing_only):
+        out["served"] = serve_leg(torch, a)
+    if not (a.no_cpu_baseline or a.kernel_timing_only):
         out["cpu_baseline"] = cpu_baseline(w, ys[0])
     print(json.dumps(out), flush=True)
 

@@ -51,7 +51,8 @@ typedef enum {
     AIR_E_UNSUPPORTED = -2,  /* valid but outside what the kernels handle (e.g. n > 16384) */
     AIR_E_NOMEM = -3,        /* workspace too small, or host allocation failed */
     AIR_E_HIP = -4,          /* a HIP call failed (message holds hipGetErrorString) */
-    AIR_E_NONFINITE = -5     /* a solve produced a non-finite residual */
+    AIR_E_NONFINITE = -5     /* a solve slot's residual history holds a non-finite value
+                                (air_state_retire; the slot is still copied out and freed) */
 } air_status;
 
 typedef enum { AIR_PARALLEL = 0, AIR_FAN_FLAT = 1 } air_beam;
@@ -130,9 +131,15 @@ air_status air_plan_tables(air_plan plan, int8_t* axis, int32_t* lo, int32_t* hi
 
 void air_plan_destroy(air_plan plan);
 
-/* y = A x: Joseph projection (ray-driven, linear interpolation along the
- * non-driving axis, times pixel |d| / |d_drive|).  x [batch][n][n] -> y [batch][V][D].
- * 1 <= batch <= max_batch. */
+/* y = A x, the X-ray transform of the AIR data term (Methods, Eq. (1): A maps
+ * the image X to the projections Y; Materials: the forward projector of
+ * ref. [26]), computed as Joseph's ray-driven projector: for each ray, the sum
+ * over its driving axis (x if |d_x| >= |d_y|, else y) of the linear
+ * interpolation between the two nearest pixels of the other axis, times the
+ * step length pixel |d| / |d_drive|.  x [batch][n][n] -> y [batch][V][D], both
+ * device, float32, caller-owned.  1 <= batch <= max_batch; x and y must not
+ * overlap.  Uses the plan's workspace (calls on one plan must be ordered on one
+ * stream). */
 air_status air_project(air_plan plan, const float* x, float* y, int32_t batch, hipStream_t stream);
 
 /* y' = C y, C = kappa D^(1/2) R D^(1/2) per view (the plan's window and
@@ -201,9 +208,11 @@ air_status air_solve_workspace_size(air_plan plan, int32_t batch, size_t* bytes)
  * images, then the rest) on two streams that the plan creates on first use
  * (default priority): they wait on an event recorded on `stream`, and
  * `stream` waits on an event recorded on each, so the call stays ordered on
- * `stream` (and can be captured there).  While kernel timing is enabled the
- * whole batch runs on `stream`.  Results are the same bits either way.  Calls
- * on one plan must come from one host thread at a time. */
+ * `stream` (and can be captured there).  With kernel timing in
+ * AIR_TIMING_ONE_STREAM mode the whole batch runs on `stream`.  Results are
+ * the same bits either way.  Calls on one plan must come from one host thread
+ * at a time.  Non-finite values are not reported by status here (the call is
+ * asynchronous): they show in X and in resid. */
 air_status air_solve(air_plan plan, const float* Y, float* X, int32_t batch, const air_solve_params* p,
                      double* resid, void* ws, size_t ws_bytes, hipStream_t stream);
 
@@ -241,7 +250,10 @@ air_status air_state_step(air_state state, int32_t max_iters, hipStream_t stream
 air_status air_state_query(air_state state, int32_t slot, int32_t* iters_done, int32_t* n_outer);
 air_status air_state_active(air_state state, int32_t* count);
 /* Copy the slot's image (device [n][n], may be NULL) and residual history
- * (device [n_outer] float64 ||W X - d||, may be NULL) out, then free the slot. */
+ * (device [n_outer] float64 ||W X - d||, may be NULL) out, then free the slot.
+ * Synchronises `stream` once, to read the slot's residual history on the host:
+ * if any of its values is not finite (a non-finite input or a diverged solve),
+ * the slot is still copied out and freed, and the call returns AIR_E_NONFINITE. */
 air_status air_state_retire(air_state state, int32_t slot, float* X_out, double* resid_out, hipStream_t stream);
 /* Checkpoint: the slot's whole continuation state (X, g, b, d - b, residual
  * history, iteration count) to a host buffer of air_state_snapshot_size bytes.
@@ -257,7 +269,15 @@ air_status air_state_restore(air_state state, const void* host_buf, hipStream_t 
  * kernel launch that plan makes (operators and air_solve) is bracketed by a
  * pair of HIP events on the launch stream.  air_kernel_timing_collect waits
  * for the recorded events and adds their elapsed times to *stats, then
- * forgets them.  Kinds index air_kernel_stats' arrays. */
+ * forgets them.  Kinds index air_kernel_stats' arrays.  Modes:
+ *   AIR_TIMING_OFF         no events
+ *   AIR_TIMING_ON          events; air_solve keeps its two sub-batch streams, so
+ *                          a kernel's time is measured while it shares the GPU
+ *                          with the other sub-batch's kernels, as in a plain solve
+ *   AIR_TIMING_ONE_STREAM  events, and every air_solve runs on the caller's
+ *                          stream: the times of kernels running alone
+ * Solve slots do not replay captured graphs while timing is on. */
+enum { AIR_TIMING_OFF = 0, AIR_TIMING_ON = 1, AIR_TIMING_ONE_STREAM = 2 };
 typedef enum {
     AIR_K_PROJECT = 0,      /* Joseph forward projector */
     AIR_K_BACKPROJECT = 1,  /* gather-form matched backprojector (all epilogues) */
@@ -271,7 +291,7 @@ typedef struct {
     double ms[AIR_K_COUNT];        /* summed kernel time */
     int64_t launches[AIR_K_COUNT]; /* number of launches */
 } air_kernel_stats;
-air_status air_kernel_timing_enable(air_plan plan, int32_t enable);
+air_status air_kernel_timing_enable(air_plan plan, int32_t mode);
 air_status air_kernel_timing_collect(air_plan plan, air_kernel_stats* stats /* host */);
 
 /* Thread-local message of the last failure on this thread ("" if none). */

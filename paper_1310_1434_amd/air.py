@@ -29,6 +29,16 @@ class AirError(RuntimeError):
         self.status = status
 
 
+class NonFiniteResult(AirError):
+    """AIR_E_NONFINITE from air_state_retire: the slot was copied out and freed,
+    but its residual history holds a non-finite value.  ``x`` and ``resid`` are
+    the copied-out image and history."""
+
+    def __init__(self, where: str, msg: str, x, resid):
+        super().__init__(AIR_E_NONFINITE, where, msg)
+        self.x, self.resid = x, resid
+
+
 class _Geometry(ctypes.Structure):
     _fields_ = [("beam", ctypes.c_int), ("n", ctypes.c_int32), ("pixel_mm", ctypes.c_double),
                 ("n_views", ctypes.c_int32), ("view_cos", ctypes.c_void_p), ("view_sin", ctypes.c_void_p),
@@ -42,6 +52,8 @@ class _SolveParams(ctypes.Structure):
 
 
 KERNEL_KINDS = ("project", "backproject", "ramp", "cg", "framelet", "other")
+# air_kernel_timing_enable modes
+TIMING_MODES = {"off": 0, "on": 1, "one_stream": 2}
 
 
 class _KernelStats(ctypes.Structure):
@@ -139,6 +151,24 @@ def host_tables(geom):
     return axis.reshape(s), lo.reshape(s), hi.reshape(s)
 
 
+def workspace_sizes(geom, capacity: int, lam: float, mu: float, n_cg: int, max_outer: int,
+                    precision: str = "fp32", filter: int = 1) -> tuple[int, int]:
+    """Device bytes of (the workspace of a max_batch = 1 plan of this geometry, a
+    solve-slot state of `capacity` slots on it), from a host-only plan (no GPU)."""
+    g, keep = _geometry_struct(geom)
+    h = ctypes.c_void_p()
+    _check(lib.air_plan_create(ctypes.byref(g), 1, PRECISIONS[precision], 0, ctypes.byref(h)), "air_plan_create")
+    try:
+        ps, ss = ctypes.c_size_t(), ctypes.c_size_t()
+        prm = _SolveParams(float(lam), float(mu), int(max_outer), int(n_cg), 0, int(filter))
+        _check(lib.air_plan_workspace_size(h, ctypes.byref(ps)), "air_plan_workspace_size")
+        _check(lib.air_state_workspace_size(h, int(capacity), ctypes.byref(prm), ctypes.byref(ss)),
+               "air_state_workspace_size")
+    finally:
+        lib.air_plan_destroy(h)
+    return max(int(ps.value), 256), max(int(ss.value), 256)
+
+
 class Plan:
     """A scan geometry with its device tables.
 
@@ -177,8 +207,12 @@ class Plan:
             self._h = None
 
     # ---- per-kernel event timing
-    def kernel_timing(self, enable: bool) -> None:
-        _check(lib.air_kernel_timing_enable(self._h, int(bool(enable))), "air_kernel_timing_enable")
+    def kernel_timing(self, mode) -> None:
+        """mode: "off", "on" (solves keep their two sub-batch streams) or
+        "one_stream" (kernels run alone); True means "on", False "off"."""
+        if isinstance(mode, bool):
+            mode = "on" if mode else "off"
+        _check(lib.air_kernel_timing_enable(self._h, TIMING_MODES[mode]), "air_kernel_timing_enable")
 
     def collect_kernel_timing(self) -> dict:
         """{kind: (total_ms, launches)} for the launches recorded since the last collect."""
@@ -347,14 +381,19 @@ class State:
         return int(it.value), int(no.value)
 
     def retire(self, slot: int):
-        """Copy out (X [n, n], resid [n_outer] float64) and free the slot (asynchronous)."""
+        """Copy out (X [n, n], resid [n_outer] float64) and free the slot (the
+        library synchronises the state's stream once).  Raises NonFiniteResult,
+        which carries both, if the residual history holds a non-finite value."""
         _, n_outer = self.query(slot)
         p = self.plan
         with torch.cuda.stream(self._torch_stream()):
             x = torch.empty((p.n, p.n), device=p.device)
             r = torch.empty((n_outer,), dtype=torch.float64, device=p.device)
-        _check(lib.air_state_retire(self._h, int(slot), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(r.data_ptr()),
-                                    self._s()), "air_state_retire")
+        st = lib.air_state_retire(self._h, int(slot), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(r.data_ptr()),
+                                  self._s())
+        if st == AIR_E_NONFINITE:
+            raise NonFiniteResult("air_state_retire", lib.air_last_error().decode(), x, r)
+        _check(st, "air_state_retire")
         return x, r
 
     def snapshot(self, slot: int) -> np.ndarray:

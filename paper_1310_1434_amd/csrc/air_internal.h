@@ -57,6 +57,10 @@ int pad_group(int batch);
 // two chosen from max |x| (so the largest value lands in [2^13, 2^14)).  The
 // projector multiplies its float32 sums by 1 / scale[b], exactly.
 int pad_group16(int batch);
+// Images the grouped buffers (padded copies, backprojector input) must hold for
+// any batch up to max_batch: the kernels write whole groups, so the last group's
+// idle lanes need room too.
+int group_images(int max_batch);
 struct PadBuf {
     float* base = nullptr;           // float32 copies, or
     uint16_t* half = nullptr;        // float16 copies (when set)

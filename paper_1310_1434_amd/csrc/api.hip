@@ -212,9 +212,10 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
         if (!p->tab16.empty()) p->off_tab16 = c.take(p->tab16.size() * sizeof(uint16_t));
         if (p->cos_weight) p->off_wsq = c.take(p->wsq.size() * sizeof(float));
         const size_t mb = (size_t)max_batch;
-        p->off_pad = c.take((mb + 7) / 8 * 8 * 2 * g.n * p->line * sizeof(float));   // grouped padded copies
+        const size_t gi = (size_t)group_images(max_batch);
+        p->off_pad = c.take(gi * 2 * g.n * p->line * sizeof(float));   // grouped padded copies
         p->off_s1 = c.take(mb * g.n_views * ds * sizeof(float));
-        p->off_s2 = c.take((mb + 15) / 16 * 16 * g.n_views * ds * sizeof(float));   // group-interleaved, <= roundup(batch, 16) images
+        p->off_s2 = c.take(gi * g.n_views * ds * sizeof(float));       // group-interleaved backprojector input
         p->off_pscale = c.take((mb + 63) / 64 * 64 * sizeof(float));
         p->off_ppart = c.take(mb * (size_t)tiles16(g.n) * sizeof(double));
         p->total = c.off;
@@ -357,7 +358,9 @@ air_status air_normal_apply(air_plan p, const float* x, float* out, int32_t batc
 
 air_status air_kernel_timing_enable(air_plan p, int32_t enable) {
     if (air_status st = check_plan(p, false)) return st;
-    p->timing = enable != 0;
+    if (enable != AIR_TIMING_OFF && enable != AIR_TIMING_ON && enable != AIR_TIMING_ONE_STREAM)
+        return fail(AIR_E_INVALID, "timing mode must be 0, 1 or 2");
+    p->timing = enable;
     return AIR_OK;
 }
 
@@ -399,10 +402,12 @@ extern "C" {
 // overlap the other's backprojections (bound by VALU and LDS).  Measured at
 // C2: 16 images as 2 x 8 run at 1.10x the throughput of one 16-image batch,
 // 32 as 2 x 16 at 1.19x two 16-image batches in turn; every image gets the
-// same bits either way.  Kernel timing keeps one
-// stream, so the per-kernel times are those of kernels running alone.
+// same bits either way.  Kernel timing in AIR_TIMING_ONE_STREAM mode keeps
+// one stream, so the per-kernel times are those of kernels running alone.
 constexpr int kSplitMin = 8;
-static int solve_parts(const air_plan_s* p, int batch) { return batch >= kSplitMin && !p->timing ? 2 : 1; }
+static int solve_parts(const air_plan_s* p, int batch) {
+    return batch >= kSplitMin && p->timing != AIR_TIMING_ONE_STREAM ? 2 : 1;
+}
 static int part_size(int batch, int parts, int i) { return parts == 1 ? batch : (i == 0 ? (batch + 1) / 2 : batch / 2); }
 static size_t part_offset(const air_plan_s* p, int batch, int parts, int i) {
     return i == 0 ? 0 : (solve_layout(p, part_size(batch, parts, 0)).total + 255) / 256 * 256;
@@ -411,7 +416,7 @@ static size_t solve_bytes(const air_plan_s* p, int batch) {
     size_t one = solve_layout(p, batch).total;
     if (batch < kSplitMin) return one;
     const size_t two = part_offset(p, batch, 2, 1) + solve_layout(p, part_size(batch, 2, 1)).total;
-    return std::max(one, two);    // (kernel timing may choose one part)
+    return std::max(one, two);    // (one-stream kernel timing runs one part)
 }
 
 air_status air_solve_workspace_size(air_plan p, int32_t batch, size_t* bytes) {

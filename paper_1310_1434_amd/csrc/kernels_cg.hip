@@ -6,7 +6,7 @@
 // k_finalize adds them in index order (one block per batch item) and derives
 // alpha or beta, so every batch item gets the same bits whatever the batch
 // size, and no atomics are used.  Scalars never leave the device.
-#include "common.cuh"
+#include "common.h"
 
 namespace air {
 

@@ -9,7 +9,7 @@
 // detector bins of one view; at each driving step they all read the same line
 // at nearby positions, so the gathers are coalesced, one gather serves every
 // image of the group, and no bounds test is needed in the inner loop.
-#include "common.cuh"
+#include "common.h"
 
 namespace air {
 
@@ -29,6 +29,15 @@ int image_group(int batch) {
 
 int pad_group(int batch) { return batch >= 2 ? 2 : 1; }
 int pad_group16(int batch) { return batch >= 3 ? 4 : batch; }
+
+int group_images(int max_batch) {
+    int most = 0;
+    for (int b = 1; b <= max_batch; b++) {
+        const int g = std::max(image_group(b), std::max(pad_group(b), pad_group16(b)));
+        most = std::max(most, (b + g - 1) / g * g);
+    }
+    return most;
+}
 
 // ---------------------------------------------------------------------------- padded copies
 template <int P>

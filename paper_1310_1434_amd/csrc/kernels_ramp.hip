@@ -18,7 +18,7 @@
 // long as both operands agree; it is chosen so that each lane reads
 // contiguous sinogram values (one 16-byte load per lane per 16 k for f32,
 // two per 32 k for the 16-bit kernels).
-#include "common.cuh"
+#include "common.h"
 
 namespace air {
 

@@ -64,7 +64,7 @@ struct air_plan_s {
         int kind;
         hipEvent_t a, b;
     };
-    bool timing = false;
+    int timing = AIR_TIMING_OFF;   // air_kernel_timing_mode
     std::vector<Timed> pending;
     std::vector<hipEvent_t> pool;
     // air_solve's concurrent sub-batches: the events that fork the device's

@@ -10,10 +10,11 @@ SolveLayout solve_layout(const air_plan_s* p, int batch) {
     const size_t B = (size_t)batch, n = (size_t)p->g.n, np = n * n;
     Carver c;
     SolveLayout L;
-    L.pad = c.take((B + 7) / 8 * 8 * 2 * n * p->line * sizeof(float));   // grouped padded copies
+    const size_t gi = (size_t)group_images(batch);     // (solve slots run any batch up to their capacity)
+    L.pad = c.take(gi * 2 * n * p->line * sizeof(float));   // grouped padded copies
     L.pscale = c.take((B + 63) / 64 * 64 * sizeof(float));
     L.s1 = c.take(B * p->g.n_views * p->ds * sizeof(float));
-    L.s2 = c.take((B + 15) / 16 * 16 * p->g.n_views * p->ds * sizeof(float));   // group-interleaved backprojector input
+    L.s2 = c.take(gi * p->g.n_views * p->ds * sizeof(float));   // group-interleaved backprojector input
     L.g = c.take(B * np * sizeof(float));
     L.r = c.take(B * np * sizeof(float));
     L.p = c.take(B * np * sizeof(float));

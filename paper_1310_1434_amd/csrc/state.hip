@@ -276,9 +276,17 @@ air_status air_state_retire(air_state st, int32_t slot, float* X_out, double* re
     if (air_status e = check_slot(st, slot)) return e;
     const int pos = st->pos_of[slot];
     const SolveBufs b = st->at(pos);
+    const int n_out = st->n_outer[slot];
+    std::vector<double> hist;
+    try {
+        hist.assign(n_out, 0.0);
+    } catch (const std::bad_alloc&) {
+        return fail(AIR_E_NOMEM, "host allocation failed");
+    }
+    // the history is read before the slot's position can be reused below
+    AIR_HIP(hipMemcpyAsync(hist.data(), b.resid, n_out * sizeof(double), hipMemcpyDeviceToHost, s));
     if (X_out) AIR_HIP(hipMemcpyAsync(X_out, b.X, st->np() * sizeof(float), hipMemcpyDeviceToDevice, s));
-    if (resid_out)
-        AIR_HIP(hipMemcpyAsync(resid_out, b.resid, st->n_outer[slot] * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (resid_out) AIR_HIP(hipMemcpyAsync(resid_out, b.resid, n_out * sizeof(double), hipMemcpyDeviceToDevice, s));
     const int last = st->nact - 1;
     if (pos != last) {
         if (air_status e = move_slot(st, last, pos, s)) return e;
@@ -289,6 +297,11 @@ air_status air_state_retire(air_state st, int32_t slot, float* X_out, double* re
     st->slot_at[last] = -1;
     st->pos_of[slot] = -1;
     st->nact--;
+    AIR_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < n_out; k++)
+        if (!std::isfinite(hist[k]))
+            return fail(AIR_E_NONFINITE, "the slot's residual history holds a non-finite value (iteration " +
+                                             std::to_string(k) + ")");
     return AIR_OK;
 }
 

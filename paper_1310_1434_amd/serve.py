@@ -9,8 +9,9 @@ every request is done:
      their iteration count are copied out and freed;
   2. admit: pending requests that have arrived are admitted first come, first
      served into a free slot of their group; a group is opened when the HBM
-     budget allows (idle empty groups are closed to make room); a request whose
-     group could never fit the budget is rejected;
+     budget allows (idle empty groups are closed, and then plans without a group
+     dropped, to make room); a request whose group could never fit the budget is
+     rejected;
   3. step: every group with active slots whose previous step has completed
      advances one Bregman iteration (one replay of its captured graph).
 
@@ -18,6 +19,11 @@ So a request that arrives while others are on the GPU joins at the next step
 of its group, and finished ones leave without waiting for the rest.  The
 executor abstraction lets the same scheduler run on the GPU (GpuExecutor) or
 on a simulated clock (tests).
+
+HBM accounting: a group's slot state is charged while the group is open; a
+geometry's plan (tables and operator scratch) is charged once, from its
+creation until it is dropped, since it outlives the groups that use it.  The
+tracked total equals the device bytes the executor holds.
 """
 from __future__ import annotations
 
@@ -65,7 +71,8 @@ class Group:
 
 
 class GpuExecutor:
-    """Groups on the GPU: a Plan, a State of `capacity` slots and a stream each."""
+    """Groups on the GPU: a State of `capacity` slots and a stream each, over
+    one Plan per geometry (kept from its first use until dropped)."""
 
     def __init__(self, lam: float, mu: float, n_cg: int, max_outer: int, capacity: int,
                  precision: str = "fp32", device: str = "cuda:0"):
@@ -75,21 +82,37 @@ class GpuExecutor:
         self.lam, self.mu, self.n_cg, self.max_outer = lam, mu, n_cg, max_outer
         self.capacity, self.precision, self.device = capacity, precision, device
         self._plans = {}
+        self._sizes = {}
+
+    def _sizes_of(self, key, geom):
+        if key not in self._sizes:
+            self._sizes[key] = self.air.workspace_sizes(geom, self.capacity, self.lam, self.mu, self.n_cg,
+                                                        self.max_outer, precision=self.precision)
+        return self._sizes[key]
 
     def plan(self, key, geom):
         if key not in self._plans:
+            self._sizes_of(key, geom)
             self._plans[key] = self.air.Plan(geom, max_batch=1, precision=self.precision, device=self.device)
         return self._plans[key]
 
     def group_bytes(self, key, geom) -> int:
-        """Device bytes of a group: its slot state plus its plan's tables and scratch."""
-        import ctypes
-        p = self.plan(key, geom)
-        prm = self.air._SolveParams(self.lam, self.mu, self.max_outer, self.n_cg, 0, 1)
-        size = ctypes.c_size_t()
-        self.air._check(self.air.lib.air_state_workspace_size(p._h, self.capacity, ctypes.byref(prm),
-                                                               ctypes.byref(size)), "air_state_workspace_size")
-        return int(size.value) + p._ws.numel()
+        """Device bytes of a group's slot state (its plan is charged separately)."""
+        return self._sizes_of(key, geom)[1]
+
+    def plan_bytes(self, key, geom) -> int:
+        """Device bytes of the geometry's plan (tables and operator scratch)."""
+        return self._sizes_of(key, geom)[0]
+
+    def plan_resident(self, key) -> bool:
+        return key in self._plans
+
+    def drop_plan(self, key):
+        self._plans.pop(key, None)
+
+    def resident_bytes(self) -> int:
+        """Device bytes of the plans already built (e.g. ahead of a run)."""
+        return sum(self._sizes[k][0] for k in self._plans)
 
     def open(self, group: Group):
         stream = self.torch.cuda.Stream(device=self.device)
@@ -122,12 +145,14 @@ class GpuExecutor:
         return group.impl["state"].query(slot)
 
     def retire(self, group: Group, slot: int, req: Request):
-        x, r = group.impl["state"].retire(slot)
+        try:
+            x, r = group.impl["state"].retire(slot)
+        except self.air.NonFiniteResult as e:      # AIR_E_NONFINITE: copied out and freed
+            x, r = e.x, e.resid
+            req.error = "non-finite residual"
         group.impl["stream"].synchronize()
         req.x = x.cpu().numpy()
         req.resid = r.cpu().numpy()
-        if not np.isfinite(req.resid).all():
-            req.error = "non-finite residual"
 
 
 class Server:
@@ -139,23 +164,35 @@ class Server:
         self.groups: dict[tuple, Group] = {}
         self.pending: deque[Request] = deque()
         self.done: list[Request] = []
-        self.used = 0
+        self.used = executor.resident_bytes()      # plans built ahead of the run
+        self.plans: dict[tuple, int] = {}           # resident plan -> its bytes (built by this server)
         self.steps = 0
 
     # ---------------------------------------------------------------- helpers
+    def _fits_ever(self, key, geom) -> bool:
+        return self.ex.group_bytes(key, geom) + self.ex.plan_bytes(key, geom) <= self.budget
+
     def _open(self, key, geom) -> Group | None:
         nbytes = self.ex.group_bytes(key, geom)
-        if nbytes > self.budget:
+        pbytes = 0 if self.ex.plan_resident(key) else self.ex.plan_bytes(key, geom)
+        if nbytes + pbytes > self.budget:
             return None
-        while self.used + nbytes > self.budget:
+        while self.used + nbytes + pbytes > self.budget:
             idle = [g for g in self.groups.values() if not g.slots and self.ex.idle(g)]
-            if not idle:
+            if idle:
+                self._close(idle[0])
+                continue
+            spare = [k for k in self.plans if k not in self.groups and k != key]
+            if not spare:
                 return None
-            self._close(idle[0])
+            self.ex.drop_plan(spare[0])
+            self.used -= self.plans.pop(spare[0])
         g = Group(key, geom, self.capacity, nbytes)
         self.ex.open(g)
         self.groups[key] = g
-        self.used += nbytes
+        self.used += nbytes + pbytes
+        if pbytes:
+            self.plans[key] = pbytes
         return g
 
     def _close(self, g: Group):
@@ -188,7 +225,7 @@ class Server:
                 continue
             g = self.groups.get(key)
             if g is None:
-                if self.ex.group_bytes(key, req.geom) > self.budget:
+                if not self._fits_ever(key, req.geom):
                     req.error = "does not fit the HBM budget"
                     self.pending.remove(req)
                     self.done.append(req)
@@ -228,14 +265,18 @@ class Server:
 
 class FakeExecutor:
     """Simulated executor for scheduler tests: a step of a group with k active
-    slots takes step_cost(group, k) seconds of a simulated clock."""
+    slots takes step_cost(group, k) seconds of a simulated clock.  `held` is
+    the memory it would hold: open groups' states plus resident plans."""
 
-    def __init__(self, bytes_per_group, step_cost):
+    def __init__(self, bytes_per_group, step_cost, bytes_per_plan=lambda geom: 0):
         self.bytes_per_group = bytes_per_group
+        self.bytes_per_plan = bytes_per_plan
         self.step_cost = step_cost
         self.now = 0.0
         self.opened = []
         self.log = []
+        self.plans = {}
+        self.held = 0
 
     def clock(self):
         return self.now
@@ -246,12 +287,30 @@ class FakeExecutor:
     def group_bytes(self, key, geom):
         return self.bytes_per_group(geom)
 
+    def plan_bytes(self, key, geom):
+        return self.bytes_per_plan(geom)
+
+    def plan_resident(self, key):
+        return key in self.plans
+
+    def drop_plan(self, key):
+        self.held -= self.plans.pop(key)
+        self.log.append(("drop_plan", key))
+
+    def resident_bytes(self):
+        return sum(self.plans.values())
+
     def open(self, g):
+        if g.key not in self.plans:
+            self.plans[g.key] = self.bytes_per_plan(g.geom)
+            self.held += self.plans[g.key]
+        self.held += self.bytes_per_group(g.geom)
         g.impl = {"busy_until": 0.0, "iters": {}, "next": 0}
         self.opened.append(g.key)
 
     def close(self, g):
         self.log.append(("close", g.key))
+        self.held -= self.bytes_per_group(g.geom)
         g.impl = None
 
     def admit(self, g, req):

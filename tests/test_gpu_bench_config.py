@@ -1,0 +1,68 @@
+"""GPU parity of the configuration the benchmark times: sixteen 512^2 fan-beam
+cases (720 views x 736 bins, split Bregman 50 x 5 CG) in one air_solve call,
+which runs them as two 8-image sub-batches on two streams (the 8-image
+backprojector groups and the image-pair forward projector).
+
+Seed 0's sinogram sits in slot 0 (first image of the first sub-batch) and
+slot 15 (last image of the second), other seeds elsewhere.  Both copies of seed 0 are compared with the
+stored FP64 oracle reconstruction (tests/golden/make_refs.py): relative L2
+1e-4 on the float32 path, 1e-3 on the mixed path.  Every other slot must be
+the same bits as its solve alone (batch 1: one stream, single-image kernels).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+BATCH = 16
+SEEDS = [0] + [1 + (b - 1) % 5 for b in range(1, BATCH - 1)] + [0]
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+@pytest.fixture(scope="module")
+def c2_batch():
+    import torch
+    assert torch.cuda.is_available()
+    w = synth.workload("c2")
+    cases = {s: synth.make_case(w, s)["y"].astype(np.float32) for s in sorted(set(SEEDS))}
+    ys = np.stack([cases[s] for s in SEEDS])
+    return torch, w, ys
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("mixed_f16", 1e-3)])
+def test_benched_c2_batch16_two_streams(c2_batch, record, prec, tol):
+    torch, w, ys = c2_batch
+    from paper_1310_1434_amd import air
+    ref = np.load(os.path.join(HERE, "golden", "c2_fan_512_720_seed0.npz"))
+    plan = air.Plan(w.geom, max_batch=BATCH, precision=prec)
+    print(f"C2 batch {BATCH} two-stream solve, {prec}", flush=True)
+    x, resid = plan.solve(torch.from_numpy(ys).cuda(), w.lam, w.mu, w.n_outer, w.n_cg)
+    torch.cuda.synchronize()
+    xb = x.cpu().numpy()
+    rb = resid.cpu().numpy()
+    for b in (0, BATCH - 1):
+        e = rel(xb[b], ref["x"])
+        record(f"rel_l2_final_c2_b16_{prec}_slot{b}", e)
+        assert e < tol, (b, e)
+        np.testing.assert_allclose(rb[b], ref["resid"], rtol=1e-2 if prec == "fp32" else 5e-2)
+    assert np.array_equal(xb[0], xb[BATCH - 1])          # the two sub-batches give seed 0 the same bits
+    solo = air.Plan(w.geom, max_batch=1, precision=prec)
+    done = {}
+    for b in range(1, BATCH - 1):
+        s = SEEDS[b]
+        if s not in done:
+            x1, r1 = solo.solve(torch.from_numpy(ys[b:b + 1]).cuda(), w.lam, w.mu, w.n_outer, w.n_cg)
+            torch.cuda.synchronize()
+            done[s] = (x1[0].cpu().numpy(), r1[0].cpu().numpy())
+        assert np.array_equal(done[s][0], xb[b]), (prec, b)
+        assert np.array_equal(done[s][1], rb[b]), (prec, b)

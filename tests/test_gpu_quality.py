@@ -77,3 +77,44 @@ def test_arms_match_oracle_and_measures_agree(arms, cases, orc, record):
             else:
                 for tg, tr in zip(Q.target_cnrs(gpu[arm][b], ph, GEOM.pixel), Q.target_cnrs(ref[arm], ph, GEOM.pixel)):
                     assert math.isclose(tg["cnr"], tr["cnr"], rel_tol=1e-3), (arm, tg, tr)
+
+
+# ----------------------------------------------------------------------------- the paper-shaped scan
+
+@pytest.fixture(scope="module")
+def paper_scans():
+    """The paper-shaped scan (Materials: 350 x 350 at 1 mm, 528 detector
+    pixels, 800 views, and its 25% subset of 200 views) of the resolution
+    phantom, with Poisson noise at I0 = 2e4."""
+    ph = SQ.resolution_phantom()
+    full = SQ.make_quality_case(ph, SQ.paper_geometry(1), 2e4, 21)
+    return ph, {1: (SQ.paper_geometry(1), full["y"], full["x_true"]),
+                4: (SQ.paper_geometry(4), full["y"][::4].copy(), full["x_true"])}
+
+
+@pytest.mark.parametrize("step", [1, 4], ids=["800_views", "200_views"])
+def test_paper_scan_operators_and_solve(paper_scans, orc, record, step):
+    """A, A'^T = A^T C and a 5 x 5 split-Bregman solve on the paper-shaped scan
+    against the FP64 oracle: 1e-5 per operator apply, 1e-4 on the image."""
+    import torch
+    from paper_1310_1434_amd import air
+    _, scans = paper_scans
+    g, y, x_true = scans[step]
+    print(f"paper-shaped scan, {g.n_views} views", flush=True)
+    G = orc.Geom(g)
+    plan = air.Plan(g, max_batch=1)
+    x32 = x_true.astype(np.float32)
+    yp = plan.project(torch.from_numpy(x32[None]).cuda())[0].cpu().numpy().astype(np.float64)
+    e_a = rel(yp, orc.project(G, x32.astype(np.float64)))
+    y32 = y.astype(np.float32)
+    Y = torch.from_numpy(y32[None]).cuda()
+    xb = plan.filtered_backproject(Y, 1)[0].cpu().numpy().astype(np.float64)
+    e_atc = rel(xb, orc.filtered_backproject(G, y32.astype(np.float64), 1))
+    xs, _ = plan.solve(Y, LAM, MU, 5, 5, with_resid=False)
+    xr, _ = orc.solve(G, y32.astype(np.float64), LAM, MU, 5, 5)
+    e_x = rel(xs[0].cpu().numpy().astype(np.float64), xr)
+    record(f"rel_l2_A_paper_{g.n_views}", e_a)
+    record(f"rel_l2_AtC_paper_{g.n_views}", e_atc)
+    record(f"rel_l2_final_paper_{g.n_views}_5x5", e_x)
+    assert e_a < 1e-5 and e_atc < 1e-5, (e_a, e_atc)
+    assert e_x < 1e-4, e_x

@@ -1,6 +1,7 @@
 """GPU serving: requests of two geometries arriving over time are served by the
-continuous-batching loop, and every result is bit-identical to solving that
-request alone."""
+continuous-batching loop; every result is bit-identical to solving that
+request alone, and the C1-geometry results match the FP64 oracle's
+reconstruction with the same iteration counts (relative L2 1e-4)."""
 import numpy as np
 import pytest
 
@@ -10,7 +11,7 @@ from synth.configs import Geometry
 pytestmark = pytest.mark.gpu
 
 
-def test_served_results_equal_solo_solves():
+def test_served_results_equal_solo_solves(orc, record):
     import torch
     from paper_1310_1434_amd import air
     from paper_1310_1434_amd.serve import GpuExecutor, Request, Server, latency_stats
@@ -42,3 +43,9 @@ def test_served_results_equal_solo_solves():
         torch.cuda.synchronize()
         assert np.array_equal(x[0].cpu().numpy(), r.x), r.rid
         assert np.array_equal(res[0].cpu().numpy(), r.resid), r.rid
+        if r.geom is g1:
+            xr, rr = orc.solve(orc.Geom(g1), r.y.astype(np.float64), lam, mu, r.n_outer, n_cg)
+            e = float(np.linalg.norm(r.x.astype(np.float64) - xr) / np.linalg.norm(xr))
+            record(f"rel_l2_served_c1_req{r.rid}", e)
+            assert e < 1e-4, (r.rid, e)
+            np.testing.assert_allclose(r.resid, rr, rtol=1e-3)

@@ -94,6 +94,9 @@ def test_snapshot_resume_is_exact(env):
 
 
 def test_nonfinite_slot_is_isolated(env):
+    """A slot whose sinogram holds a NaN: air_state_retire reports
+    AIR_E_NONFINITE (and still copies it out and frees it); the other slot is
+    untouched and retires with AIR_OK."""
     torch, air, plan, ys = env
     bad = ys[1].clone()
     bad[7, 11] = float("nan")
@@ -101,7 +104,11 @@ def test_nonfinite_slot_is_isolated(env):
     g = st.admit(ys[0], n_outer=3)
     b = st.admit(bad, n_outer=3)
     st.step(3)
-    xb, rb = finish(st, b)
+    with pytest.raises(air.NonFiniteResult) as e:
+        st.retire(b)
+    assert e.value.status == air.AIR_E_NONFINITE
+    rb = e.value.resid.cpu().numpy()
+    assert st.active == 1
     xg, rg = finish(st, g)
     assert not np.isfinite(rb).all()
     xs, rs = solo(env, ys[0], 3)

@@ -353,6 +353,28 @@ def test_cg_converges_to_dense_cholesky(orc):
     assert np.abs(M - M.T).max() < 1e-13 * np.abs(M).max()
 
 
+def test_eq5_cg_matches_dense_cholesky_32x32(orc):
+    """The stated pin size: 32 x 32 image, parallel beam, 48 views over [0, pi),
+    47 bins of 1 mm, lambda = 0.005.  CG run until its residual norm squared
+    falls below 1e-26 equals the Cholesky solve of the dense
+    (A^T C A + lambda I) X = A^T C Y to 1e-10."""
+    geo, g, y = _small_problem(orc, n=32, views=48, bins=47, seed=17)
+    lam = 0.005
+    M = _dense(orc, g, geo.n, lam)
+    rhs = orc.filtered_backproject(g, y, 1).ravel()
+    ref = scipy.linalg.cho_solve(scipy.linalg.cho_factor(M), rhs)
+    n_cg = 0
+    x = np.zeros(geo.n * geo.n)
+    while True:
+        n_cg += 200
+        x, _ = orc.solve(g, y, lam, 1.0, 0, n_cg, reg=1)
+        r = rhs - M @ x.ravel()
+        if float(r @ r) < 1e-26 or n_cg >= 4000:
+            break
+    assert float(r @ r) < 1e-26, (n_cg, float(r @ r))
+    assert np.linalg.norm(x.ravel() - ref) < 1e-10 * np.linalg.norm(ref)
+
+
 def test_cg_iterates_minimise_over_krylov_space(orc):
     """After n CG steps from x0, x_n minimises the M-norm error over x0 + K_n(M, r0)."""
     geo, g, y = _small_problem(orc, n=16, views=24, bins=25)

@@ -83,3 +83,41 @@ def test_latency_stats_and_arrivals():
     reqs = [make(i, G1, 2, float(t[i])) for i in range(20)]
     st = latency_stats(srv.run(reqs))
     assert st["count"] == 20 and 0 < st["p50_s"] <= st["p99_s"] <= st["max_s"]
+
+
+def test_tracked_bytes_equal_bytes_held():
+    """A geometry's plan is charged once, from its creation until it is dropped;
+    a group's state while the group is open.  After every pass of the loop the
+    server's figure equals what the executor holds, also while groups close and
+    plans are dropped to make room."""
+    G3 = Geo(40, 24)
+    ex = FakeExecutor(lambda g: 4, lambda g, k: 0.01, bytes_per_plan=lambda g: 1)
+    srv = Server(ex, 6, 2, clock=ex.clock, sleep=ex.sleep)
+    seen = []
+    poll = srv.poll
+
+    def checked(now):
+        busy = poll(now)
+        assert srv.used == ex.held <= srv.budget
+        seen.append(srv.used)
+        return busy
+
+    srv.poll = checked
+    reqs = [make(0, G1, 2, 0.0), make(1, G2, 2, 0.001), make(2, G3, 2, 0.002), make(3, G1, 2, 0.003)]
+    done = srv.run(reqs)
+    assert all(r.error is None for r in done)
+    assert any(e[0] == "drop_plan" for e in ex.log)      # 4 (state) + 1 (plan) + 1 (other plan) > 6
+    assert max(seen) <= 6
+
+
+def test_nonfinite_result_is_reported_and_does_not_stop_the_loop():
+    class Bad(FakeExecutor):
+        def retire(self, g, slot, req):
+            super().retire(g, slot, req)
+            if req.rid == 1:
+                req.error = "non-finite residual"
+    ex = Bad(lambda g: 1, lambda g, k: 0.01)
+    srv = Server(ex, 10, 2, clock=ex.clock, sleep=ex.sleep)
+    done = srv.run([make(i, G1, 2, 0.0) for i in range(3)])
+    assert [r.error for r in done] == [None, "non-finite residual", None]
+    assert latency_stats(done)["count"] == 2
