@@ -216,6 +216,25 @@ air_status air_solve_workspace_size(air_plan plan, int32_t batch, size_t* bytes)
 air_status air_solve(air_plan plan, const float* Y, float* X, int32_t batch, const air_solve_params* p,
                      double* resid, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* air_solve for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): no workspace
+ * argument, and nothing is allocated (with kernel timing off).  The solve's
+ * scratch is a static device array of AIR_NOALLOC_SCRATCH_BYTES in the library,
+ * one copy per GPU, held from the library's load on that GPU until the process
+ * ends.  The whole batch runs on `stream` (no sub-batch streams, so none is
+ * created), with the same kernels as air_solve and the same results, bit for
+ * bit.  Every value the solve reads from the scratch it has written first in
+ * the same call, so the previous call's contents never matter.
+ * Errors: as air_solve, and AIR_E_NOMEM (before any GPU work) if the batch needs
+ * more scratch than AIR_NOALLOC_SCRATCH_BYTES (at 512 x 512 with 720 views x 736
+ * bins, about 27 MB per image: batches of up to 9).  All calls on one GPU share
+ * its copy of the array:
+ * calls that overlap on one GPU (different streams or threads without ordering
+ * between them) race and corrupt each other's results; order them on one stream. */
+#define AIR_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+air_status air_solve_noalloc(air_plan plan, const float* Y, float* X, int32_t batch, const air_solve_params* p,
+                             double* resid, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------------
  * Solve slots (continuous batching).  A state holds up to `capacity` split-Bregman
  * reconstructions of one plan's geometry, each with its own sinogram, start image

@@ -76,6 +76,7 @@ SIGNATURES = {
     "air_framelet": ([_P, _P, _P, _I, _I, _P], ctypes.c_int),
     "air_solve_workspace_size": ([_P, _I, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "air_solve": ([_P, _P, _P, _I, ctypes.POINTER(_SolveParams), _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "air_solve_noalloc": ([_P, _P, _P, _I, ctypes.POINTER(_SolveParams), _P, _P], ctypes.c_int),
     "air_state_workspace_size": ([_P, _I, ctypes.POINTER(_SolveParams), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "air_state_create": ([_P, _I, ctypes.POINTER(_SolveParams), _P, ctypes.c_size_t, ctypes.POINTER(_P)], ctypes.c_int),
     "air_state_destroy": ([_P], None),
@@ -307,6 +308,21 @@ class Plan:
         if resid is not None:
             resid = resid[:, :n_outer]
         return x, resid
+
+    def solve_noalloc(self, y: torch.Tensor, x: torch.Tensor, lam: float, mu: float, n_outer: int, n_cg: int,
+                      reg: int = 0, filter: int = 1, resid: torch.Tensor | None = None) -> None:
+        """air_solve_noalloc: the solve with the library's static scratch, on the
+        current stream; x [B, n, n] holds the start image and receives the
+        result, resid (float64 [B, n_outer], optional) the residual history.
+        Nothing is allocated here either: the caller passes every tensor."""
+        b = y.shape[0]
+        if resid is not None and (resid.dtype != torch.float64 or tuple(resid.shape) != (b, max(n_outer, 1))
+                                  or resid.device != self.device or not resid.is_contiguous()):
+            raise ValueError("resid must be a contiguous float64 tensor [batch, n_outer] on the plan's device")
+        p = _SolveParams(float(lam), float(mu), int(n_outer), int(n_cg), int(reg), int(filter))
+        _check(lib.air_solve_noalloc(self._h, self._sino(y), self._img(x), b, ctypes.byref(p),
+                                     ctypes.c_void_p(resid.data_ptr()) if resid is not None else None,
+                                     _stream(self.device)), "air_solve_noalloc")
 
 
 class State:

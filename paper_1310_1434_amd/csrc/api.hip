@@ -468,20 +468,21 @@ static air_status part_begin(air_plan p, const float* Y, float* X, int b0, int n
     return solve_init(p, B, Y + b0 * nyv, nb, solve_setup(prm), s);
 }
 
-air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const air_solve_params* prm,
-                     double* resid, void* ws, size_t ws_bytes, hipStream_t s) {
+static air_status check_solve(air_plan p, const float* Y, float* X, int32_t batch, const air_solve_params* prm) {
     if (air_status st = check_plan(p, true)) return st;
     if (air_status st = check_batch(p, batch, false)) return st;
-    if (!Y || !X || !prm || !ws) return fail(AIR_E_INVALID, "null pointer");
-    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(AIR_E_INVALID, "workspace must be 256-byte aligned");
+    if (!Y || !X || !prm) return fail(AIR_E_INVALID, "null pointer");
     if (prm->reg < 0 || prm->reg > 2) return fail(AIR_E_INVALID, "reg must be 0, 1 or 2");
     if (prm->filter != 0 && prm->filter != 1) return fail(AIR_E_INVALID, "filter must be 0 or 1");
     if (!(prm->lambda >= 0.0) || !std::isfinite(prm->lambda)) return fail(AIR_E_INVALID, "lambda must be >= 0");
     if (prm->reg != 1 && (!(prm->mu > 0.0) || !std::isfinite(prm->mu))) return fail(AIR_E_INVALID, "mu must be > 0");
     if (prm->n_outer < 0 || prm->n_cg < 0) return fail(AIR_E_INVALID, "iteration counts must be >= 0");
-    if (ws_bytes < solve_bytes(p, batch)) return fail(AIR_E_NOMEM, "workspace smaller than air_solve_workspace_size");
-    char* w = static_cast<char*>(ws);
-    const int parts = solve_parts(p, batch);
+    return AIR_OK;
+}
+
+// The solve on workspace w (checked by the caller), as `parts` sub-batches.
+static air_status solve_run(air_plan p, const float* Y, float* X, int32_t batch, const air_solve_params* prm,
+                            double* resid, char* w, int parts, hipStream_t s) {
     if (parts == 1) {
         SolveBufs B;
         if (air_status st = part_begin(p, Y, X, 0, batch, prm, resid, w, s, B)) return st;
@@ -521,4 +522,55 @@ air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const 
     return result;
 }
 
+air_status air_solve(air_plan p, const float* Y, float* X, int32_t batch, const air_solve_params* prm,
+                     double* resid, void* ws, size_t ws_bytes, hipStream_t s) {
+    if (air_status st = check_solve(p, Y, X, batch, prm)) return st;
+    if (!ws) return fail(AIR_E_INVALID, "null pointer");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(AIR_E_INVALID, "workspace must be 256-byte aligned");
+    if (ws_bytes < solve_bytes(p, batch)) return fail(AIR_E_NOMEM, "workspace smaller than air_solve_workspace_size");
+    return solve_run(p, Y, X, batch, prm, resid, static_cast<char*>(ws), solve_parts(p, batch), s);
+}
+
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// air_solve_noalloc: the solve's scratch in a file-scope device array, one copy per
+// GPU (the runtime places it when it loads the library's code on that GPU).
+namespace {
+
+__device__ __align__(256) static unsigned char scratch[AIR_NOALLOC_SCRATCH_BYTES];
+
+// Device address of the current GPU's copy of `scratch`, looked up once per
+// device with that device current.  On the host, `scratch` names a host-side
+// stand-in: only these addresses may reach a kernel or a copy.
+air_status scratch_address(char** out) {
+    static std::mutex mu;
+    static char* addr[64] = {};
+    int dev = 0;
+    AIR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(AIR_E_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* a = nullptr;
+        AIR_HIP(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+        if (!a) return fail(AIR_E_HIP, "hipGetSymbolAddress returned no address for the static scratch");
+        addr[dev] = static_cast<char*>(a);
+    }
+    *out = addr[dev];
+    return AIR_OK;
+}
+
+}  // namespace
+
+extern "C" air_status air_solve_noalloc(air_plan p, const float* Y, float* X, int32_t batch,
+                                        const air_solve_params* prm, double* resid, hipStream_t s) {
+    if (air_status st = check_solve(p, Y, X, batch, prm)) return st;
+    const size_t need = solve_layout(p, batch).total;
+    if (need > AIR_NOALLOC_SCRATCH_BYTES)
+        return fail(AIR_E_NOMEM, "air_solve_noalloc: this batch needs " + std::to_string(need) +
+                                     " bytes of scratch, above the static " +
+                                     std::to_string((size_t)AIR_NOALLOC_SCRATCH_BYTES) + " bytes");
+    char* w = nullptr;
+    if (air_status st = scratch_address(&w)) return st;
+    return solve_run(p, Y, X, batch, prm, resid, w, 1, s);    // one stream: no streams or events to create
+}
