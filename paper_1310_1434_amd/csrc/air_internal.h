@@ -125,6 +125,11 @@ struct RampTables {
     int n_terms, tab_j;
     float out_scale;           // kappa * 2^-12 for the 16-bit modes
     const float* wsq;          // [ds] D^(1/2) of a cosine-weighted C (applied before and after R), or null
+    // float16 split only: [rows] scratch for a power-of-two scale per input row
+    // (b * n_views + v), chosen from the row's max |y| so that the split terms
+    // neither overflow nor fall into the float16 subnormal range; null = no
+    // scaling (the float32 and bfloat16 modes, whose range is float32's)
+    float* rscale;
 };
 // scale: 0 = C y;  RAMP_POST = S C y  (S = diag(step); the projector's output
 // is already S J x, so S C S J x is RAMP_POST applied to it).

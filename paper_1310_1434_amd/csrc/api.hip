@@ -218,6 +218,7 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
         p->off_s2 = c.take(gi * g.n_views * ds * sizeof(float));       // group-interleaved backprojector input
         p->off_pscale = c.take((mb + 63) / 64 * 64 * sizeof(float));
         p->off_ppart = c.take(mb * (size_t)tiles16(g.n) * sizeof(double));
+        p->off_rscale = c.take(mb * g.n_views * sizeof(float));
         p->total = c.off;
     } catch (const std::bad_alloc&) {
         delete p;
@@ -297,10 +298,10 @@ air_status air_ramp(air_plan p, const float* y, float* yf, int32_t batch, hipStr
     if (air_status st = stage_sino(p, y, batch, p->at<float>(p->off_s1), &src, s)) return st;
     const int rows = batch * p->g.n_views;
     if (p->direct(yf)) {
-        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, yf, rows, p->ds, 0, 0, s));
+        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(p->at<float>(p->off_rscale)), src, yf, rows, p->ds, 0, 0, s));
     } else {
         float* s2 = p->at<float>(p->off_s2);
-        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, s2, rows, p->ds, 0, 0, s));
+        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(p->at<float>(p->off_rscale)), src, s2, rows, p->ds, 0, 0, s));
         AIR_K(AIR_K_OTHER, launch_repack(s2, p->ds, yf, p->g.n_bins, rows, p->g.n_bins, p->g.n_bins, s));
     }
     return AIR_OK;
@@ -317,7 +318,7 @@ air_status air_filtered_backproject(air_plan p, const float* y, float* x, int32_
     if (air_status st = stage_sino(p, y, batch, p->at<float>(p->off_s1), &src, s)) return st;
     float* s2 = p->at<float>(p->off_s2);
     const int grp = image_group(batch);
-    if (filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, s2, batch * p->g.n_views, p->ds,
+    if (filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(p->at<float>(p->off_rscale)), src, s2, batch * p->g.n_views, p->ds,
                                               RAMP_POST, grp, s));
     else AIR_K(AIR_K_OTHER, launch_scale(p->kgeom(), src, s2, batch, grp, s));
     BpArgs a{};
@@ -343,7 +344,7 @@ air_status air_normal_apply(air_plan p, const float* x, float* out, int32_t batc
     if (air_status e = build_pad(p, x, pad, p->at<double>(p->off_ppart), batch, s)) return e;
     AIR_K(AIR_K_PROJECT, launch_project(kg, pad, s1, batch, s));
     const int grp = image_group(batch);
-    if (filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), s1, s2, batch * p->g.n_views, p->ds,
+    if (filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(p->at<float>(p->off_rscale)), s1, s2, batch * p->g.n_views, p->ds,
                                               RAMP_POST, grp, s));
     else AIR_K(AIR_K_OTHER, launch_scale(kg, s1, s2, batch, grp, s));
     const float* src = s2;

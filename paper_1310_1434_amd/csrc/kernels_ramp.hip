@@ -132,6 +132,37 @@ __global__ __launch_bounds__(256) void k_ramp_f32(const float* __restrict__ y, f
     }
 }
 
+// ---------------------------------------------------------------------------- row scales
+// One wavefront per row of stride ds: scale[row] = 2^(14 - e) for the row's
+// max |y| = f 2^e (f in [0.5, 1)), so that the scaled row's largest value lies
+// in [2^13, 2^14); 1 for a zero or non-finite row.  The float16 split of a
+// scaled value then neither overflows (float16 max 65504) nor falls into the
+// float16 subnormal range unless it is 2^27 times smaller than the row's
+// largest value, and dividing the filtered row by the scale is exact.
+__global__ __launch_bounds__(256) void k_row_scale(const float* __restrict__ y, float* __restrict__ scale, int rows,
+                                                   int ds) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (row >= rows) return;     // (uniform over the wavefront)
+    const float* r = y + (size_t)row * ds;
+    float m = 0.f;
+    for (int k = 4 * lane; k < ds; k += 4 * kWave) {      // ds is a multiple of 32
+        const float4 v = *reinterpret_cast<const float4*>(r + k);
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+    // (fmaxf drops a NaN operand; a NaN row keeps the max of its other values)
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, kWave));
+    if (lane == 0) {
+        float s = 1.f;
+        if (m > 0.f && isfinite(m)) {
+            int e;
+            frexpf(m, &e);
+            s = ldexpf(1.f, min(max(14 - e, -126), 126));
+        }
+        scale[row] = s;
+    }
+}
+
 // ---------------------------------------------------------------------------- 16-bit splits
 // v_mfma_f32_16x16x16 (f16 / bf16): lane l supplies row (or column) l % 16 at
 // k slots 4 (l / 16) + i, i < 4, mapped to the actual k = k0 + 4 (l / 16) + i,
@@ -166,6 +197,8 @@ __global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y,
     const RampRow ar = ramp_row(m, batch, t.n_views, ds, grp);
     const bool mvalid = m < mrows && ar.valid;
     const float* arow = y + (mvalid ? ((size_t)ar.b * t.n_views + ar.v) * ds : 0);
+    // the row's power-of-two scale (float16 split), applied before the split
+    const float rs = (t.rscale && mvalid) ? t.rscale[(size_t)ar.b * t.n_views + ar.v] : 1.f;
     f4_t accA[NG], accB[NG];
 #pragma unroll
     for (int c = 0; c < NG; c++) {
@@ -200,7 +233,7 @@ __global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y,
                 a.x *= wv.x; a.y *= wv.y; a.z *= wv.z; a.w *= wv.w;
             }
             if (!mvalid) a = make_float4(0.f, 0.f, 0.f, 0.f);
-            const float av[4] = {a.x, a.y, a.z, a.w};
+            const float av[4] = {a.x * rs, a.y * rs, a.z * rs, a.w * rs};
             // staged entry of T(k0 + 4 slot - ncol) for column tile 0; tile c is 16 lower
             const int x0 = k0 + 4 * slot - ncol + ds + kRampZero - 4 * j_lo;
             if constexpr (PREC == AIR_MIXED_F16) {
@@ -257,11 +290,13 @@ __global__ __launch_bounds__(256) void k_ramp_split(const float* __restrict__ y,
         const RampRow orow = ramp_row(row, batch, t.n_views, ds, grp);
         if (row < mrows && orow.valid) {
             const float* so = t.step + (size_t)orow.v * ds;
+            // undo the row's power-of-two scale exactly
+            const float osc = t.rscale ? t.out_scale / t.rscale[(size_t)orow.b * t.n_views + orow.v] : t.out_scale;
 #pragma unroll
             for (int c = 0; c < NG; c++) {
                 if (c >= ng) break;
                 const int col = ncol + 16 * c;
-                float o = t.out_scale * fmaf(accB[c][r], cross, accA[c][r]);
+                float o = osc * fmaf(accB[c][r], cross, accA[c][r]);
                 if (t.wsq) o *= t.wsq[col];     // and D^(1/2) after
                 if (SCALE & RAMP_POST) o *= so[col];
                 yf[orow.out + (size_t)col * cs] = o;
@@ -280,6 +315,10 @@ static hipError_t launch_ramp_scaled(int prec, const RampTables& t, const float*
         hipLaunchKernelGGL(k_ramp_f32<SCALE>, grid, block, 2 * ds * sizeof(float), s, y, yf, t.taps32, t.step,
                            t.wsq, t.n_views, rows, ds, grp);
     } else if (prec == AIR_MIXED_F16 || prec == AIR_MIXED_BF16) {
+        if (t.rscale) {
+            hipLaunchKernelGGL(k_row_scale, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, y, t.rscale, rows, ds);
+            if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+        }
         // widest column tiles (up to 128 columns) that still give at least three blocks per CU
         const int rt8 = 8 * ((row_tiles + 7) / 8);
         const size_t lds = 0;

@@ -57,7 +57,7 @@ struct air_plan_s {
     // workspace layout (bytes)
     size_t off_rays = 0, off_step = 0, off_views = 0, off_taps = 0, off_tab16 = 0, off_wsq = 0,
            off_vorder = 0;
-    size_t off_pad = 0, off_s1 = 0, off_s2 = 0, off_pscale = 0, off_ppart = 0, total = 0;
+    size_t off_pad = 0, off_s1 = 0, off_s2 = 0, off_pscale = 0, off_ppart = 0, off_rscale = 0, total = 0;
     char* ws = nullptr;
     // per-kernel event timing (air_kernel_timing_enable)
     struct Timed {
@@ -116,7 +116,9 @@ struct air_plan_s {
         k.v_half = v_half;
         return k;
     }
-    RampTables ramp_tables() const {
+    // rscale: [rows] scratch of the float16 split's per-row scales (used by
+    // AIR_MIXED_F16 plans only)
+    RampTables ramp_tables(float* rscale) const {
         RampTables t;
         t.taps32 = reinterpret_cast<const float*>(ws + off_taps);
         t.step = reinterpret_cast<const float*>(ws + off_step);
@@ -126,6 +128,7 @@ struct air_plan_s {
         t.tab_j = ramp_tab_j(ds);
         t.out_scale = (float)(kappa / 4096.0);
         t.wsq = cos_weight ? reinterpret_cast<const float*>(ws + off_wsq) : nullptr;
+        t.rscale = prec == AIR_MIXED_F16 ? rscale : nullptr;
         return t;
     }
     template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -194,6 +197,7 @@ struct SolveBufs {
     float* pscale;  // [batch] scales of float16 padded copies (mixed-precision plans)
     float* s1;      // [batch][n_views][ds] projections
     float* s2;      // group-interleaved backprojector input (G = image_group(batch))
+    float* rscale;  // [batch][n_views] per-row scales of the float16 split ramp
     float* g;       // [batch][n][n]  A'^T Y
     float* r;       // [batch][n][n]  right-hand side, then CG residual
     float* p;       // [batch][n][n]
@@ -218,7 +222,7 @@ struct SolveSetup {
 
 // Bytes of the per-image buffers of SolveBufs (excluding the sinogram scratch).
 struct SolveLayout {
-    size_t pad, pscale, s1, s2, g, r, p, q, bb, e, part, scal, iters, total;
+    size_t pad, pscale, s1, s2, rscale, g, r, p, q, bb, e, part, scal, iters, total;
 };
 SolveLayout solve_layout(const air_plan_s* p, int batch);
 SolveBufs solve_bufs(const air_plan_s* p, const SolveLayout& L, char* ws, float* X, int batch);

@@ -15,6 +15,7 @@ SolveLayout solve_layout(const air_plan_s* p, int batch) {
     L.pscale = c.take((B + 63) / 64 * 64 * sizeof(float));
     L.s1 = c.take(B * p->g.n_views * p->ds * sizeof(float));
     L.s2 = c.take(gi * p->g.n_views * p->ds * sizeof(float));   // group-interleaved backprojector input
+    L.rscale = c.take(B * p->g.n_views * sizeof(float));
     L.g = c.take(B * np * sizeof(float));
     L.r = c.take(B * np * sizeof(float));
     L.p = c.take(B * np * sizeof(float));
@@ -37,6 +38,7 @@ SolveBufs solve_bufs(const air_plan_s* p, const SolveLayout& L, char* w, float* 
     B.pscale = F(L.pscale);
     B.s1 = F(L.s1);
     B.s2 = F(L.s2);
+    B.rscale = F(L.rscale);
     B.g = F(L.g);
     B.r = F(L.r);
     B.p = F(L.p);
@@ -62,7 +64,7 @@ air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch,
     const float* src = nullptr;
     if (air_status e = stage_sino(p, Y, batch, B.s1, &src, s)) return e;
     const int grp = image_group(batch);
-    if (st.filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), src, B.s2, rows, p->ds, RAMP_POST, grp, s));
+    if (st.filter) AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(B.rscale), src, B.s2, rows, p->ds, RAMP_POST, grp, s));
     else AIR_K(AIR_K_OTHER, launch_scale(kg, src, B.s2, batch, grp, s));
     BpArgs a{};
     a.mode = BP_PLAIN;
@@ -110,7 +112,7 @@ static air_status fbs_iteration(air_plan p, const SolveBufs& B, int batch, const
     if (air_status e = build_pad(p, B.X, pad, B.part, batch, s)) return e;
     AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, s));
     if (st.filter)
-        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(), B.s1, B.s2, rows, p->ds, RAMP_POST, grp, s));
+        AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(B.rscale), B.s1, B.s2, rows, p->ds, RAMP_POST, grp, s));
     else AIR_K(AIR_K_OTHER, launch_scale(kg, B.s1, B.s2, batch, grp, s));
     BpArgs a{};
     a.mode = BP_STEP;
@@ -136,7 +138,7 @@ static air_status fbs_iteration(air_plan p, const SolveBufs& B, int batch, const
 air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSetup& st, hipStream_t s) {
     if (st.reg == 2) return fbs_iteration(p, B, batch, st, s);
     const KGeom kg = p->kgeom();
-    const RampTables rt = p->ramp_tables();
+    const RampTables rt = p->ramp_tables(B.rscale);
     const int n = p->g.n, rows = batch * p->g.n_views, nblk = tiles16(n), nblk_bp = bp_blocks(n, batch);
     const size_t np = (size_t)n * n;
     const int grp = image_group(batch);

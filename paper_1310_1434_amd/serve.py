@@ -83,6 +83,7 @@ class GpuExecutor:
         self.capacity, self.precision, self.device = capacity, precision, device
         self._plans = {}
         self._sizes = {}
+        self._upload = None     # stream of the host-to-device sinogram copies
 
     def _sizes_of(self, key, geom):
         if key not in self._sizes:
@@ -125,10 +126,25 @@ class GpuExecutor:
         group.impl = None
 
     def admit(self, group: Group, req: Request) -> int:
-        st = group.impl["state"]
-        with self.torch.cuda.stream(group.impl["stream"]):
-            y = self.torch.from_numpy(np.ascontiguousarray(req.y, np.float32)).to(self.device, non_blocking=False)
-            return st.admit(y, n_outer=req.n_outer)
+        """Queue the request's sinogram upload on a copy stream and its admission
+        behind it on the group's stream; the host does not wait for either (nor
+        for the group's step in flight)."""
+        torch = self.torch
+        if self._upload is None:
+            self._upload = torch.cuda.Stream(device=self.device)
+        st, gs = group.impl["state"], group.impl["stream"]
+        host = torch.from_numpy(np.ascontiguousarray(req.y, np.float32)).pin_memory()
+        with torch.cuda.stream(self._upload):
+            y = torch.empty(host.shape, dtype=torch.float32, device=self.device)
+            y.copy_(host, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self._upload)
+        gs.wait_event(ev)
+        group.impl.setdefault("staged", {})
+        with torch.cuda.stream(gs):
+            slot = st.admit(y, n_outer=req.n_outer)       # (keeps y alive for the group's stream)
+        group.impl["staged"][slot] = host                # pinned source, alive until the slot retires
+        return slot
 
     def idle(self, group: Group) -> bool:
         ev = group.impl["event"]
@@ -151,6 +167,7 @@ class GpuExecutor:
             x, r = e.x, e.resid
             req.error = "non-finite residual"
         group.impl["stream"].synchronize()
+        group.impl.get("staged", {}).pop(slot, None)
         req.x = x.cpu().numpy()
         req.resid = r.cpu().numpy()
 

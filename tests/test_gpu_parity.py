@@ -576,3 +576,26 @@ def test_mixed_solve_c2_full_size(air, torch_mod, record, case, wname):
     e = rel(host(x)[0], ref["x"])
     record("rel_l2_final_mixed_c2", e)
     assert e < 1e-3
+
+
+@pytest.mark.parametrize("prec", ["mixed_f16", "mixed_bf16"])
+@pytest.mark.parametrize("scale", [1e-20, 1e20])
+def test_split_ramp_at_extreme_sinogram_scales(air, torch_mod, orc, record, prec, scale):
+    """The 16-bit splits keep float32-level accuracy at any sinogram scale: the
+    float16 split takes a power-of-two scale per row from its max |y| (no
+    overflow above 65504, no float16 subnormals for tiny rows), the bfloat16
+    split has float32's exponent range.  C and A'^T = A^T C at 1e-20 and 1e+20
+    times a C2 sinogram against the oracle."""
+    g = geom("c2")
+    y = (sino_for("c2") * scale).astype(np.float32)
+    plan = air.Plan(g, max_batch=1, precision=prec)
+    Y = dev(torch_mod, y[None])
+    G = orc.Geom(g)
+    yf = host(plan.ramp(Y))[0]
+    e_c = rel(yf, orc.ramp(G, y.astype(np.float64)))
+    x = host(plan.filtered_backproject(Y, filter=1))[0]
+    e_a = rel(x, orc.filtered_backproject(G, y.astype(np.float64), 1))
+    record(f"rel_l2_C_{prec}_scale{scale:g}", e_c)
+    record(f"rel_l2_AtC_{prec}_scale{scale:g}", e_a)
+    assert np.isfinite(yf).all() and np.isfinite(x).all()
+    assert e_c < 1e-5 and e_a < 1e-5, (e_c, e_a)
