@@ -88,6 +88,11 @@ def parse():
     ap.add_argument("--quality-i0", type=float, default=2e4, help="incident photons per ray of the quality scans")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into profiles/traffic_c2.json")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="print a markdown table of a rocprofv3 --kernel-trace --stats output directory")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="print a markdown table of rocprofv3 --pmc output directories (per-dispatch averages of the "
+                         "projector, backprojector and ramp kernels, with derived rates)")
     return ap.parse_args()
 
 
@@ -283,6 +288,76 @@ def summarize_pmc(fetch_dir: str, write_dir: str, batch: int):
     print(json.dumps(out, indent=1))
 
 
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)):
+        rows += list(csv.DictReader(open(f)))
+    return rows
+
+
+def _short(name: str) -> str:
+    name = name.split("(")[0].strip()
+    return name[5:] if name.startswith("void ") else name
+
+
+def summarize_trace(d: str) -> str:
+    """Markdown table of a kernel-trace statistics file (rocprofv3 --stats)."""
+    rows = _csv_rows(d, "kernel_stats.csv")
+    out = ["| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in rows[:16]:
+        out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def summarize_counters(dirs, batch: int) -> str:
+    """Per-dispatch counter averages of the projector, backprojector and ramp
+    kernels over several rocprofv3 --pmc directories (one counter set each),
+    with the rates derived from them: VALU busy = SQ_ACTIVE_INST_VALU (quad
+    cycles, summed over the 1024 SIMDs) x 4 / (1024 x kernel cycles), kernel
+    cycles = GRBM_GUI_ACTIVE / 8 (summed over the eight XCDs); VALU lane
+    operations per useful FMA = 64 SQ_INSTS_VALU / (2 samples x images)."""
+    import collections
+    import synth
+    from paper_1310_1434_amd import air
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    meta = {}
+    for d in dirs:
+        for r in _csv_rows(d, "counter_collection.csv"):
+            name = _short(r["Kernel_Name"])
+            if not name.startswith(("air::k_backproject", "air::k_project", "air::k_ramp")):
+                continue
+            vals[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
+            meta[name] = (r.get("LDS_Block_Size"), r.get("Grid_Size"), r.get("Workgroup_Size"))
+    w = synth.workload("c2")
+    _, lo, hi = air.host_tables(w.geom)
+    samples = int(np.maximum(hi - lo + 1, 0).sum())
+    out = []
+    for name in sorted(vals):
+        c = {k: sum(v) / len(v) for k, v in vals[name].items()}
+        lds, grid, wg = meta[name]
+        out.append(f"**`{name}`** (LDS bytes {lds}, grid {grid} work-items in groups of {wg})\n")
+        out.append("| counter | per dispatch |")
+        out.append("|---|---|")
+        for k in sorted(c):
+            out.append(f"| {k} | {c[k]:.4g} |")
+        cyc = c.get("GRBM_GUI_ACTIVE", 0) / 8.0
+        if cyc and "SQ_ACTIVE_INST_VALU" in c:
+            out.append(f"| *VALU busy (derived)* | {c['SQ_ACTIVE_INST_VALU'] * 4 / (1024 * cyc):.2f} |")
+        if "k_backproject" in name or "k_project" in name:
+            imgs = int(name.split("<")[1].split(",")[2]) if "k_backproject" in name else None
+            if imgs is None:
+                imgs = batch // 2 if batch >= 8 else batch
+            fma = 2.0 * samples * imgs
+            if "SQ_INSTS_VALU" in c:
+                out.append(f"| *VALU lane operations per useful FMA (derived, {imgs} images, {samples} samples "
+                           f"per image)* | {64 * c['SQ_INSTS_VALU'] / fma:.2f} |")
+        out.append("")
+    return "\n".join(out)
+
+
 def serving_workload(n_requests: int, rate: float, seed: int = 0):
     """The serving mix: image size uniform over {256, 512, 768} (0.78 mm pixels,
     1.4375 n bins of 1.2 mm), views uniform over {180, 360, 720, 1440} over 2 pi,
@@ -325,7 +400,7 @@ def serve_run(torch, reqs, precision, rate, base_rate, capacity, warmup):
 
     reqs = [copy.copy(r) for r in reqs]
     for r in reqs:
-        r.arrival *= base_rate / rate
+        r.arrival = r.arrival * base_rate / rate if rate else 0.0      # rate 0: all at once
     ex = GpuExecutor(lam=0.005, mu=1.0, n_cg=5, max_outer=50, capacity=capacity, precision=precision)
     for r in reqs:                    # ray tables are built before the clock starts
         ex.plan(geometry_key(r.geom), r.geom)
@@ -356,15 +431,17 @@ def serve_run(torch, reqs, precision, rate, base_rate, capacity, warmup):
 
 def serve_leg(torch, a):
     """The serving mix at 40 requests/s on both paths, then the mixed path at 20
-    and 30 requests/s on the first 150 requests.  A rate counts as stable when
-    no queue builds up over the stream: the mean latency of its last third of
-    requests is at most 1.5 x that of its first third (beyond capacity the
-    latency grows with every arrival)."""
+    and 30 requests/s on the first 150 requests, and the same 150 requests all
+    at once: the rate at which that backlog drains is the server's capacity
+    for this mix, and Poisson arrivals are stable at any rate below it.  Each
+    run also reports its latency trend (mean latency of the last third of the
+    requests over the first third: about 1 while arrivals are served, growing
+    beyond capacity; noisy on short streams whose request mix drifts)."""
     reqs = serving_workload(a.serve_requests, a.serve_rate)
     print(f"bench: serving leg, {len(reqs)} requests", file=sys.stderr, flush=True)
     out = {"workload": f"{len(reqs)} requests: n in {{256, 512, 768}}, views in {{180, 360, 720, 1440}}, "
                        "100% or 25%, I0 U[1e4, 1e5], 20-50 Bregman x 5 CG, Poisson arrivals",
-           "stable_if": "latency_growth <= 1.5 (mean latency of the last third of the requests over the first third)"}
+           "stable_if": "offered rate below the capacity (capacity_mixed: a 150-request backlog's drain rate)"}
     for prec in ("fp32", "mixed_f16"):
         out[prec] = serve_run(torch, reqs, prec, a.serve_rate, a.serve_rate, a.serve_capacity, a.serve_warmup)
     sweep = []
@@ -374,9 +451,52 @@ def serve_leg(torch, a):
     sweep.append(out["mixed_f16"])
     out["rate_sweep_mixed"] = [{k: s[k] for k in ("offered_rate_per_s", "recon_per_s", "p50_s", "p99_s",
                                                   "latency_growth")} for s in sweep]
-    stable = [s["offered_rate_per_s"] for s in sweep
-              if s["latency_growth"] is not None and s["latency_growth"] <= 1.5]
-    out["max_stable_rate_per_s"] = max(stable) if stable else None
+    burst = serve_run(torch, reqs[:150], "mixed_f16", 0.0, a.serve_rate, a.serve_capacity, 0)
+    out["capacity_mixed"] = {"requests": burst["requests"], "recon_per_s": burst["recon_per_s"],
+                             "wall_s": burst["wall_s"], "note": "all requests arrive at once"}
+    out["max_stable_rate_per_s"] = burst["recon_per_s"]
+    out["stable_at_40_per_s"] = burst["recon_per_s"] > a.serve_rate
+    return out
+
+
+def c5_leg(torch, air, batch: int = 16):
+    """1024^2 fan beam, 2304 views x 1536 bins, a batch of 16 (one seeded case
+    replicated; the kernels' work does not depend on the values): solves of 1
+    and 2 Bregman iterations on each path (two sub-batch streams, as timed for
+    C2) give the time per iteration, from which a 50-iteration solve is
+    extrapolated; plus the kernels of one iteration, alone and in the two-stream
+    configuration, and the dominant kernel's roofline."""
+    import synth
+    w = synth.workload("c5")
+    y1 = synth.make_case(w, 0)["y"].astype(np.float32)
+    y = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(y1, (batch,) + y1.shape))).cuda()
+    out = {"workload": w.name, "batch": batch, "n": w.geom.n, "views": w.geom.n_views, "bins": w.geom.n_bins,
+           "n_outer": w.n_outer, "n_cg": w.n_cg}
+    for prec in ("fp32", "mixed_f16"):
+        plan = air.Plan(w.geom, max_batch=batch, precision=prec)
+        ws = torch.empty(plan.solve_workspace_bytes(batch), dtype=torch.uint8, device="cuda")
+        t = {}
+        for k in (1, 2, 1, 2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.solve(y, w.lam, w.mu, k, w.n_cg, workspace=ws, with_resid=False)
+            torch.cuda.synchronize()
+            t[k] = time.perf_counter() - t0          # (the second of each pair: warm)
+        per_outer = t[2] - t[1]
+        setup = t[1] - per_outer
+        full = setup + w.n_outer * per_outer
+        r = {"s_per_outer_iteration": per_outer, "setup_s": setup, "recon_per_s_extrapolated": batch / full,
+             "extrapolated": f"a {w.n_outer}-iteration solve from timed solves of 1 and 2 iterations"}
+        if prec == "fp32":
+            rsteps = ray_steps(plan)
+            km = instrumented(torch, air, plan, y, w, ws, "on", 1)
+            kma = instrumented(torch, air, plan, y, w, ws, "one_stream", 1)
+            r["kernel_ms"] = {k: {"avg_ms": v["avg_ms"], "launches": v["launches"]} for k, v in km.items()}
+            r["roofline"] = roofline(km, w.geom, batch, 1, w.n_cg, rsteps, prec, "two sub-batch streams")
+            r["roofline_alone"] = roofline(kma, w.geom, batch, 1, w.n_cg, rsteps, prec, "every kernel alone")
+        out[prec] = r
+        del plan, ws
+        torch.cuda.synchronize()
     return out
 
 
@@ -483,6 +603,12 @@ def main():
     if a.summarize_pmc:
         summarize_pmc(a.summarize_pmc[0], a.summarize_pmc[1], a.batch)
         return
+    if a.summarize_trace:
+        print(summarize_trace(a.summarize_trace))
+        return
+    if a.summarize_counters:
+        print(summarize_counters(a.summarize_counters, a.batch))
+        return
     if a.quality:
         print(json.dumps({"quality": quality_bench(a)}), flush=True)
         return
@@ -582,6 +708,11 @@ def main():
     del plans
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    if a.workload == "c2" and not a.kernel_timing_only:
+        print("bench: C5 and C3 ramp-GEMM legs", file=sys.stderr, flush=True)
+        out["c5"] = c5_leg(torch, air)
+        out["c3_ramp_gemm"] = c3_gemm_bench(a)
+        torch.cuda.empty_cache()
     if a.workload == "c2" and not (a.no_serve or a.kernel_timing_only):
         out["served"] = serve_leg(torch, a)
     if not (a.no_cpu_baseline or a.kernel_timing_only):
