@@ -12,8 +12,11 @@ every request is done:
      budget allows (idle empty groups are closed, and then plans without a group
      dropped, to make room); a request whose group could never fit the budget is
      rejected;
-  3. step: every group with active slots whose previous step has completed
-     advances one Bregman iteration (one replay of its captured graph).
+  3. step: every group with active slots and fewer than `depth` steps in
+     flight (2 by default) enqueues one more Bregman iteration (one replay of
+     its captured graph), so the next step is already queued behind the
+     running one; no step is enqueued past a slot's last iteration (the
+     library stops there), so a finished slot waits only for its own step.
 
 So a request that arrives while others are on the GPU joins at the next step
 of its group, and finished ones leave without waiting for the rest.  The
@@ -119,7 +122,7 @@ class GpuExecutor:
         stream = self.torch.cuda.Stream(device=self.device)
         state = self.air.State(self.plan(group.key, group.geom), self.capacity, self.lam, self.mu, self.n_cg,
                                self.max_outer, stream=stream)
-        group.impl = {"state": state, "stream": stream, "event": None}
+        group.impl = {"state": state, "stream": stream, "events": deque()}
 
     def close(self, group: Group):
         group.impl["stream"].synchronize()
@@ -146,15 +149,24 @@ class GpuExecutor:
         group.impl["staged"][slot] = host                # pinned source, alive until the slot retires
         return slot
 
+    def in_flight(self, group: Group) -> int:
+        """Steps of the group enqueued and not yet completed."""
+        evs = group.impl["events"]
+        while evs and evs[0].query():
+            evs.popleft()
+        return len(evs)
+
     def idle(self, group: Group) -> bool:
-        ev = group.impl["event"]
-        return ev is None or ev.query()
+        return self.in_flight(group) == 0
 
     def step(self, group: Group) -> int:
+        """Enqueue one Bregman iteration of the group's active slots; 0 if a slot
+        has reached its iteration count (it must be retired first)."""
         k = group.impl["state"].step(1)
-        ev = self.torch.cuda.Event()
-        ev.record(group.impl["stream"])
-        group.impl["event"] = ev
+        if k:
+            ev = self.torch.cuda.Event()
+            ev.record(group.impl["stream"])
+            group.impl["events"].append(ev)
         return k
 
     def progress(self, group: Group, slot: int) -> tuple[int, int]:
@@ -173,10 +185,12 @@ class GpuExecutor:
 
 
 class Server:
-    def __init__(self, executor, hbm_budget: int, capacity: int, clock=time.perf_counter, sleep=time.sleep):
+    def __init__(self, executor, hbm_budget: int, capacity: int, clock=time.perf_counter, sleep=time.sleep,
+                 depth: int = 2):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.capacity = capacity
+        self.depth = depth
         self.clock, self.sleep = clock, sleep
         self.groups: dict[tuple, Group] = {}
         self.pending: deque[Request] = deque()
@@ -259,12 +273,12 @@ class Server:
             g.slots[slot] = req
             self.pending.remove(req)
             busy = True
-        # 3. step every group with work whose previous step completed
+        # 3. keep up to `depth` steps in flight in every group with work
         for g in self.groups.values():
-            if g.slots and self.ex.idle(g):
-                self.ex.step(g)
-                self.steps += 1
-                busy = True
+            if g.slots and self.ex.in_flight(g) < self.depth:
+                if self.ex.step(g):
+                    self.steps += 1
+                    busy = True
         return busy
 
     def run(self, requests: list[Request], idle_sleep: float = 2e-4) -> list[Request]:
@@ -322,7 +336,7 @@ class FakeExecutor:
             self.plans[g.key] = self.bytes_per_plan(g.geom)
             self.held += self.plans[g.key]
         self.held += self.bytes_per_group(g.geom)
-        g.impl = {"busy_until": 0.0, "iters": {}, "next": 0}
+        g.impl = {"done_at": deque(), "iters": {}, "next": 0}
         self.opened.append(g.key)
 
     def close(self, g):
@@ -337,14 +351,24 @@ class FakeExecutor:
         self.log.append(("admit", req.rid, self.now))
         return slot
 
+    def in_flight(self, g):
+        q = g.impl["done_at"]
+        while q and q[0] <= self.now:
+            q.popleft()
+        return len(q)
+
     def idle(self, g):
-        return self.now >= g.impl["busy_until"]
+        return self.in_flight(g) == 0
 
     def step(self, g):
-        k = len(g.slots)
+        its = g.impl["iters"]
+        if any(its[slot][0] >= its[slot][1] for slot in g.slots):
+            return 0                          # a finished slot must be retired first
         for slot in g.slots:
-            g.impl["iters"][slot][0] += 1
-        g.impl["busy_until"] = self.now + self.step_cost(g, k)
+            its[slot][0] += 1
+        q = g.impl["done_at"]
+        start = q[-1] if q and q[-1] > self.now else self.now
+        q.append(start + self.step_cost(g, len(g.slots)))
         return 1
 
     def progress(self, g, slot):

@@ -121,3 +121,32 @@ def test_nonfinite_result_is_reported_and_does_not_stop_the_loop():
     done = srv.run([make(i, G1, 2, 0.0) for i in range(3)])
     assert [r.error for r in done] == [None, "non-finite residual", None]
     assert latency_stats(done)["count"] == 2
+
+
+def test_steps_are_enqueued_ahead_but_never_past_a_slot_end():
+    """With two steps in flight a group's next iteration is queued behind the
+    running one, so a coarse polling loop no longer idles the group between
+    steps; no step is ever enqueued beyond a slot's iteration count."""
+    def finish_time(depth):
+        ex = FakeExecutor(lambda g: 1, lambda g, k: 0.01)
+        srv = Server(ex, 10, 2, clock=ex.clock, sleep=ex.sleep, depth=depth)
+        peak = []
+        poll = srv.poll
+
+        def watched(now):
+            busy = poll(now)
+            for g in srv.groups.values():
+                peak.append(ex.in_flight(g))
+                for slot in g.slots:
+                    it, n_outer = ex.progress(g, slot)
+                    assert it <= n_outer
+            return busy
+
+        srv.poll = watched
+        done = srv.run([make(0, G1, 6, 0.0), make(1, G1, 4, 0.0)], idle_sleep=0.004)
+        return max(r.finished for r in done), max(peak)
+
+    t1, p1 = finish_time(1)
+    t2, p2 = finish_time(2)
+    assert p1 == 1 and p2 == 2
+    assert t2 < t1
