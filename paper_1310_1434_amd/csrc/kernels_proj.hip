@@ -205,6 +205,32 @@ __device__ __forceinline__ int64_t fx_at2(const RayEntry& e, int a2) { return e.
 // into [0, n + 2] only ever moves samples onto the zero padding, so an
 // out-of-range step contributes exactly zero (no range test needed).
 __device__ __forceinline__ int fx_clamped_index(int64_t t, int n) { return min(max(fx_index(t), 0), n + 2); }
+// The same as one unsigned minimum: a negative index wraps above n + 2 and so
+// lands on the two zero samples at the far end of the line instead of the near
+// end; either way the step contributes exactly zero.
+__device__ __forceinline__ uint32_t fx_clamped_index_u(int64_t t, int n) {
+    return min((uint32_t)fx_index(t), (uint32_t)(n + 2));
+}
+
+// Raw buffer loads of a group's padded copies: a buffer descriptor for the
+// group (uniform), this lane's byte offset (its line set and sample index) and
+// the step's row offset, uniform over the wavefront, as the scalar offset.
+// Offsets are 32-bit, so the buffer path serves groups below 2 GiB.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t group_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <int BYTES>
+__device__ __forceinline__ void buf_load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, uint32_t (&w)[BYTES / 4]) {
+    if constexpr (BYTES == 16) {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+        w[0] = u[0]; w[1] = u[1]; w[2] = u[2]; w[3] = u[3];
+    } else if constexpr (BYTES == 8) {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+        w[0] = u[0]; w[1] = u[1];
+    } else {
+        w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0);
+    }
+}
 
 // Block -> (view, chunk of 256 bins).  Blocks go to the eight XCDs round-robin
 // (block L to XCD L mod 8); XCDs 0-3 take the views whose rays are mostly
@@ -222,7 +248,7 @@ __device__ __forceinline__ bool proj_block(const KGeom& g, int chunks, int& v, i
 typedef float float2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 typedef float float4_a8 __attribute__((ext_vector_type(4), aligned(8)));
 
-template <int P>
+template <int P, bool BUF>
 __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __restrict__ pad,
                                                          float* __restrict__ y, int chunks, int batch) {
     static_assert(P == 1 || P == 2, "images per thread");
@@ -251,21 +277,47 @@ __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __
     for (int q = 0; q < P; q++) acc[q] = 0.f;
     int64_t t = fx_at(e, a_lo - g.c0);
     const int64_t m = (int64_t)e.m * 2;
-    uint32_t row = (uint32_t)(a_lo * line);
+    if constexpr (BUF) {
+        // the same samples through a buffer descriptor: one unsigned minimum and
+        // one shift-add per step instead of two clamps, an add and a 64-bit address
+        constexpr uint32_t SB = P * 4;             // bytes per sample
+        const uint32_t set_bytes = (uint32_t)g.n * (uint32_t)line * SB;
+        const __amdgpu_buffer_rsrc_t rs = group_rsrc(pad + (size_t)blockIdx.y * 2 * g.n * line * P, 2 * set_bytes);
+        const uint32_t lane_base = axis ? set_bytes : 0u;
+        uint32_t row_bytes = (uint32_t)a_lo * (uint32_t)line * SB;
 #pragma unroll 4
-    for (int a = a_lo; a <= a_hi; a++, t += m, row += line) {
-        const float f = fx_frac(t);
-        const float* p = lines + (size_t)((row + (uint32_t)fx_clamped_index(t, g.n)) * (uint32_t)P);
-        if constexpr (P == 1) {
-            const float2_a4 u = *reinterpret_cast<const float2_a4*>(p);
-            acc[0] = fmaf(1.f - f, u.x, acc[0]);
-            acc[0] = fmaf(f, u.y, acc[0]);
-        } else {
-            const float4_a8 u = *reinterpret_cast<const float4_a8*>(p);    // [j][0..1], [j + 1][0..1]
-            acc[0] = fmaf(1.f - f, u.x, acc[0]);
-            acc[0] = fmaf(f, u.z, acc[0]);
-            acc[1] = fmaf(1.f - f, u.y, acc[1]);
-            acc[1] = fmaf(f, u.w, acc[1]);
+        for (int a = a_lo; a <= a_hi; a++, t += m, row_bytes += (uint32_t)line * SB) {
+            const float f = fx_frac(t);
+            uint32_t w[2 * P];
+            buf_load<2 * SB>(rs, fx_clamped_index_u(t, g.n) * SB + lane_base, row_bytes, w);
+            if constexpr (P == 1) {
+                acc[0] = fmaf(1.f - f, __uint_as_float(w[0]), acc[0]);
+                acc[0] = fmaf(f, __uint_as_float(w[1]), acc[0]);
+            } else {                                   // [j][0..1], [j + 1][0..1]
+                acc[0] = fmaf(1.f - f, __uint_as_float(w[0]), acc[0]);
+                acc[0] = fmaf(f, __uint_as_float(w[2]), acc[0]);
+                acc[1] = fmaf(1.f - f, __uint_as_float(w[1]), acc[1]);
+                acc[1] = fmaf(f, __uint_as_float(w[3]), acc[1]);
+            }
+        }
+    }
+    if constexpr (!BUF) {
+        uint32_t row = (uint32_t)(a_lo * line);
+#pragma unroll 4
+        for (int a = a_lo; a <= a_hi; a++, t += m, row += line) {
+            const float f = fx_frac(t);
+            const float* p = lines + (size_t)((row + (uint32_t)fx_clamped_index(t, g.n)) * (uint32_t)P);
+            if constexpr (P == 1) {
+                const float2_a4 u = *reinterpret_cast<const float2_a4*>(p);
+                acc[0] = fmaf(1.f - f, u.x, acc[0]);
+                acc[0] = fmaf(f, u.y, acc[0]);
+            } else {
+                const float4_a8 u = *reinterpret_cast<const float4_a8*>(p);    // [j][0..1], [j + 1][0..1]
+                acc[0] = fmaf(1.f - f, u.x, acc[0]);
+                acc[0] = fmaf(f, u.z, acc[0]);
+                acc[1] = fmaf(1.f - f, u.y, acc[1]);
+                acc[1] = fmaf(f, u.w, acc[1]);
+            }
         }
     }
     if (k >= g.ds) return;
@@ -282,6 +334,20 @@ __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __
 // The same projector over float16 copies (mixed-precision plans): groups of
 // P <= 4 images per sample, converted to float32 before the multiply-adds, sums
 // divided by the images' power-of-two scales.
+// Samples j (s0) and j + 1 (s1) of P float16 images from the words of one load.
+template <int P>
+__device__ __forceinline__ void unpack_half_pair(const uint32_t* w, float (&s0)[P], float (&s1)[P]) {
+    auto h = [&](int idx) {      // half number idx of the loaded words
+        const uint32_t x = w[idx >> 1];
+        return __half2float(__ushort_as_half((unsigned short)((idx & 1) ? x >> 16 : x & 0xffff)));
+    };
+#pragma unroll
+    for (int q = 0; q < P; q++) {
+        s0[q] = h(q);
+        s1[q] = h(P + q);
+    }
+}
+
 template <int P>
 __device__ __forceinline__ void load_half_pair(const uint16_t* p, float (&s0)[P], float (&s1)[P]) {
     if constexpr (P == 4) {
@@ -306,7 +372,7 @@ __device__ __forceinline__ void load_half_pair(const uint16_t* p, float (&s0)[P]
     }
 }
 
-template <int P>
+template <int P, bool BUF>
 __global__ __launch_bounds__(kProjBlock) void k_project16(KGeom g, const uint16_t* __restrict__ pad,
                                                            const float* __restrict__ scale, float* __restrict__ y,
                                                            int chunks, int batch) {
@@ -333,16 +399,39 @@ __global__ __launch_bounds__(kProjBlock) void k_project16(KGeom g, const uint16_
     for (int q = 0; q < P; q++) acc[q] = 0.f;
     int64_t t = fx_at(e, a_lo - g.c0);
     const int64_t m = (int64_t)e.m * 2;
-    uint32_t row = (uint32_t)(a_lo * line);
+    if constexpr (BUF) {
+        constexpr uint32_t SB = P * 2;             // bytes per sample
+        const uint32_t set_bytes = (uint32_t)g.n * (uint32_t)line * SB;
+        const __amdgpu_buffer_rsrc_t rs = group_rsrc(pad + (size_t)blockIdx.y * 2 * g.n * line * P, 2 * set_bytes);
+        const uint32_t lane_base = axis ? set_bytes : 0u;
+        uint32_t row_bytes = (uint32_t)a_lo * (uint32_t)line * SB;
 #pragma unroll 4
-    for (int a = a_lo; a <= a_hi; a++, t += m, row += line) {
-        const float f = fx_frac(t);
-        float s0[P], s1[P];
-        load_half_pair<P>(lines + (size_t)((row + (uint32_t)fx_clamped_index(t, g.n)) * (uint32_t)P), s0, s1);
+        for (int a = a_lo; a <= a_hi; a++, t += m, row_bytes += (uint32_t)line * SB) {
+            const float f = fx_frac(t);
+            uint32_t w[(2 * SB + 3) / 4];
+            buf_load<(2 * SB + 3) / 4 * 4>(rs, fx_clamped_index_u(t, g.n) * SB + lane_base,
+                                           row_bytes, w);
+            float s0[P], s1[P];
+            unpack_half_pair<P>(w, s0, s1);
 #pragma unroll
-        for (int q = 0; q < P; q++) {
-            acc[q] = fmaf(1.f - f, s0[q], acc[q]);
-            acc[q] = fmaf(f, s1[q], acc[q]);
+            for (int q = 0; q < P; q++) {
+                acc[q] = fmaf(1.f - f, s0[q], acc[q]);
+                acc[q] = fmaf(f, s1[q], acc[q]);
+            }
+        }
+    }
+    if constexpr (!BUF) {
+        uint32_t row = (uint32_t)(a_lo * line);
+#pragma unroll 4
+        for (int a = a_lo; a <= a_hi; a++, t += m, row += line) {
+            const float f = fx_frac(t);
+            float s0[P], s1[P];
+            load_half_pair<P>(lines + (size_t)((row + (uint32_t)fx_clamped_index(t, g.n)) * (uint32_t)P), s0, s1);
+#pragma unroll
+            for (int q = 0; q < P; q++) {
+                acc[q] = fmaf(1.f - f, s0[q], acc[q]);
+                acc[q] = fmaf(f, s1[q], acc[q]);
+            }
         }
     }
     if (k >= g.ds) return;
@@ -358,23 +447,32 @@ __global__ __launch_bounds__(kProjBlock) void k_project16(KGeom g, const uint16_
 }
 
 static void launch_project_g(const KGeom& g, PadBuf pad, float* y, int batch, hipStream_t s) {
+    // buffer addressing while a group's two line sets stay below 2 GiB (32-bit offsets)
+    const auto fits = [&](int sample_bytes) { return 2.0 * g.n * g.line * sample_bytes < 2147483648.0; };
+    const int chunks = (g.ds + kProjBlock - 1) / kProjBlock;
     if (pad.half) {
-        const int chunks = (g.ds + kProjBlock - 1) / kProjBlock;
         const int pg = pad_group16(batch);
         dim3 grid(2 * g.v_half * chunks, (batch + pg - 1) / pg), block(kProjBlock);
-        if (pg == 4)
-            hipLaunchKernelGGL((k_project16<4>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
+        const bool buf = fits(2 * pg);
+        if (pg == 4 && buf)
+            hipLaunchKernelGGL((k_project16<4, true>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
+        else if (pg == 4)
+            hipLaunchKernelGGL((k_project16<4, false>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
+        else if (pg == 2 && buf)
+            hipLaunchKernelGGL((k_project16<2, true>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
         else if (pg == 2)
-            hipLaunchKernelGGL((k_project16<2>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
-        else
-            hipLaunchKernelGGL((k_project16<1>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
+            hipLaunchKernelGGL((k_project16<2, false>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
+        else    // (a single image's two float16 samples are not dword aligned: pointer loads)
+            hipLaunchKernelGGL((k_project16<1, false>), grid, block, 0, s, g, pad.half, pad.scale, y, chunks, batch);
         return;
     }
-    const int chunks = (g.ds + kProjBlock - 1) / kProjBlock;
     const int pg = pad_group(batch);
     dim3 grid(2 * g.v_half * chunks, (batch + pg - 1) / pg), block(kProjBlock);
-    if (pg == 2) hipLaunchKernelGGL((k_project<2>), grid, block, 0, s, g, pad.base, y, chunks, batch);
-    else hipLaunchKernelGGL((k_project<1>), grid, block, 0, s, g, pad.base, y, chunks, batch);
+    const bool buf = fits(4 * pg);
+    if (pg == 2 && buf) hipLaunchKernelGGL((k_project<2, true>), grid, block, 0, s, g, pad.base, y, chunks, batch);
+    else if (pg == 2) hipLaunchKernelGGL((k_project<2, false>), grid, block, 0, s, g, pad.base, y, chunks, batch);
+    else if (buf) hipLaunchKernelGGL((k_project<1, true>), grid, block, 0, s, g, pad.base, y, chunks, batch);
+    else hipLaunchKernelGGL((k_project<1, false>), grid, block, 0, s, g, pad.base, y, chunks, batch);
 }
 
 hipError_t launch_project(const KGeom& g, PadBuf pad, float* y, int batch, hipStream_t s) {
