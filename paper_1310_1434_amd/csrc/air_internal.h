@@ -15,6 +15,8 @@
 
 namespace air {
 
+struct BpWin;
+
 // Geometry block passed by value to the projector kernels.
 struct KGeom {
     int n;          // image side
@@ -36,7 +38,32 @@ struct KGeom {
     // views whose rays are mostly x-driven first, then the mostly y-driven ones.
     const int32_t* vorder;
     int v_half;
+    float kdet;             // sdd / bin: fan-beam detector bins per unit of ap / bp
+    // backprojector windows: [tile][view] over the 16 x 32 pixel tiles, row-major
+    // (see BpWin), and the same for horizontal pixel pairs
+    const BpWin* bpwin;
+    const float2* bpwinx;
 };
+
+// Window record of one 16 x 32 pixel tile of the backprojector (two vertically
+// adjacent pixels per thread) and one view, built once per plan by
+// launch_bp_windows.  The tile stages the bins kb0 .. kb0 + nb - 1; a thread
+// whose pixel pair has its midpoint projected to the continuous bin km takes the
+// staged slots ceil(km - lo) .. floor(km + hi) (relative to kb0), which hold
+// every ray that can give either pixel a non-zero weight.
+struct BpWin {
+    int32_t kb0;
+    int32_t meta;   // bits 0-15: nb; bit 16: some staged ray is x-driven; bit 17: some is y-driven
+    float lo, hi;   // kb0 + h and h - kb0, h the window's half-width in bins
+};
+static_assert(sizeof(BpWin) == 16, "BpWin is read as one 16-byte scalar load");
+constexpr int kBpTileW = 16, kBpTileH = 32;
+__host__ __device__ inline size_t bp_window_count(int n, int n_views) {
+    return (size_t)((n + kBpTileW - 1) / kBpTileW) * ((n + kBpTileH - 1) / kBpTileH) * n_views;
+}
+// Fills win[bp_window_count] and winx (the same half-widths for horizontal pixel
+// pairs, as {lo, hi}) from the geometry and the ray table of g.
+hipError_t launch_bp_windows(const KGeom& g, BpWin* win, float2* winx, hipStream_t s);
 
 // Images are processed in groups of image_group(batch) in {1, 2, 4, 8, 16}: the
 // group a backprojector thread serves.  The choice minimises

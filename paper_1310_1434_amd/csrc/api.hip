@@ -209,6 +209,8 @@ air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_prec
         p->off_views = c.take(p->views.size() * sizeof(float));
         p->off_taps = c.take(p->taps32.size() * sizeof(float));
         p->off_vorder = c.take(p->vorder.size() * sizeof(int32_t));
+        p->off_bpwin = c.take(bp_window_count(g.n, g.n_views) * sizeof(BpWin));
+        p->off_bpwinx = c.take(bp_window_count(g.n, g.n_views) * sizeof(float2));
         if (!p->tab16.empty()) p->off_tab16 = c.take(p->tab16.size() * sizeof(uint16_t));
         if (p->cos_weight) p->off_wsq = c.take(p->wsq.size() * sizeof(float));
         const size_t mb = (size_t)max_batch;
@@ -256,6 +258,12 @@ air_status air_plan_bind_workspace(air_plan p, void* dev, size_t bytes, hipStrea
                                hipMemcpyHostToDevice, s));
     if (p->cos_weight)
         AIR_HIP(hipMemcpyAsync(ws + p->off_wsq, p->wsq.data(), p->wsq.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    {
+        // the backprojector's window table, from the tables just copied
+        const KGeom kg = p->kgeom_at(ws);
+        AIR_HIP(launch_bp_windows(kg, reinterpret_cast<BpWin*>(ws + p->off_bpwin),
+                                  reinterpret_cast<float2*>(ws + p->off_bpwinx), s));
+    }
     AIR_HIP(hipStreamSynchronize(s));
     p->ws = ws;
     return AIR_OK;

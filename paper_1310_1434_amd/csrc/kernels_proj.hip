@@ -505,25 +505,143 @@ hipError_t launch_scale(const KGeom& g, const float* y, float* out, int batch, i
 // pixels per thread share more intercept work but halve the wavefronts (1.24
 // against 0.82 ms at 512^2 and 8 images), one pixel doubles them but also the
 // LDS reads per pixel (1.38 against 0.99 ms at 16 images).  For every view the
-// thread takes the bins whose rays
-// can give any of its pixels a non-zero Joseph weight: any sample that touches
-// a pixel lies in the diamond |dx| + |dy| < pixel around its centre, so its ray
-// meets the detector within hw bins of the centre's own projection k_c, where
-// hw bounds the projected half-width of the diamond over the whole tile; the
-// interval (between the projections of the first and last centre, which bound
-// the others) is widened by 0.01 bin.  For each candidate the thread
-// re-evaluates the forward projector's own fixed-point intercept and float32
-// weights, so the result is the exact transpose of J (k_project before its
-// step scaling) up to summation order.  An x-driven ray crosses all PIX pixels at the same
-// intercept, so one evaluation gives every weight; a y-driven ray needs its
-// own intercept (one multiply-add) per pixel.  A larger window only adds candidates of weight
+// thread takes the bins whose rays can give any of its pixels a non-zero Joseph
+// weight: any sample that touches a pixel lies in the diamond |dx| + |dy| < pixel
+// around its centre, so its ray meets the detector within hw bins of the
+// centre's own projection, and the centres lie within e bins of the projection
+// km of their midpoint, so the thread takes the bins within hw + e + 0.01 of km.
+// hw and e are bounded over the whole tile, once per plan (k_bp_windows, which
+// also fixes the bins the tile stages for each view and whether their rays are
+// x- or y-driven).  For each candidate the thread re-evaluates the forward
+// projector's own fixed-point intercept and float32 weights, so the result is
+// the exact transpose of J (k_project before its step scaling) up to summation
+// order.  An x-driven ray crosses all PIX pixels at the same intercept, so one
+// evaluation gives every weight; a y-driven ray needs its own intercept (one
+// multiply-add) per pixel.  A larger window only adds candidates of weight
 // exactly zero, so every pixel gets the same bits whatever PIX and BT.
 //
-// Views are processed eight at a time, two per wavefront.  Per view, the
-// tile's bins (the union of its pixels' intervals, at most 32 PIX per pass),
-// their sinogram values, the tile window and the view's direction are staged
-// in shared memory by one wavefront, so the per-view work reads only LDS.  The
-// terms of a pass are summed in float32, across passes in float64.  No atomics.
+// Views are processed eight at a time.  Per view, the tile's bins (at most 32
+// PIX per pass) and their sinogram values are staged in shared memory by one
+// wavefront (two views each); the window records and the view directions are
+// uniform over the block and read with scalar loads.  The terms of a pass are
+// summed in float32, across passes in float64.  No atomics.
+
+// Loads from addresses that are uniform over the wavefront, through the scalar
+// cache (for data the kernel only reads).
+typedef const __attribute__((address_space(4))) uint32_t uniform_word;
+__device__ __forceinline__ uint32_t uniform_u32(const void* p, int k) { return ((uniform_word*)p)[k]; }
+__device__ __forceinline__ BpWin uniform_win(const BpWin* p) {
+    BpWin r;
+    r.kb0 = (int32_t)uniform_u32(p, 0);
+    r.meta = (int32_t)uniform_u32(p, 1);
+    r.lo = __uint_as_float(uniform_u32(p, 2));
+    r.hi = __uint_as_float(uniform_u32(p, 3));
+    return r;
+}
+__device__ __forceinline__ float2 uniform_f2(const float2* p) {
+    return make_float2(__uint_as_float(uniform_u32(p, 0)), __uint_as_float(uniform_u32(p, 1)));
+}
+
+// Continuous detector bin of the projection of point (px, py) in view (c, s),
+// in float32 (k_bp_windows bounds its rounding); BEAM: 0 parallel, 1 fan.
+template <int BEAM>
+__device__ __forceinline__ float bin_of(const KGeom& g, float px, float py, float c, float s) {
+    if constexpr (BEAM == 0) return fmaf(fmaf(px, c, py * s), g.inv_bin, g.half_d);
+    const float ap = fmaf(py, c, -px * s);
+    const float bp = fmaf(-px, c, fmaf(-py, s, g.sod));
+    return fmaf(ap * __builtin_amdgcn_rcpf(bp), g.kdet, g.half_d);
+}
+
+// Float32 value not below x.
+__device__ __forceinline__ float float_up(double x) {
+    const float f = (float)x;
+    return (double)f < x ? nextafterf(f, INFINITY) : f;
+}
+
+// One thread per (tile, view), in float64.  The rectangle R of pixel centres the
+// tile's threads project spans the tile's in-image pixels and the in-image
+// stand-ins of those past the edge (pairs are clamped to n - PIX).  Over R:
+// hw bounds the projected half-width of a pixel's diamond (parallel beam
+// pixel m / bin with m = max(|c|, |s|); fan beam: a vertex moves ap and bp by at
+// most pixel m, so |du| <= sdd pixel m (bp + |ap|) / (bp (bp - pixel m)) / bin,
+// which grows with |ap| and falls with bp); the tile stages the bins within
+// hw + 1/2 of the corners' projections.  A pair's centres lie within
+// e = (PIX - 1) pixel / 2 max |du/dy| of its midpoint's projection (|du/dx| for
+// horizontal pairs).  Parallel beam: u = (x c + y s) / bin + half_d, so
+// |du/dy| = |s| / bin.  Fan beam: u = (sdd / bin) ap / bp + half_d with
+// ap = y c - x s and bp = sod - x c - y s, so du/dy = (sdd / bin) (c bp + s ap)
+// / bp^2 and du/dx = (sdd / bin) (c ap - s bp) / bp^2; both numerators are
+// linear in (x, y), so their largest magnitudes over R are at its corners, as
+// is the smallest bp.  The 0.01 bin added to the half-widths covers the float32
+// rounding of the kernel's projections.
+template <int PIX>
+__global__ __launch_bounds__(256) void k_bp_windows(KGeom g, BpWin* __restrict__ win, float2* __restrict__ winx) {
+    constexpr int TW = kBpTileW, TH = kBpTileH;
+    static_assert(TH == 16 * PIX && TW == 16, "backprojector tiles");
+    const int n = g.n, tiles_x = (n + TW - 1) / TW;
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= bp_window_count(n, g.n_views)) return;
+    const int v = (int)(idx % g.n_views), tile = (int)(idx / g.n_views);
+    const int i0 = (tile % tiles_x) * TW, j0 = (tile / tiles_x) * TH;
+    const int ia = min(i0, max(n - PIX, 0)), ja = min(j0, max(n - PIX, 0));
+    const int ib = max(min(i0 + TW - 1, n - 1), ia + PIX - 1), jb = max(min(j0 + TH - 1, n - 1), ja + PIX - 1);
+    const double pixel = g.pixel, hn = g.half_n, inv_bin = g.inv_bin, hd = g.half_d;
+    const double x[2] = {(ia - hn) * pixel, (ib - hn) * pixel}, y[2] = {(ja - hn) * pixel, (jb - hn) * pixel};
+    const double c = g.views[v].x, s = g.views[v].y;
+    double k_lo = INFINITY, k_hi = -INFINITY, bp_min = INFINITY, ap_max = 0.0, ny = 0.0, nx = 0.0;
+    for (int q = 0; q < 4; q++) {
+        const double qx = x[q & 1], qy = y[q >> 1];
+        double u;
+        if (g.beam == 0) {
+            u = (qx * c + qy * s) * inv_bin + hd;
+        } else {
+            const double ap = qy * c - qx * s, bp = (double)g.sod - (qx * c + qy * s);
+            u = (double)g.sdd * ap / bp * inv_bin + hd;
+            bp_min = fmin(bp_min, bp);
+            ap_max = fmax(ap_max, fabs(ap));
+            ny = fmax(ny, fabs(c * bp + s * ap));
+            nx = fmax(nx, fabs(c * ap - s * bp));
+        }
+        k_lo = fmin(k_lo, u);
+        k_hi = fmax(k_hi, u);
+    }
+    const double dm = pixel * fmax(fabs(c), fabs(s));
+    double hw, dy, dx;
+    if (g.beam == 0) {
+        hw = dm * inv_bin;
+        dy = fabs(s) * inv_bin;
+        dx = fabs(c) * inv_bin;
+    } else {
+        const double k = (double)g.sdd * inv_bin;
+        hw = k * dm * (bp_min + ap_max) / (bp_min * (bp_min - dm));
+        dy = k * ny / (bp_min * bp_min);
+        dx = k * nx / (bp_min * bp_min);
+    }
+    const int kb0 = max(0, (int)floor(k_lo - hw - 0.5));
+    const int kb1 = min(g.n_bins - 1, (int)ceil(k_hi + hw + 0.5));
+    int any_x = 0, any_y = 0;
+    const RayEntry* rays = g.rays + (size_t)v * g.n_bins;
+    for (int k = kb0; k <= kb1; k++) {
+        if (ray_axis(rays[k].meta)) any_y = 1;
+        else any_x = 1;
+    }
+    const double e = 0.5 * (PIX - 1) * pixel;
+    const double hy = hw + e * dy + 0.01, hx = hw + e * dx + 0.01;
+    BpWin r;
+    r.kb0 = kb0;
+    r.meta = max(0, kb1 - kb0 + 1) | (any_x << 16) | (any_y << 17);
+    r.lo = float_up(kb0 + hy);
+    r.hi = float_up(hy - kb0);
+    win[idx] = r;
+    winx[idx] = make_float2(float_up(kb0 + hx), float_up(hx - kb0));
+}
+
+hipError_t launch_bp_windows(const KGeom& g, BpWin* win, float2* winx, hipStream_t s) {
+    const size_t count = bp_window_count(g.n, g.n_views);
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bp_windows<2>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, g, win, winx);
+    return hipGetLastError();
+}
 
 // Weights of ray e for the pixels (i, j + q), q < PIX, or all zero if !use.
 // AX: 0 = the ray is x-driven, 1 = y-driven, 2 = either (read from the
@@ -560,20 +678,20 @@ __device__ __forceinline__ void joseph_column(const RayEntry& e, bool use, int i
 }
 
 // Accumulate the candidates [wlo, whi] (staged bins of one view, SV floats per
-// slot) into the pixels, two at a time.
+// slot) into the pixels, two at a time.  The second of the last pair may be
+// slot whi + 1 (at most the spare slot past the staged bins): it holds a
+// finite value and takes weight zero.
 template <int AX, int BT, int PIX, int SV>
 __device__ __forceinline__ void bp_candidates(const RayEntry* rays, const float* vals, int wlo, int whi, int i,
                                               int j, int c0, float (&acc)[PIX][BT]) {
     for (int w = wlo; w <= whi; w += 2) {
-        const bool two = w + 1 <= whi;
-        const int w1 = two ? w + 1 : w;
-        const RayEntry e0 = rays[w], e1 = rays[w1];
+        const RayEntry e0 = rays[w], e1 = rays[w + 1];
         float y0[BT], y1[BT];
         load_group<BT>(vals + w * SV, y0);
-        load_group<BT>(vals + w1 * SV, y1);
+        load_group<BT>(vals + (w + 1) * SV, y1);
         float wt0[PIX], wt1[PIX];
         joseph_column<AX, PIX>(e0, true, i, j, c0, wt0);
-        joseph_column<AX, PIX>(e1, two, i, j, c0, wt1);
+        joseph_column<AX, PIX>(e1, w + 1 <= whi, i, j, c0, wt1);
 #pragma unroll
         for (int r = 0; r < PIX; r++)
 #pragma unroll
@@ -610,10 +728,10 @@ template <int BT, int PIX, int SV>
 __device__ __forceinline__ void bp_candidates_any(int axes, const RayEntry* rays, const float* vals, int wlo, int whi,
                                                   int i, int j, int c0, float (&acc)[PIX][BT]) {
     if (wlo > whi) return;
-    RayEntry e0 = rays[wlo], e1 = rays[min(wlo + 1, whi)];
+    RayEntry e0 = rays[wlo], e1 = rays[wlo + 1];
     float y0[BT], y1[BT];
     load_group<BT>(vals + wlo * SV, y0);
-    load_group<BT>(vals + min(wlo + 1, whi) * SV, y1);
+    load_group<BT>(vals + (wlo + 1) * SV, y1);
     for (int w = wlo; w <= whi; w += 2) {
         float wt0[PIX], wt1[PIX];
         joseph_pair<PIX>(axes, e0, e1, w + 1 <= whi, i, j, c0, wt0, wt1);
@@ -622,23 +740,12 @@ __device__ __forceinline__ void bp_candidates_any(int axes, const RayEntry* rays
 #pragma unroll
             for (int q = 0; q < BT; q++) acc[r][q] = fmaf(wt1[r], y1[q], fmaf(wt0[r], y0[q], acc[r][q]));
         if (w + 2 <= whi) {
-            const int m1 = min(w + 3, whi);
             e0 = rays[w + 2];
-            e1 = rays[m1];
+            e1 = rays[w + 3];
             load_group<BT>(vals + (w + 2) * SV, y0);
-            load_group<BT>(vals + m1 * SV, y1);
+            load_group<BT>(vals + (w + 3) * SV, y1);
         }
     }
-}
-
-// Continuous detector bin of the projection of point (px, py) in view (c, s);
-// BEAM: 0 parallel, 1 fan (g.beam, fixed per launch).
-template <int BEAM>
-__device__ __forceinline__ float bin_of(const KGeom& g, float px, float py, float c, float s) {
-    if constexpr (BEAM == 0) return fmaf(fmaf(px, c, py * s), g.inv_bin, g.half_d);
-    const float ap = fmaf(py, c, -px * s);
-    const float bp = g.sod - fmaf(px, c, py * s);
-    return fmaf(g.sdd * ap * __builtin_amdgcn_rcpf(bp), g.inv_bin, g.half_d);
 }
 
 // Pixels per backprojector thread (see k_backproject).
@@ -649,23 +756,19 @@ int bp_blocks(int n, int batch) { return ((n + 15) / 16) * ((n + 16 * bp_pix(bat
 // uniform branches per view (about 5% of the launch).
 template <int MODE, bool REDUCE, int BT, int PIX, int BEAM>
 __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __restrict__ y, BpArgs a, int batch) {
-    constexpr int NV = 8;                  // views per pass, two per wavefront (the same for every group size)
+    constexpr int NV = 8;                  // views per pass (the same for every group size)
     constexpr int VW = NV / 4;             // views staged per wavefront
     constexpr int BINS = 32 * PIX;         // staged bins per view and pass
     constexpr int TH = 16 * PIX;           // tile height
+    static_assert(TH == kBpTileH && kBpTileW == 16, "tiles of the window table");
     static_assert(BINS % kWave == 0, "whole wavefronts stage a view");
-    __shared__ __align__(16) RayEntry s_ray[NV][BINS];
+    // one spare slot past the staged bins, read by the second candidate of a pair
+    constexpr int SLOTS = BINS + 1;
+    __shared__ __align__(16) RayEntry s_ray[NV][SLOTS];
     // slot stride: BT floats, padded by 4 from 8 images up so that the 16-byte
     // reads of 8 consecutive slots fall in distinct LDS banks
     constexpr int SV = BT >= 8 ? BT + 4 : BT;
-    __shared__ __align__(16) float s_val[NV][BINS * SV];
-    // per view: tile window (first bin, bin count, half-width as float bits),
-    // whether the staged rays are all x-driven (0), all y-driven (1) or both
-    // (2), and (cos, sin) as float bits; read together, with one wait
-    __shared__ __align__(16) int s_view[NV][8];
-    // per view: 1 if any staged ray is x-driven, 2 if any is y-driven, 4 if the
-    // window needs more than one staging pass
-    __shared__ __align__(16) int s_flags[NV];
+    __shared__ __align__(16) float s_val[NV][SLOTS * SV];
     // A group of views whose staged rays are all x-driven runs one loop
     // with no axis test.  One whose rays are all y-driven runs the same
     // loop over horizontal pixel tuples instead, which then share each
@@ -681,7 +784,7 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     constexpr bool kModes = BT <= 4;
     static_assert(!kModes || BT < kBpInLoopMin, "single-axis groups use the per-axis loop");
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     // tiles -> XCDs: blocks go to the eight XCDs round-robin; when the tile grid
     // splits into eight equal rectangles, each XCD gets one of them, so the
     // tiles sharing an L2 are neighbours and stage overlapping windows
@@ -700,17 +803,23 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
     const int i = i0 + tx, j = j0 + PIX * ty;      // pixels (i, j + r), r < PIX
     const int b0 = blockIdx.z * BT;
     const int n = g.n;
-    // (pixels past the image edge take an in-image neighbour's window; their sums are dropped)
+    // the tile's window records, one per view
+    const size_t wrow = (size_t)(by * gridDim.x + bx) * g.n_views;
+    const BpWin* wt = g.bpwin + wrow;
+    const float2* wtx = g.bpwinx + wrow;
+    // midpoint of the thread's pixel column (pixels past the image edge take an
+    // in-image neighbour's window; their sums are dropped)
     const float px = ((float)min(i, n - 1) - g.half_n) * g.pixel;
-    const float py = ((float)min(j, max(n - PIX, 0)) - g.half_n) * g.pixel;
+    const float pym = ((float)min(j, max(n - PIX, 0)) - g.half_n + 0.5f * (PIX - 1)) * g.pixel;
     // the same thread's horizontal tuple (ih + q, jh), q < PIX, used for view
-    // groups whose rays are all y-driven (kModes)
+    // groups whose rays are all y-driven (kModes), and its midpoint
     const int ih = i0 + PIX * (threadIdx.x % (16 / PIX)), jh = j0 + threadIdx.x / (16 / PIX);
-    const float pxh = ((float)min(ih, max(n - PIX, 0)) - g.half_n) * g.pixel;
+    const float pxhm = ((float)min(ih, max(n - PIX, 0)) - g.half_n + 0.5f * (PIX - 1)) * g.pixel;
     const float pyh = ((float)min(jh, n - 1) - g.half_n) * g.pixel;
-    // corners of the tile's in-image pixel centres, for the tile windows
-    const float cx[2] = {((float)i0 - g.half_n) * g.pixel, ((float)min(i0 + 15, n - 1) - g.half_n) * g.pixel};
-    const float cy[2] = {((float)j0 - g.half_n) * g.pixel, ((float)min(j0 + TH - 1, n - 1) - g.half_n) * g.pixel};
+    // the spare slots start as zeros (afterwards they hold zeros or finite sums)
+    if (threadIdx.x < NV) reinterpret_cast<int4*>(s_ray[threadIdx.x])[BINS] = make_int4(0, 0, 0, 0);
+    static_assert(NV * SV <= 256, "one pass zeroes the spare value slots");
+    if (threadIdx.x < NV * SV) s_val[threadIdx.x / SV][BINS * SV + threadIdx.x % SV] = 0.f;
     // group-interleaved input [group][v][k][BT]: this thread's BT images are
     // contiguous and 4 * BT-byte aligned
     const float* yg = y + (size_t)blockIdx.z * g.n_views * g.ds * BT;
@@ -720,131 +829,70 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
 #pragma unroll
         for (int q = 0; q < BT; q++) tot[r][q] = 0.0;
     for (int v0 = 0; v0 < g.n_views; v0 += NV) {
-        // Tile windows: wavefront w takes the views w + 4 h of the pass (h < VW),
-        // lane 4 h + c corner c; they reach the other wavefronts through LDS.
-        int my_kb0[VW], my_nb[VW];
-        {
-            float kc_lo = 3e38f, kc_hi = -3e38f, hw = 0.f;
-            float2 cs = make_float2(1.f, 0.f);
-            const int h = lane >> 2, c = lane & 3;
-            const int v = v0 + wave + 4 * h;
-            if (h < VW && v < g.n_views) {
-                cs = g.views[v];
-                const float qx = cx[c & 1], qy = cy[c >> 1];
-                const float kc = bin_of<BEAM>(g, qx, qy, cs.x, cs.y);
-                const float m = fmaxf(fabsf(cs.x), fabsf(cs.y));
-                float bp_min = 1.f, ap_max = 0.f;
-                if constexpr (BEAM != 0) {
-                    ap_max = fabsf(fmaf(qy, cs.x, -qx * cs.y));
-                    bp_min = g.sod - fmaf(qx, cs.x, qy * cs.y);
-                }
-                kc_lo = kc;
-                kc_hi = kc;
+        // staging passes over the widest window of the eight views, and the
+        // union of their axis bits (bit 0: some ray x-driven, bit 1: some y-driven)
+        int passes = 0, axes_any = 0;
 #pragma unroll
-                for (int off = 1; off <= 2; off <<= 1) {
-                    kc_lo = fminf(kc_lo, __shfl_xor(kc_lo, off, kWave));
-                    kc_hi = fmaxf(kc_hi, __shfl_xor(kc_hi, off, kWave));
-                    bp_min = fminf(bp_min, __shfl_xor(bp_min, off, kWave));
-                    ap_max = fmaxf(ap_max, __shfl_xor(ap_max, off, kWave));
-                }
-                // projected half-width of a pixel's diamond, in bins: parallel
-                // pixel * m; fan: a vertex moves ap and bp by at most pixel * m,
-                // so |du| <= sdd pixel m (bp + |ap|) / (bp (bp - pixel m)), which
-                // grows with |ap| and falls with bp over the tile
-                const float dm = g.pixel * m;
-                if constexpr (BEAM == 0)
-                    hw = dm * g.inv_bin;
-                else
-                    hw = g.sdd * dm * (bp_min + ap_max) * __builtin_amdgcn_rcpf(bp_min * (bp_min - dm)) * g.inv_bin;
-            }
-#pragma unroll
-            for (int hh = 0; hh < VW; hh++) {
-                const float klo_f = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc_lo), 4 * hh));
-                const float khi_f = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc_hi), 4 * hh));
-                const float hws = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hw), 4 * hh));
-                const float csx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cs.x), 4 * hh));
-                const float csy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cs.y), 4 * hh));
-                my_kb0[hh] = 0;
-                my_nb[hh] = 0;
-                if (v0 + wave + 4 * hh < g.n_views) {
-                    my_kb0[hh] = max(0, (int)floorf(klo_f - hws - 0.5f));
-                    const int kb1 = min(g.n_bins - 1, (int)ceilf(khi_f + hws + 0.5f));
-                    my_nb[hh] = max(0, kb1 - my_kb0[hh] + 1);
-                }
-                if (lane == 0) {
-                    *reinterpret_cast<int4*>(&s_view[wave + 4 * hh][0]) =
-                        make_int4(my_kb0[hh], my_nb[hh], __float_as_int(hws), 0);
-                    *reinterpret_cast<int2*>(&s_view[wave + 4 * hh][4]) =
-                        make_int2(__float_as_int(csx), __float_as_int(csy));
-                }
+        for (int s = 0; s < NV; s++) {
+            if (v0 + s < g.n_views) {
+                const int m = (int)uniform_u32(&wt[v0 + s], 1);
+                passes = max(passes, ((m & 0xFFFF) + BINS - 1) / BINS);
+                axes_any |= m >> 16;
             }
         }
+        int mode = 0;    // 1: all rays x-driven, 2: all y-driven (one pass, up to 4 images)
+        if (kModes && passes == 1) mode = (axes_any & 2) == 0 ? 1 : ((axes_any & 1) == 0 ? 2 : 0);
         float acc[PIX][BT];
 #pragma unroll
         for (int r = 0; r < PIX; r++)
 #pragma unroll
             for (int q = 0; q < BT; q++) acc[r][q] = 0.f;
-        int passes = 1;
         for (int p = 0; p < passes; p++) {
-            // stage: wavefront w loads bins kb0 + p * BINS + (lane, lane + 64, ...) of its views
+            // stage: wavefront w loads bins kb0 + p * BINS + (lane, lane + 64, ...)
+            // of views w and w + 4 of the pass; slots past the window get zeros
 #pragma unroll
             for (int hh = 0; hh < VW; hh++) {
-                const int sv = wave + 4 * hh;
-                bool any_x = false, any_y = false;
+                const int sv = wave + 4 * hh, v = v0 + sv;
+                int kb0 = 0, nb = 0;
+                if (v < g.n_views) {
+                    const BpWin r = uniform_win(&wt[v]);
+                    kb0 = r.kb0;
+                    nb = r.meta & 0xFFFF;
+                }
 #pragma unroll
                 for (int hb = 0; hb < BINS / kWave; hb++) {
                     const int slot = hb * kWave + lane;
                     const int w = p * BINS + slot;
-                    const bool act = w < my_nb[hh];
-                    int ax = 0;
-                    if (act) {
-                        const int v = v0 + sv, k = my_kb0[hh] + w;
-                        const RayEntry e = g.rays[(size_t)v * g.n_bins + k];
-                        s_ray[sv][slot] = e;
-                        ax = ray_axis(e.meta);
-                        float t[BT];
+                    int4 e = make_int4(0, 0, 0, 0);     // a RayEntry
+                    float t[BT];
+#pragma unroll
+                    for (int q = 0; q < BT; q++) t[q] = 0.f;
+                    if (w < nb) {
+                        const int k = kb0 + w;
+                        e = reinterpret_cast<const int4*>(g.rays)[(size_t)v * g.n_bins + k];
                         load_group<BT>(yg + ((size_t)v * g.ds + k) * BT, t);
-                        store_group<BT>(&s_val[sv][slot * SV], t);
                     }
-                    any_x = any_x || __ballot(act && ax == 0) != 0;
-                    any_y = any_y || __ballot(act && ax == 1) != 0;
-                }
-                if (lane == 0) {
-                    s_view[sv][3] = any_y ? (any_x ? 2 : 1) : 0;
-                    if constexpr (kModes) s_flags[sv] = (any_x ? 1 : 0) | (any_y ? 2 : 0) | (my_nb[hh] > BINS ? 4 : 0);
+                    reinterpret_cast<int4*>(s_ray[sv])[slot] = e;
+                    store_group<BT>(&s_val[sv][slot * SV], t);
                 }
             }
             __syncthreads();
-            int mode = 0;
-            if (kModes && p == 0) {
-                const int4 fa = *reinterpret_cast<const int4*>(&s_flags[0]);
-                const int4 fb = *reinterpret_cast<const int4*>(&s_flags[4]);
-                const int f = __builtin_amdgcn_readfirstlane(fa.x | fa.y | fa.z | fa.w | fb.x | fb.y | fb.z | fb.w);
-                if (!(f & 4)) mode = (f & 2) == 0 ? 1 : ((f & 1) == 0 ? 2 : 0);
-            }
-            static_assert(NV == 8, "flags read as two int4");
-            // this view's candidate slots [wlo, whi] for centres (xa, ya) and (xa + dx, ya + dy)
-            auto slots = [&](int s, float xa, float ya, float dx, float dy, int& wlo, int& whi) {
-                const int4 vw = *reinterpret_cast<const int4*>(&s_view[s][0]);
-                const int2 vc = *reinterpret_cast<const int2*>(&s_view[s][4]);
-                const int kb0 = __builtin_amdgcn_readfirstlane(vw.x);
-                const int nbs = __builtin_amdgcn_readfirstlane(vw.y);
-                const float hws = __int_as_float(__builtin_amdgcn_readfirstlane(vw.z));
-                const float2 cs = make_float2(__int_as_float(__builtin_amdgcn_readfirstlane(vc.x)),
-                                              __int_as_float(__builtin_amdgcn_readfirstlane(vc.y)));
-                const float ka = bin_of<BEAM>(g, xa, ya, cs.x, cs.y);
-                const float kb = bin_of<BEAM>(g, xa + dx, ya + dy, cs.x, cs.y);
-                const int klo = max(kb0, (int)ceilf(fminf(ka, kb) - hws - 0.01f));
-                const int khi = min(kb0 + nbs - 1, (int)floorf(fmaxf(ka, kb) + hws + 0.01f));
-                wlo = max(klo - kb0, 0);
-                whi = min(khi - kb0, BINS - 1);
+            // the staged slots [wlo, whi] within the window of a pixel pair whose
+            // midpoint projects to km
+            const int base = p * BINS;
+            auto window = [&](float km, float lo, float hi, int meta, int& wlo, int& whi) {
+                wlo = max((int)ceilf(km - lo) - base, 0);
+                whi = min((int)floorf(km + hi) - base, min((meta & 0xFFFF) - 1 - base, BINS - 1));
             };
             if (mode == 1) {
 #pragma unroll
                 for (int s = 0; s < NV; s++) {
-                    if (v0 + s >= g.n_views) continue;
+                    const int v = v0 + s;
+                    if (v >= g.n_views) continue;
+                    const BpWin r = uniform_win(&wt[v]);
+                    const float2 cs = uniform_f2(&g.views[v]);
                     int wlo, whi;
-                    slots(s, px, py, 0.f, (PIX - 1) * g.pixel, wlo, whi);
+                    window(bin_of<BEAM>(g, px, pym, cs.x, cs.y), r.lo, r.hi, r.meta, wlo, whi);
                     bp_candidates<0, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
                 }
                 __syncthreads();
@@ -854,16 +902,20 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
                 // acc (still zero: first and only pass) first holds the tuple sums
 #pragma unroll
                 for (int s = 0; s < NV; s++) {
-                    if (v0 + s >= g.n_views) continue;
+                    const int v = v0 + s;
+                    if (v >= g.n_views) continue;
+                    const int meta = (int)uniform_u32(&wt[v], 1);
+                    const float2 lh = uniform_f2(&wtx[v]);
+                    const float2 cs = uniform_f2(&g.views[v]);
                     int wlo, whi;
-                    slots(s, pxh, pyh, (PIX - 1) * g.pixel, 0.f, wlo, whi);
+                    window(bin_of<BEAM>(g, pxhm, pyh, cs.x, cs.y), lh.x, lh.y, meta, wlo, whi);
                     // the x-driven loop with the roles of rows and columns exchanged
                     bp_candidates<0, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, jh, ih, g.c0, acc);
                 }
                 __syncthreads();
                 // tuple sums -> [row][column][image] in the value buffer -> vertical owners
                 float* xb = &s_val[0][0];
-                static_assert(NV * BINS * SV >= 16 * TH * BT, "exchange fits the value buffer");
+                static_assert(NV * SLOTS * SV >= 16 * TH * BT, "exchange fits the value buffer");
 #pragma unroll
                 for (int q = 0; q < PIX; q++) store_group<BT>(xb + ((jh - j0) * 16 + (ih - i0) + q) * BT, acc[q]);
                 __syncthreads();
@@ -874,24 +926,15 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
             }
 #pragma unroll
             for (int s = 0; s < NV; s++) {
-                // the view's window (uniform over the block), and this column's
-                // bin interval from its first and last centre
-                const int4 vw = *reinterpret_cast<const int4*>(&s_view[s][0]);
-                const int2 vc = *reinterpret_cast<const int2*>(&s_view[s][4]);
-                const int kb0 = __builtin_amdgcn_readfirstlane(vw.x);
-                const int nbs = __builtin_amdgcn_readfirstlane(vw.y);
-                if (p == 0) passes = max(passes, (nbs + BINS - 1) / BINS);
-                if (v0 + s >= g.n_views) continue;
-                const float hws = __int_as_float(__builtin_amdgcn_readfirstlane(vw.z));
-                const float2 cs = make_float2(__int_as_float(__builtin_amdgcn_readfirstlane(vc.x)),
-                                              __int_as_float(__builtin_amdgcn_readfirstlane(vc.y)));
-                const float ka = bin_of<BEAM>(g, px, py, cs.x, cs.y);
-                const float kb = bin_of<BEAM>(g, px, py + (PIX - 1) * g.pixel, cs.x, cs.y);
-                const int klo = max(kb0, (int)ceilf(fminf(ka, kb) - hws - 0.01f));
-                const int khi = min(kb0 + nbs - 1, (int)floorf(fmaxf(ka, kb) + hws + 0.01f));
-                const int base = kb0 + p * BINS;
-                const int wlo = max(klo - base, 0), whi = min(khi - base, BINS - 1);
-                const int axes = __builtin_amdgcn_readfirstlane(vw.w);   // uniform over the block
+                const int v = v0 + s;
+                if (v >= g.n_views) continue;
+                const BpWin r = uniform_win(&wt[v]);
+                const float2 cs = uniform_f2(&g.views[v]);
+                int wlo, whi;
+                window(bin_of<BEAM>(g, px, pym, cs.x, cs.y), r.lo, r.hi, r.meta, wlo, whi);
+                // staged rays all x-driven (0), all y-driven (1) or both (2)
+                const int am = (r.meta >> 16) & 3;
+                const int axes = am == 1 ? 0 : (am == 2 ? 1 : 2);
                 if constexpr (BT >= kBpInLoopMin)
                     bp_candidates_any<BT, PIX, SV>(axes, s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
                 else if (axes == 0)

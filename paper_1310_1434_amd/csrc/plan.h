@@ -56,7 +56,7 @@ struct air_plan_s {
     int n_terms = 0;
     // workspace layout (bytes)
     size_t off_rays = 0, off_step = 0, off_views = 0, off_taps = 0, off_tab16 = 0, off_wsq = 0,
-           off_vorder = 0;
+           off_vorder = 0, off_bpwin = 0, off_bpwinx = 0;
     size_t off_pad = 0, off_s1 = 0, off_s2 = 0, off_pscale = 0, off_ppart = 0, off_rscale = 0, total = 0;
     char* ws = nullptr;
     // per-kernel event timing (air_kernel_timing_enable)
@@ -94,7 +94,9 @@ struct air_plan_s {
         return e;
     }
 
-    KGeom kgeom() const {
+    KGeom kgeom() const { return kgeom_at(ws); }
+    // the same for a workspace at base (before it is bound)
+    KGeom kgeom_at(const char* base) const {
         KGeom k;
         k.n = g.n;
         k.n_views = g.n_views;
@@ -109,11 +111,14 @@ struct air_plan_s {
         k.half_d = (float)(0.5 * (g.n_bins - 1));
         k.sod = (float)g.sod;
         k.sdd = (float)g.sdd;
-        k.rays = reinterpret_cast<const RayEntry*>(ws + off_rays);
-        k.step = reinterpret_cast<const float*>(ws + off_step);
-        k.views = reinterpret_cast<const float2*>(ws + off_views);
-        k.vorder = reinterpret_cast<const int32_t*>(ws + off_vorder);
+        k.rays = reinterpret_cast<const RayEntry*>(base + off_rays);
+        k.step = reinterpret_cast<const float*>(base + off_step);
+        k.views = reinterpret_cast<const float2*>(base + off_views);
+        k.vorder = reinterpret_cast<const int32_t*>(base + off_vorder);
         k.v_half = v_half;
+        k.kdet = (float)(g.sdd / g.bin);
+        k.bpwin = reinterpret_cast<const BpWin*>(base + off_bpwin);
+        k.bpwinx = reinterpret_cast<const float2*>(base + off_bpwinx);
         return k;
     }
     // rscale: [rows] scratch of the float16 split's per-row scales (used by
