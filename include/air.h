@@ -68,7 +68,14 @@ typedef enum { AIR_PARALLEL = 0, AIR_FAN_FLAT = 1 } air_beam;
  * lies in [2^13, 2^14); the scale is undone exactly on the float32 sums), which
  * halves the bytes of its gathers.  Projector accumulation, images,
  * sinograms and CG vectors are float32 in all modes; CG inner products, the
- * step sizes alpha/beta and the Bregman residual norm are float64. */
+ * step sizes alpha/beta and the Bregman residual norm are float64.
+ * Range: the projector and backprojector sum interpolation weights scaled by
+ * 2^32 (the scale is undone exactly), so float32 images and sinograms must
+ * stay below 2^80 (about 1.2e24) in magnitude, and their products with the
+ * operators below float32's largest value; within that range every operator
+ * commutes with power-of-two scaling bit for bit.  Larger values overflow to
+ * infinity (the mixed modes' scaled image copies lift the limit for the
+ * projector's input only). */
 typedef enum { AIR_FP32 = 0, AIR_MIXED_F16 = 1, AIR_MIXED_BF16 = 2 } air_precision;
 
 typedef struct {

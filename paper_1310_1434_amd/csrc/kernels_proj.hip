@@ -190,7 +190,15 @@ __device__ __forceinline__ int wave_max_i(int v) {
 // Sample index (high word) and fraction (low word) of a fixed-point intercept.
 static_assert(kFrac == 32 && kSlopeFrac == 31, "fixed-point layout");
 __device__ __forceinline__ int fx_index(int64_t t) { return (int)(t >> 32); }
-__device__ __forceinline__ float fx_frac(int64_t t) { return (float)(uint32_t)t * 0x1p-32f; }
+// The interpolation weights of a sample are f and 1 - f, f = frac(t) rounded to
+// float32.  The kernels use them scaled by 2^32: W = 2^32 f (the fraction word
+// converted to float32) and G = 2^32 - W = 2^32 (1 - f), rounded.  Scaling by a
+// power of two changes no rounding of the weights, their products or the sums
+// of those, so each kernel multiplies its result by 2^-32 once, exactly, and
+// gets the same bits as with f and 1 - f (for magnitudes that neither overflow
+// nor fall to subnormals when scaled: |values| below about 2^90).
+__device__ __forceinline__ float fx_wfrac(int64_t t) { return (float)(uint32_t)t; }
+constexpr float kFxOne = 0x1p32f;
 // intercept at driving index a: tc + 2 (a - c0) m, as one 32x32->64 multiply and one shift-add
 __device__ __forceinline__ int64_t fx_at(const RayEntry& e, int a_minus_c0) {
     int64_t prod = (int64_t)a_minus_c0 * (int64_t)e.m;
@@ -287,17 +295,17 @@ __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __
         uint32_t row_bytes = (uint32_t)a_lo * (uint32_t)line * SB;
 #pragma unroll 4
         for (int a = a_lo; a <= a_hi; a++, t += m, row_bytes += (uint32_t)line * SB) {
-            const float f = fx_frac(t);
+            const float wf = fx_wfrac(t), wg = kFxOne - wf;
             uint32_t w[2 * P];
             buf_load<2 * SB>(rs, fx_clamped_index_u(t, g.n) * SB + lane_base, row_bytes, w);
             if constexpr (P == 1) {
-                acc[0] = fmaf(1.f - f, __uint_as_float(w[0]), acc[0]);
-                acc[0] = fmaf(f, __uint_as_float(w[1]), acc[0]);
+                acc[0] = fmaf(wg, __uint_as_float(w[0]), acc[0]);
+                acc[0] = fmaf(wf, __uint_as_float(w[1]), acc[0]);
             } else {                                   // [j][0..1], [j + 1][0..1]
-                acc[0] = fmaf(1.f - f, __uint_as_float(w[0]), acc[0]);
-                acc[0] = fmaf(f, __uint_as_float(w[2]), acc[0]);
-                acc[1] = fmaf(1.f - f, __uint_as_float(w[1]), acc[1]);
-                acc[1] = fmaf(f, __uint_as_float(w[3]), acc[1]);
+                acc[0] = fmaf(wg, __uint_as_float(w[0]), acc[0]);
+                acc[0] = fmaf(wf, __uint_as_float(w[2]), acc[0]);
+                acc[1] = fmaf(wg, __uint_as_float(w[1]), acc[1]);
+                acc[1] = fmaf(wf, __uint_as_float(w[3]), acc[1]);
             }
         }
     }
@@ -305,23 +313,23 @@ __global__ __launch_bounds__(kProjBlock) void k_project(KGeom g, const float* __
         uint32_t row = (uint32_t)(a_lo * line);
 #pragma unroll 4
         for (int a = a_lo; a <= a_hi; a++, t += m, row += line) {
-            const float f = fx_frac(t);
+            const float wf = fx_wfrac(t), wg = kFxOne - wf;
             const float* p = lines + (size_t)((row + (uint32_t)fx_clamped_index(t, g.n)) * (uint32_t)P);
             if constexpr (P == 1) {
                 const float2_a4 u = *reinterpret_cast<const float2_a4*>(p);
-                acc[0] = fmaf(1.f - f, u.x, acc[0]);
-                acc[0] = fmaf(f, u.y, acc[0]);
+                acc[0] = fmaf(wg, u.x, acc[0]);
+                acc[0] = fmaf(wf, u.y, acc[0]);
             } else {
                 const float4_a8 u = *reinterpret_cast<const float4_a8*>(p);    // [j][0..1], [j + 1][0..1]
-                acc[0] = fmaf(1.f - f, u.x, acc[0]);
-                acc[0] = fmaf(f, u.z, acc[0]);
-                acc[1] = fmaf(1.f - f, u.y, acc[1]);
-                acc[1] = fmaf(f, u.w, acc[1]);
+                acc[0] = fmaf(wg, u.x, acc[0]);
+                acc[0] = fmaf(wf, u.z, acc[0]);
+                acc[1] = fmaf(wg, u.y, acc[1]);
+                acc[1] = fmaf(wf, u.w, acc[1]);
             }
         }
     }
     if (k >= g.ds) return;
-    const float sv = ray ? g.step[(size_t)v * g.ds + k] : 0.f;
+    const float sv = ray ? g.step[(size_t)v * g.ds + k] * 0x1p-32f : 0.f;     // (weights scaled by 2^32)
 #pragma unroll
     for (int q = 0; q < P; q++) {
         if (b0 + q >= batch) break;
@@ -407,7 +415,7 @@ __global__ __launch_bounds__(kProjBlock) void k_project16(KGeom g, const uint16_
         uint32_t row_bytes = (uint32_t)a_lo * (uint32_t)line * SB;
 #pragma unroll 4
         for (int a = a_lo; a <= a_hi; a++, t += m, row_bytes += (uint32_t)line * SB) {
-            const float f = fx_frac(t);
+            const float wf = fx_wfrac(t), wg = kFxOne - wf;
             uint32_t w[(2 * SB + 3) / 4];
             buf_load<(2 * SB + 3) / 4 * 4>(rs, fx_clamped_index_u(t, g.n) * SB + lane_base,
                                            row_bytes, w);
@@ -415,8 +423,8 @@ __global__ __launch_bounds__(kProjBlock) void k_project16(KGeom g, const uint16_
             unpack_half_pair<P>(w, s0, s1);
 #pragma unroll
             for (int q = 0; q < P; q++) {
-                acc[q] = fmaf(1.f - f, s0[q], acc[q]);
-                acc[q] = fmaf(f, s1[q], acc[q]);
+                acc[q] = fmaf(wg, s0[q], acc[q]);
+                acc[q] = fmaf(wf, s1[q], acc[q]);
             }
         }
     }
@@ -424,18 +432,18 @@ __global__ __launch_bounds__(kProjBlock) void k_project16(KGeom g, const uint16_
         uint32_t row = (uint32_t)(a_lo * line);
 #pragma unroll 4
         for (int a = a_lo; a <= a_hi; a++, t += m, row += line) {
-            const float f = fx_frac(t);
+            const float wf = fx_wfrac(t), wg = kFxOne - wf;
             float s0[P], s1[P];
             load_half_pair<P>(lines + (size_t)((row + (uint32_t)fx_clamped_index(t, g.n)) * (uint32_t)P), s0, s1);
 #pragma unroll
             for (int q = 0; q < P; q++) {
-                acc[q] = fmaf(1.f - f, s0[q], acc[q]);
-                acc[q] = fmaf(f, s1[q], acc[q]);
+                acc[q] = fmaf(wg, s0[q], acc[q]);
+                acc[q] = fmaf(wf, s1[q], acc[q]);
             }
         }
     }
     if (k >= g.ds) return;
-    const float sv = ray ? g.step[(size_t)v * g.ds + k] : 0.f;
+    const float sv = ray ? g.step[(size_t)v * g.ds + k] * 0x1p-32f : 0.f;     // (weights scaled by 2^32)
 #pragma unroll
     for (int q = 0; q < P; q++) {
         const int b = b0 + q;
@@ -643,24 +651,27 @@ hipError_t launch_bp_windows(const KGeom& g, BpWin* win, float2* winx, hipStream
     return hipGetLastError();
 }
 
-// Weights of ray e for the pixels (i, j + q), q < PIX, or all zero if !use.
+// Weights of ray e for the pixels (i, j + q), q < PIX (scaled by 2^32, see
+// fx_wfrac), or all zero if !use.
 // AX: 0 = the ray is x-driven, 1 = y-driven, 2 = either (read from the
-// table).  With d = j0 - ob (j0 the first sample's index, ob the pixel's
-// interpolated index) a pixel takes 1 - f at d == 0 and f at d == -1.  Only
+// table).  A pixel takes G if the first sample of the pair is the pixel's own
+// (in its interpolated index) and W if it is the one before.  Only
 // a sample with -1 <= j0 < n can match an in-image pixel: exactly the samples
 // the forward projector weights, so no range test is needed.
 template <int AX, int PIX>
 __device__ __forceinline__ void joseph_column(const RayEntry& e, bool use, int i, int j, int c0, float (&w)[PIX]) {
+    // (the first sample's padded index s is compared with the pixels' own,
+    // which are constants of the thread)
     if constexpr (AX == 0) {
         // all pixels sit on the column the ray samples at i: one intercept
         const int64_t t = fx_at2(e, 2 * (i - c0));
-        const float f = fx_frac(t), g = 1.f - f;
-        const int d = fx_index(t) - kPad - j;
+        const float wf = fx_wfrac(t), wg = kFxOne - wf;
+        const int s = fx_index(t);
         bool at[PIX + 1];     // at[k]: the first sample is on row j + k - 1
 #pragma unroll
-        for (int k = 0; k <= PIX; k++) at[k] = use && d == k - 1;
+        for (int k = 0; k <= PIX; k++) at[k] = use && s == j + kPad + k - 1;
 #pragma unroll
-        for (int q = 0; q < PIX; q++) w[q] = at[q + 1] ? g : (at[q] ? f : 0.f);
+        for (int q = 0; q < PIX; q++) w[q] = at[q + 1] ? wg : (at[q] ? wf : 0.f);
     } else {
         // y-driven (AX == 1, or AX == 2 and the table says so): driving row
         // j + q, interpolated index i; x-driven: driving column i, index j + q
@@ -668,11 +679,12 @@ __device__ __forceinline__ void joseph_column(const RayEntry& e, bool use, int i
 #pragma unroll
         for (int q = 0; q < PIX; q++) {
             const int64_t t = fx_at2(e, 2 * ((ydrv ? j + q : i) - c0));
-            const float f = fx_frac(t);
-            float g = 1.f - f;
-            asm volatile("" : "+v"(g));    // keep the selection branch-free (1 - f is not sunk into a branch)
-            const int d = fx_index(t) - kPad - (ydrv ? i : j + q);
-            w[q] = (use && d == 0) ? g : ((use && d == -1) ? f : 0.f);
+            const float wf = fx_wfrac(t);
+            float wg = kFxOne - wf;
+            asm volatile("" : "+v"(wg));    // keep the selection branch-free (G is not sunk into a branch)
+            const int s = fx_index(t);
+            const int o = (ydrv ? i : j + q) + kPad;
+            w[q] = (use && s == o) ? wg : ((use && s == o - 1) ? wf : 0.f);
         }
     }
 }
@@ -951,6 +963,10 @@ __global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __res
 #pragma unroll
             for (int q = 0; q < BT; q++) tot[r][q] += (double)acc[r][q];
     }
+#pragma unroll
+    for (int r = 0; r < PIX; r++)
+#pragma unroll
+        for (int q = 0; q < BT; q++) tot[r][q] *= 0x1p-32;     // (weights scaled by 2^32: exact)
     const int nblk = gridDim.x * gridDim.y;
     const int blk = by * gridDim.x + bx;
     float res[PIX][BT];     // RESIDUAL: r of every pixel and image (0 outside the image or batch)

@@ -559,9 +559,31 @@ def test_mixed_plan_projection_of_zero_and_tiny_images(air, torch_mod):
     x[2] = 1e30 * np.random.default_rng(1).uniform(size=(g.n, g.n))
     y = host(plan.project(dev(torch_mod, x)))
     assert np.all(y[0] == 0.0)
-    ref = host(air.Plan(g, max_batch=3).project(dev(torch_mod, x)))
+    # the float32 plan's reference for the 1e30 image is taken at 2^-40 of it
+    # (float32 plans are specified below 2^80) and scaled back exactly
+    s = np.array([1.0, 1.0, 2.0 ** -40], np.float32)[:, None, None]
+    ref = host(air.Plan(g, max_batch=3).project(dev(torch_mod, x * s))) / s
     assert np.isfinite(y).all()
     assert rel(y[1], ref[1]) < 5e-4 and rel(y[2], ref[2]) < 5e-4
+
+
+@pytest.mark.parametrize("name", ["ragged", "c1"])
+def test_float32_operators_commute_with_power_of_two_scales(air, torch_mod, name):
+    """Within the float32 plans' range (below 2^80) the projector and the
+    normal operator commute with power-of-two scaling bit for bit: the 2^32
+    scale of the interpolation weights neither overflows nor changes a rounding,
+    and tiny inputs keep their bits too."""
+    g = geom(name)
+    plan = air.Plan(g, max_batch=2)
+    x = np.random.default_rng(5).uniform(0.0, 1.0, size=(2, g.n, g.n)).astype(np.float32)
+    y0 = host(plan.project(dev(torch_mod, x)))
+    n0 = host(plan.normal_apply(dev(torch_mod, x), 0.25))
+    for k in (70, -70):
+        f = np.float32(2.0 ** k)
+        y = host(plan.project(dev(torch_mod, x * f)))
+        assert np.array_equal(y, y0 * f), k
+        nk = host(plan.normal_apply(dev(torch_mod, x * f), 0.25))
+        assert np.array_equal(nk, n0 * f), k
 
 
 @pytest.mark.parametrize("case,wname", [("c2_fan_512_720_seed0", "c2")])
