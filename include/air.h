@@ -121,11 +121,13 @@ enum {
 air_status air_plan_create(const air_geometry* geom, int32_t max_batch, air_precision prec,
                            uint32_t flags, air_plan* out);
 
-/* Device bytes the plan needs: tables, taps and operator scratch for max_batch. */
+/* Device bytes the plan needs: tables, taps, the backprojector's window table
+ * (24 bytes per 16 x 32 pixel tile and view) and operator scratch for max_batch. */
 air_status air_plan_workspace_size(air_plan plan, size_t* bytes);
 
 /* Hand the plan its workspace (device, 256-byte aligned, >= workspace_size
- * bytes, caller-owned, must outlive the plan's use) and upload the tables.
+ * bytes, caller-owned, must outlive the plan's use), upload the tables and
+ * build the backprojector's window table from them (one kernel on `stream`).
  * Synchronises `stream` once (the host tables are copied before returning). */
 air_status air_plan_bind_workspace(air_plan plan, void* dev_ptr, size_t bytes, hipStream_t stream);
 
