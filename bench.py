@@ -340,6 +340,9 @@ def summarize_counters(dirs, batch: int) -> str:
     w = synth.workload("c2")
     _, lo, hi = air.host_tables(w.geom)
     samples = int(np.maximum(hi - lo + 1, 0).sum())
+    # the projectors of a run work on the same sub-batches as its backprojector groups
+    groups = [int(n.split("<")[1].split(",")[2]) for n in vals if n.startswith("air::k_backproject<")]
+    proj_imgs = max(groups) if groups else (batch // 2 if batch >= 8 else batch)
     out = []
     for name in sorted(vals):
         c = {k: sum(v) / len(v) for k, v in vals[name].items()}
@@ -353,9 +356,7 @@ def summarize_counters(dirs, batch: int) -> str:
         if cyc and "SQ_ACTIVE_INST_VALU" in c:
             out.append(f"| *VALU busy (derived)* | {c['SQ_ACTIVE_INST_VALU'] * 4 / (1024 * cyc):.2f} |")
         if "k_backproject" in name or "k_project" in name:
-            imgs = int(name.split("<")[1].split(",")[2]) if "k_backproject" in name else None
-            if imgs is None:
-                imgs = batch // 2 if batch >= 8 else batch
+            imgs = int(name.split("<")[1].split(",")[2]) if "k_backproject" in name else proj_imgs
             fma = 2.0 * samples * imgs
             if "SQ_INSTS_VALU" in c:
                 out.append(f"| *VALU lane operations per useful FMA (derived, {imgs} images, {samples} samples "

@@ -767,7 +767,7 @@ int bp_blocks(int n, int batch) { return ((n + 15) / 16) * ((n + 16 * bp_pix(bat
 // The beam type is a template parameter: as a run-time test it cost three
 // uniform branches per view (about 5% of the launch).
 template <int MODE, bool REDUCE, int BT, int PIX, int BEAM>
-__global__ __launch_bounds__(256) void k_backproject(KGeom g, const float* __restrict__ y, BpArgs a, int batch) {
+__global__ __launch_bounds__(256, BT <= 8 ? 4 : 3) void k_backproject(KGeom g, const float* __restrict__ y, BpArgs a, int batch) {
     constexpr int NV = 8;                  // views per pass (the same for every group size)
     constexpr int VW = NV / 4;             // views staged per wavefront
     constexpr int BINS = 32 * PIX;         // staged bins per view and pass
