@@ -95,6 +95,9 @@ def parse():
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into profiles/traffic_c2.json")
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="print a markdown table of a rocprofv3 --kernel-trace --stats output directory")
+    ap.add_argument("--summarize-timeline", metavar="DIR",
+                    help="print a markdown summary of a rocprofv3 --kernel-trace output directory (busy fraction, "
+                         "concurrency, time per kernel)")
     ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
                     help="print a markdown table of rocprofv3 --pmc output directories (per-dispatch averages of the "
                          "projector, backprojector and ramp kernels, with derived rates)")
@@ -315,6 +318,50 @@ def summarize_trace(d: str) -> str:
     for r in rows[:16]:
         out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                    f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def summarize_timeline(d: str) -> str:
+    """Markdown summary of a rocprofv3 --kernel-trace output directory (the
+    dispatch timeline): the GPU's busy fraction (union of the kernels' intervals
+    over the traced span), the mean number of kernels running while busy, time
+    per kernel, and the backprojector launches by group size and grid."""
+    import collections
+    rows = []
+    for r in _csv_rows(d, "kernel_trace.csv"):
+        if r.get("Kind", "KERNEL_DISPATCH") != "KERNEL_DISPATCH":
+            continue
+        grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), _short(r["Kernel_Name"]), grid))
+    rows.sort()
+    t0, t1 = rows[0][0], max(r[1] for r in rows)
+    busy, cs, ce = 0, None, None
+    for s, e, _, _ in rows:
+        if ce is None or s > ce:
+            if ce is not None:
+                busy += ce - cs
+            cs, ce = s, e
+        else:
+            ce = max(ce, e)
+    busy += ce - cs
+    total = sum(e - s for s, e, _, _ in rows)
+    out = [f"{len(rows)} dispatches over {(t1 - t0) / 1e9:.2f} s; GPU busy (some kernel running) "
+           f"{busy / (t1 - t0):.3f} of the span; {total / busy:.2f} kernels running on average while busy.", "",
+           "| kernel | calls | total s | avg us | share of kernel time |", "|---|---|---|---|---|"]
+    by = collections.defaultdict(lambda: [0, 0])
+    for s, e, n, _ in rows:
+        by[n][0] += 1
+        by[n][1] += e - s
+    for n, (c, t) in sorted(by.items(), key=lambda x: -x[1][1])[:20]:
+        out.append(f"| `{n}` | {c} | {t / 1e9:.3f} | {t / c / 1e3:.1f} | {t / total:.3f} |")
+    bp = collections.defaultdict(lambda: [0, 0])
+    for s, e, n, g in rows:
+        if n.startswith("air::k_backproject<"):
+            bp[(n, g)][0] += 1
+            bp[(n, g)][1] += e - s
+    out += ["", "| backprojector launch | work-items | calls | avg us |", "|---|---|---|---|"]
+    for (n, g), (c, t) in sorted(bp.items(), key=lambda x: -x[1][1])[:16]:
+        out.append(f"| `{n}` | {g} | {c} | {t / c / 1e3:.1f} |")
     return "\n".join(out)
 
 
@@ -612,6 +659,9 @@ def main():
         return
     if a.summarize_trace:
         print(summarize_trace(a.summarize_trace))
+        return
+    if a.summarize_timeline:
+        print(summarize_timeline(a.summarize_timeline))
         return
     if a.summarize_counters:
         print(summarize_counters(a.summarize_counters, a.batch))
