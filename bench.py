@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--serve-warmup", type=int, default=30, help="first requests left out of the latency figures")
     ap.add_argument("--serve-rate", type=float, default=40.0, help="offered load, requests per second")
     ap.add_argument("--serve-capacity", type=int, default=8, help="slots per geometry group")
+    ap.add_argument("--serve-max-active", type=int, default=0,
+                    help="groups stepping at a time, those holding the oldest requests (0: all)")
     ap.add_argument("--serve-precision", default="mixed_f16", choices=["fp32", "mixed_f16", "mixed_bf16"])
     ap.add_argument("--quality", action="store_true",
                     help="run the FBP / IR / AIR image-quality comparison (CNR, FWHM) on the paper-shaped scan")
@@ -446,7 +448,7 @@ def serving_workload(n_requests: int, rate: float, seed: int = 0):
 
 
 
-def serve_run(torch, reqs, precision, rate, base_rate, capacity, warmup):
+def serve_run(torch, reqs, precision, rate, base_rate, capacity, warmup, max_active=None):
     """Serve `reqs`, generated at base_rate requests/s, at `rate` (arrival times
     scaled by base_rate / rate) on a fresh executor; latency figures leave out
     the first `warmup` requests."""
@@ -460,7 +462,7 @@ def serve_run(torch, reqs, precision, rate, base_rate, capacity, warmup):
         ex.plan(geometry_key(r.geom), r.geom)
     torch.cuda.synchronize()
     free, _ = torch.cuda.mem_get_info()
-    srv = Server(ex, int(0.8 * free) + ex.resident_bytes(), capacity)
+    srv = Server(ex, int(0.8 * free) + ex.resident_bytes(), capacity, max_active=max_active)
     t = time.perf_counter()
     done = srv.run(reqs)
     wall = time.perf_counter() - t
@@ -477,7 +479,7 @@ def serve_run(torch, reqs, precision, rate, base_rate, capacity, warmup):
            "failed": len(done) - len(ok), "recon_per_s": len(ok) / wall, "wall_s": wall,
            "p50_s": st.get("p50_s"), "p99_s": st.get("p99_s"), "max_s": st.get("max_s"),
            "latency_growth": growth, "geometry_groups": len({geometry_key(r.geom) for r in reqs}), "slots_per_group": capacity,
-           "steps": srv.steps}
+           "max_active_groups": max_active, "steps": srv.steps}
     del srv, ex
     torch.cuda.synchronize()
     return out
@@ -493,19 +495,21 @@ def serve_leg(torch, a):
     beyond capacity; noisy on short streams whose request mix drifts)."""
     reqs = serving_workload(a.serve_requests, a.serve_rate)
     print(f"bench: serving leg, {len(reqs)} requests", file=sys.stderr, flush=True)
+    k = a.serve_max_active or None
     out = {"workload": f"{len(reqs)} requests: n in {{256, 512, 768}}, views in {{180, 360, 720, 1440}}, "
                        "100% or 25%, I0 U[1e4, 1e5], 20-50 Bregman x 5 CG, Poisson arrivals",
-           "stable_if": "offered rate below the capacity (capacity_mixed: a 150-request backlog's drain rate)"}
+           "stable_if": "offered rate below the capacity (capacity_mixed: a 150-request backlog's drain rate)",
+           "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "4 (HIP default)"), "max_active_groups": k}
     for prec in ("fp32", "mixed_f16"):
-        out[prec] = serve_run(torch, reqs, prec, a.serve_rate, a.serve_rate, a.serve_capacity, a.serve_warmup)
+        out[prec] = serve_run(torch, reqs, prec, a.serve_rate, a.serve_rate, a.serve_capacity, a.serve_warmup, k)
     sweep = []
     for rate in (20.0, 30.0):
         sub = reqs[:150]
-        sweep.append(serve_run(torch, sub, "mixed_f16", rate, a.serve_rate, a.serve_capacity, 15))
+        sweep.append(serve_run(torch, sub, "mixed_f16", rate, a.serve_rate, a.serve_capacity, 15, k))
     sweep.append(out["mixed_f16"])
     out["rate_sweep_mixed"] = [{k: s[k] for k in ("offered_rate_per_s", "recon_per_s", "p50_s", "p99_s",
                                                   "latency_growth")} for s in sweep]
-    burst = serve_run(torch, reqs[:150], "mixed_f16", 0.0, a.serve_rate, a.serve_capacity, 0)
+    burst = serve_run(torch, reqs[:150], "mixed_f16", 0.0, a.serve_rate, a.serve_capacity, 0, k)
     out["capacity_mixed"] = {"requests": burst["requests"], "recon_per_s": burst["recon_per_s"],
                              "wall_s": burst["wall_s"], "note": "all requests arrive at once"}
     out["max_stable_rate_per_s"] = burst["recon_per_s"]

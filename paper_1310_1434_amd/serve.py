@@ -186,11 +186,14 @@ class GpuExecutor:
 
 class Server:
     def __init__(self, executor, hbm_budget: int, capacity: int, clock=time.perf_counter, sleep=time.sleep,
-                 depth: int = 2):
+                 depth: int = 2, max_active: int | None = None):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.capacity = capacity
         self.depth = depth
+        # at most this many groups get new steps at a time, those whose oldest
+        # active request arrived first (None: every group with work)
+        self.max_active = max_active
         self.clock, self.sleep = clock, sleep
         self.groups: dict[tuple, Group] = {}
         self.pending: deque[Request] = deque()
@@ -273,9 +276,14 @@ class Server:
             g.slots[slot] = req
             self.pending.remove(req)
             busy = True
-        # 3. keep up to `depth` steps in flight in every group with work
-        for g in self.groups.values():
-            if g.slots and self.ex.in_flight(g) < self.depth:
+        # 3. keep up to `depth` steps in flight in every group with work (or in
+        #    the max_active groups holding the oldest requests)
+        work = [g for g in self.groups.values() if g.slots]
+        if self.max_active is not None and len(work) > self.max_active:
+            work.sort(key=lambda g: min((r.arrival, r.rid) for r in g.slots.values()))
+            work = work[:self.max_active]
+        for g in work:
+            if self.ex.in_flight(g) < self.depth:
                 if self.ex.step(g):
                     self.steps += 1
                     busy = True

@@ -150,3 +150,36 @@ def test_steps_are_enqueued_ahead_but_never_past_a_slot_end():
     t2, p2 = finish_time(2)
     assert p1 == 1 and p2 == 2
     assert t2 < t1
+
+
+def test_max_active_steps_the_groups_holding_the_oldest_requests():
+    """With max_active groups stepping at a time, the group whose oldest request
+    arrived first gets the steps; a later group waits until that request is
+    done, then gets its turn (no group starves: every request completes)."""
+    ex = FakeExecutor(lambda g: 1, lambda g, k: 0.01)
+    srv = Server(ex, 10, 2, clock=ex.clock, sleep=ex.sleep, max_active=1)
+    steps = []
+    step = ex.step
+
+    def logged(g):
+        k = step(g)
+        if k:
+            steps.append((ex.now, g.key))
+        return k
+
+    ex.step = logged
+    reqs = [make(0, G1, 5, 0.0), make(1, G2, 3, 0.001), make(2, G1, 2, 0.03)]
+    done = srv.run(reqs, idle_sleep=0.002)
+    assert all(r.error is None for r in done)
+    keys = [k for _, k in steps]
+    first_g2 = next(i for i, k in enumerate(keys) if k != keys[0])
+    # G1 runs request 0's five iterations (request 2 joins it for one); then
+    # G2's request, older than request 2, gets the steps; request 2 ends last
+    assert first_g2 == 5 and keys[5:8] == [keys[5]] * 3 and keys[8:] == [keys[0]]
+    assert done[2].finished > done[1].finished
+    assert done[0].finished <= done[1].finished
+    # without the limit both groups step from the start
+    ex2 = FakeExecutor(lambda g: 1, lambda g, k: 0.01)
+    srv2 = Server(ex2, 10, 2, clock=ex2.clock, sleep=ex2.sleep)
+    done2 = srv2.run([make(0, G1, 5, 0.0), make(1, G2, 3, 0.001), make(2, G1, 2, 0.03)], idle_sleep=0.002)
+    assert done2[1].finished < done[1].finished
