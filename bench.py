@@ -36,6 +36,7 @@ import time
 
 import numpy as np
 
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -87,7 +88,9 @@ def parse():
     ap.add_argument("--serve-warmup", type=int, default=30, help="first requests left out of the latency figures")
     ap.add_argument("--serve-rate", type=float, default=40.0, help="offered load, requests per second")
     ap.add_argument("--serve-capacity", type=int, default=8, help="slots per geometry group")
-    ap.add_argument("--serve-max-active", type=int, default=0,
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="GPU_MAX_HW_QUEUES for this process (1-32; 0 keeps the environment's value)")
+    ap.add_argument("--serve-max-active", type=int, default=4,
                     help="groups stepping at a time, those holding the oldest requests (0: all)")
     ap.add_argument("--serve-precision", default="mixed_f16", choices=["fp32", "mixed_f16", "mixed_bf16"])
     ap.add_argument("--quality", action="store_true",
@@ -499,7 +502,7 @@ def serve_leg(torch, a):
     out = {"workload": f"{len(reqs)} requests: n in {{256, 512, 768}}, views in {{180, 360, 720, 1440}}, "
                        "100% or 25%, I0 U[1e4, 1e5], 20-50 Bregman x 5 CG, Poisson arrivals",
            "stable_if": "offered rate below the capacity (capacity_mixed: a 150-request backlog's drain rate)",
-           "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "4 (HIP default)"), "max_active_groups": k}
+           "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"), "max_active_groups": k}
     for prec in ("fp32", "mixed_f16"):
         out[prec] = serve_run(torch, reqs, prec, a.serve_rate, a.serve_rate, a.serve_capacity, a.serve_warmup, k)
     sweep = []
@@ -654,6 +657,15 @@ def c2_leg(torch, air, w, B, steps, warmup, precisions, golden):
 
 def main():
     a = parse()
+    # HIP maps streams onto GPU_MAX_HW_QUEUES hardware queues (4 by default):
+    # the serving leg runs one stream per geometry group, and groups whose
+    # streams share a queue cannot overlap.  HIP reads it when it initialises,
+    # so it is set here, before anything imports torch.
+    if not 0 <= a.hw_queues <= 32:
+        print("bench.py: --hw-queues takes 1 to 32 (0 keeps the environment's value)", file=sys.stderr)
+        sys.exit(2)
+    if a.hw_queues:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(a.hw_queues)
     if a.gpus != 1:
         print(f"bench.py: measures one GPU; --gpus {a.gpus} is not supported (independent reconstructions "
               "shard across GPUs with no communication; this build runs on one GPU)", file=sys.stderr)

@@ -178,6 +178,27 @@ def test_gpu_adjoint_is_exact_transpose(air, torch_mod, g):
     assert (A > 0).sum() > nr
 
 
+@pytest.mark.parametrize("g", [Geometry("parallel", n=1, pixel=1.0, n_views=6, n_bins=5, bin=0.7),
+                               Geometry("fan", n=2, pixel=1.0, n_views=7, n_bins=9, bin=0.6, sod=20.0, sdd=35.0),
+                               Geometry("fan", n=3, pixel=0.9, n_views=8, n_bins=12, bin=0.5, sod=25.0, sdd=40.0),
+                               Geometry("fan", n=17, pixel=1.0, n_views=9, n_bins=31, bin=1.0, sod=60.0, sdd=100.0),
+                               Geometry("parallel", n=33, pixel=1.0, n_views=11, n_bins=50, bin=0.9)],
+                         ids=["n1", "n2", "n3", "n17", "n33"])
+def test_gpu_adjoint_is_exact_transpose_at_image_edges(air, torch_mod, g):
+    """The same bit-for-bit transpose on images whose last tile starts on the
+    last row or column (n = 17, 33) or that are smaller than a pixel pair
+    (n = 1, 2, 3): the backprojector's window table covers the clamped
+    stand-in pixels of pairs cut by the image edge."""
+    n, nr = g.n, g.n_views * g.n_bins
+    plan = air.Plan(g, max_batch=max(n * n, nr))
+    t = torch_mod
+    A = host(plan.project(t.eye(n * n, device="cuda").reshape(n * n, n, n))).reshape(n * n, nr).T
+    At = host(plan.filtered_backproject(t.eye(nr, device="cuda").reshape(nr, g.n_views, g.n_bins), 0))
+    At = At.reshape(nr, n * n).T
+    assert np.array_equal(A.T, At)
+    assert (A > 0).sum() >= n * n
+
+
 def test_gpu_adjoint_dot_product_c2(air, torch_mod):
     g = geom("c2")
     plan = air.Plan(g, max_batch=1)
