@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void k_cg_xr(CgArgs a) {
         a.r[idx] = rn;
         part = (double)rn * (double)rn;
     }
-    const int nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
+    const int nblk = gridDim.x * gridDim.y, blk = (j0 / 16) * gridDim.x + i0 / 16;
     block_partial<256>(part, a.partial + (size_t)b * nblk + blk);
 }
 
@@ -128,6 +128,19 @@ __device__ __forceinline__ float fl_h(int m, int off) {
 
 __device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
+// The 16x16 tile of a framelet block.  Blocks reach the eight XCDs round-robin;
+// when the tile grid divides into eight, block L works on tile (L mod 8) T/8 +
+// L/8 (T tiles, row-major), so each XCD covers one contiguous band of tile rows
+// and the halo rows and cache lines that neighbouring tiles share stay in its
+// L2.  The block's partial sum keeps the tile's own index.
+__device__ __forceinline__ void framelet_tile(int& i0, int& j0) {
+    const int gx = gridDim.x, T = gx * gridDim.y;
+    int t = blockIdx.y * gx + blockIdx.x;
+    if (T % 8 == 0) t = (t % 8) * (T / 8) + t / 8;
+    i0 = (t % gx) * 16;
+    j0 = (t / gx) * 16;
+}
+
 // All nine bands of W x at pixel (i, j), periodic boundary.
 __device__ __forceinline__ void framelet_at(const float* __restrict__ xb, int n, int i, int j, float z[9]) {
     float rowf[3][3];   // [dy][m_x]: filtered along x
@@ -168,7 +181,9 @@ __device__ __forceinline__ float framelet_adj_at(const float* __restrict__ zb, i
 }
 
 __global__ __launch_bounds__(256) void k_framelet_fwd(const float* __restrict__ x, float* __restrict__ z, int n) {
-    const int i = blockIdx.x * 16 + (threadIdx.x & 15), j = blockIdx.y * 16 + (threadIdx.x >> 4), b = blockIdx.z;
+    int i0, j0;
+    framelet_tile(i0, j0);
+    const int i = i0 + (threadIdx.x & 15), j = j0 + (threadIdx.x >> 4), b = blockIdx.z;
     if (i >= n || j >= n) return;
     const size_t np = (size_t)n * n;
     float zz[9];
@@ -178,7 +193,9 @@ __global__ __launch_bounds__(256) void k_framelet_fwd(const float* __restrict__ 
 }
 
 __global__ __launch_bounds__(256) void k_framelet_adj(const float* __restrict__ z, float* __restrict__ x, int n) {
-    const int i = blockIdx.x * 16 + (threadIdx.x & 15), j = blockIdx.y * 16 + (threadIdx.x >> 4), b = blockIdx.z;
+    int i0, j0;
+    framelet_tile(i0, j0);
+    const int i = i0 + (threadIdx.x & 15), j = j0 + (threadIdx.x >> 4), b = blockIdx.z;
     if (i >= n || j >= n) return;
     const size_t np = (size_t)n * n;
     x[b * np + (size_t)j * n + i] = framelet_adj_at(z + (size_t)b * 9 * np, n, i, j);
@@ -187,7 +204,9 @@ __global__ __launch_bounds__(256) void k_framelet_adj(const float* __restrict__ 
 // rhs = g + mu W^T e
 __global__ __launch_bounds__(256) void k_tf_rhs(const float* __restrict__ g, const float* __restrict__ e, float mu,
                                                 float* __restrict__ rhs, int n) {
-    const int i = blockIdx.x * 16 + (threadIdx.x & 15), j = blockIdx.y * 16 + (threadIdx.x >> 4), b = blockIdx.z;
+    int i0, j0;
+    framelet_tile(i0, j0);
+    const int i = i0 + (threadIdx.x & 15), j = j0 + (threadIdx.x >> 4), b = blockIdx.z;
     if (i >= n || j >= n) return;
     const size_t np = (size_t)n * n, idx = b * np + (size_t)j * n + i;
     rhs[idx] = fmaf(mu, framelet_adj_at(e + (size_t)b * 9 * np, n, i, j), g[idx]);
@@ -197,7 +216,9 @@ __global__ __launch_bounds__(256) void k_tf_rhs(const float* __restrict__ g, con
 // bands 1..8 (band 0: d = v, b stays 0); b <- v - d; e <- d - b (what the next
 // right-hand side needs); resid = ||z - d||_2.
 __global__ __launch_bounds__(256) void k_tf_shrink(TfArgs a) {
-    const int i = blockIdx.x * 16 + (threadIdx.x & 15), j = blockIdx.y * 16 + (threadIdx.x >> 4), b = blockIdx.z;
+    int i0, j0;
+    framelet_tile(i0, j0);
+    const int i = i0 + (threadIdx.x & 15), j = j0 + (threadIdx.x >> 4), b = blockIdx.z;
     const int n = a.n;
     const size_t np = (size_t)n * n;
     double part = 0.0;
@@ -221,13 +242,15 @@ __global__ __launch_bounds__(256) void k_tf_shrink(TfArgs a) {
             part = fma(dz, dz, part);
         }
     }
-    const int nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
+    const int nblk = gridDim.x * gridDim.y, blk = (j0 / 16) * gridDim.x + i0 / 16;
     block_partial<256>(part, a.partial + (size_t)b * nblk + blk);
 }
 
 // Forward-backward splitting, proximal step part 1: e = shrink(W x, thr), band 0 kept.
 __global__ __launch_bounds__(256) void k_fbs_shrink(TfArgs a) {
-    const int i = blockIdx.x * 16 + (threadIdx.x & 15), j = blockIdx.y * 16 + (threadIdx.x >> 4), b = blockIdx.z;
+    int i0, j0;
+    framelet_tile(i0, j0);
+    const int i = i0 + (threadIdx.x & 15), j = j0 + (threadIdx.x >> 4), b = blockIdx.z;
     const int n = a.n;
     if (i >= n || j >= n) return;
     const size_t np = (size_t)n * n, pix = (size_t)j * n + i;
@@ -244,7 +267,9 @@ __global__ __launch_bounds__(256) void k_fbs_shrink(TfArgs a) {
 
 // part 2: X_new = W^T e over X (= a.bb), partial sums of (X_new - X)^2.
 __global__ __launch_bounds__(256) void k_fbs_adjoint(TfArgs a) {
-    const int i = blockIdx.x * 16 + (threadIdx.x & 15), j = blockIdx.y * 16 + (threadIdx.x >> 4), b = blockIdx.z;
+    int i0, j0;
+    framelet_tile(i0, j0);
+    const int i = i0 + (threadIdx.x & 15), j = j0 + (threadIdx.x >> 4), b = blockIdx.z;
     const int n = a.n;
     const size_t np = (size_t)n * n;
     double part = 0.0;
@@ -255,7 +280,7 @@ __global__ __launch_bounds__(256) void k_fbs_adjoint(TfArgs a) {
         part = dx * dx;
         a.bb[idx] = xn;
     }
-    const int nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
+    const int nblk = gridDim.x * gridDim.y, blk = (j0 / 16) * gridDim.x + i0 / 16;
     block_partial<256>(part, a.partial + (size_t)b * nblk + blk);
 }
 
