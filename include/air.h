@@ -277,6 +277,12 @@ air_status air_state_step(air_state state, int32_t max_iters, hipStream_t stream
 /* Host-side bookkeeping, no GPU call. */
 air_status air_state_query(air_state state, int32_t slot, int32_t* iters_done, int32_t* n_outer);
 air_status air_state_active(air_state state, int32_t* count);
+/* Which slots are finished (active and through all their Bregman iterations),
+ * as a host bitmask: bit s % 32 of done_mask[s / 32] for slot s; done_mask has
+ * (capacity + 31) / 32 words.  Host-side bookkeeping, no GPU call: the
+ * iterations counted are those queued by air_state_step, so a finished slot's
+ * last step may still be running (air_state_retire orders its copies after it). */
+air_status air_state_poll(air_state state, int32_t* done_mask);
 /* Copy the slot's image (device [n][n], may be NULL) and residual history
  * (device [n_outer] float64 ||W X - d||, may be NULL) out, then free the slot.
  * Synchronises `stream` once, to read the slot's residual history on the host:

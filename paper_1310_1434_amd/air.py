@@ -84,6 +84,7 @@ SIGNATURES = {
     "air_state_step": ([_P, _I, _P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "air_state_query": ([_P, _I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "air_state_active": ([_P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "air_state_poll": ([_P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "air_state_retire": ([_P, _I, _P, _P, _P], ctypes.c_int),
     "air_state_snapshot_size": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "air_state_snapshot": ([_P, _I, _P, _P], ctypes.c_int),
@@ -390,6 +391,13 @@ class State:
         done = ctypes.c_int32()
         _check(lib.air_state_step(self._h, int(max_iters), self._s(), ctypes.byref(done)), "air_state_step")
         return int(done.value)
+
+    def finished(self) -> list[int]:
+        """Slots through all their iterations (air_state_poll's bitmask)."""
+        words = (self.capacity + 31) // 32
+        mask = (ctypes.c_int32 * words)()
+        _check(lib.air_state_poll(self._h, mask), "air_state_poll")
+        return [s for s in range(self.capacity) if (mask[s // 32] & 0xFFFFFFFF) >> (s % 32) & 1]
 
     def query(self, slot: int):
         it, no = ctypes.c_int32(), ctypes.c_int32()

@@ -272,6 +272,16 @@ air_status air_state_active(air_state st, int32_t* count) {
     return AIR_OK;
 }
 
+air_status air_state_poll(air_state st, int32_t* done_mask) {
+    if (!st || !done_mask) return fail(AIR_E_INVALID, "null pointer");
+    const int words = (st->capacity + 31) / 32;
+    for (int w = 0; w < words; w++) done_mask[w] = 0;
+    for (int slot = 0; slot < st->capacity; slot++)
+        if (st->pos_of[slot] >= 0 && st->iters[slot] >= st->n_outer[slot])
+            done_mask[slot / 32] = (int32_t)((uint32_t)done_mask[slot / 32] | (1u << (slot % 32)));
+    return AIR_OK;
+}
+
 air_status air_state_retire(air_state st, int32_t slot, float* X_out, double* resid_out, hipStream_t s) {
     if (air_status e = check_slot(st, slot)) return e;
     const int pos = st->pos_of[slot];

@@ -58,15 +58,19 @@ def test_continuous_batching_is_bit_identical_to_solo(env):
     results = {}
     running[0] = st.admit(ys[0], n_outer=6)
     running[1] = st.admit(ys[1], n_outer=3)
+    assert st.finished() == []
     assert st.step(10) == 3                    # limited by request 1
+    assert st.finished() == [running[1]]       # air_state_poll: request 1 is through
     running[2] = st.admit(ys[2], n_outer=5)    # arrives while request 0 runs
     results[1] = finish(st, running.pop(1))    # its slot is freed; request 2 moves into its place
     running[3] = st.admit(ys[3], n_outer=4)    # reuses the freed slot id
     while running:
         assert st.step(1) == 1
+        done = st.finished()
         for req, slot in list(running.items()):
             it, no = st.query(slot)
             assert no == n_outer[req]
+            assert (slot in done) == (it == no)
             if it == no:
                 results[req] = finish(st, running.pop(req))
     assert st.active == 0
