@@ -174,6 +174,14 @@ def instrumented(torch, air, plan, y, w, ws, mode, n_outer):
     return {k: {"avg_ms": (v[0] / v[1]) if v[1] else 0.0, "launches": v[1], "total_ms": v[0]} for k, v in kt.items()}
 
 
+def operator_applies(kind, n_outer, n_cg):
+    """Launches of one operator per image in a split-Bregman solve: the CG
+    products, the start image's residual (one apply at the start: later CG runs
+    start from the carried residual) and, for the ramp and the backprojector,
+    A'^T Y."""
+    return n_outer * n_cg + (1 if kind == "project" else 2)
+
+
 def roofline(kernel_ms, g, B, n_outer, n_cg, rsteps, precision, label):
     """The dominant kernel of an instrumented solve on its roofline.  Images per
     launch follow from the launch count (a split batch launches each operator
@@ -181,9 +189,7 @@ def roofline(kernel_ms, g, B, n_outer, n_cg, rsteps, precision, label):
     dom = max(("project", "backproject", "ramp"), key=lambda k: kernel_ms[k]["total_ms"])
     km = kernel_ms[dom]
     t = km["avg_ms"] * 1e-3
-    applies = {"project": n_outer * (1 + n_cg), "backproject": 1 + n_outer * (1 + n_cg),
-               "ramp": 1 + n_outer * (1 + n_cg)}[dom]
-    ipl = B * applies / km["launches"]
+    ipl = B * operator_applies(dom, n_outer, n_cg) / km["launches"]
     if dom == "ramp":
         flops = 2.0 * ipl * g.n_views * g.n_bins * g.n_bins
         peak = MFMA_PEAK_TFLOPS["fp32" if precision == "fp32" else precision]
@@ -766,7 +772,7 @@ def main():
     rays_launch = g.n_views * g.n_bins
     for kind, key in (("project", "proj_grays_s"), ("backproject", "backproj_grays_s")):
         k = km[kind]
-        ipl = B * (n_outer * (1 + w.n_cg) + (kind == "backproject")) / k["launches"] if k["launches"] else 0
+        ipl = B * operator_applies(kind, n_outer, w.n_cg) / k["launches"] if k["launches"] else 0
         out[key] = ipl * rays_launch / (k["avg_ms"] * 1e-3) / 1e9 if k["avg_ms"] else None
     out["grays_note"] = "rays per launch / launch duration in the instrumented solve (kernel_ms_config)"
     out["kernel_source_hash"] = kernel_source_hash()

@@ -202,6 +202,12 @@ air_status air_solve_workspace_size(air_plan plan, int32_t batch, size_t* bytes)
  *                   v = W X + b; d = shrink(v, lambda / (2 mu)) on bands 1..8,
  *                   d = v on band 0; b = v - d
  * L2 (reg = 1): n_cg CG steps on (A'^T A + lambda I) X = A'^T Y from X.
+ * The residual each CG run starts from, rhs - M X (M the system matrix), is
+ * not recomputed with an operator apply: the call computes c = g - M X once
+ * for the start image, every CG run's last step carries it forward
+ * (c = its recursive residual minus mu W^T (d - b)), and a run starts from
+ * c + mu W^T (d - b): equal in exact arithmetic, one apply per outer
+ * iteration fewer.
  * Forward-backward splitting (reg = 2; Methods, Eq. (6) and the proximal step):
  *   n_outer times:  X' = X - mu A'^T (A X - Y)
  *                   X  = W^T shrink(W X', mu lambda / 2)   (band 0 passes through)
@@ -267,8 +273,10 @@ air_status air_state_create(air_plan plan, int32_t capacity, const air_solve_par
                             air_state* out);
 void air_state_destroy(air_state state);
 /* Start a reconstruction in a free slot: g = A'^T Y, b = d = 0, X = X0 (device
- * [n][n]) or zeros when X0 is NULL.  Y: device [V][D].  n_outer in [1, the
- * state's n_outer].  *slot receives the slot id.  AIR_E_NOMEM if all slots are busy. */
+ * [n][n]) or zeros when X0 is NULL, and the carried residual g - M X (see
+ * air_solve; one operator apply when X0 is given).  Y: device [V][D].  n_outer
+ * in [1, the state's n_outer].  *slot receives the slot id.  AIR_E_NOMEM if
+ * all slots are busy. */
 air_status air_state_admit(air_state state, const float* Y, const float* X0, int32_t n_outer, hipStream_t stream,
                            int32_t* slot);
 /* Advance every active slot by k = min(max_iters, the fewest iterations any
@@ -289,7 +297,7 @@ air_status air_state_poll(air_state state, int32_t* done_mask);
  * if any of its values is not finite (a non-finite input or a diverged solve),
  * the slot is still copied out and freed, and the call returns AIR_E_NONFINITE. */
 air_status air_state_retire(air_state state, int32_t slot, float* X_out, double* resid_out, hipStream_t stream);
-/* Checkpoint: the slot's whole continuation state (X, g, b, d - b, residual
+/* Checkpoint: the slot's whole continuation state (X, g - M X, b, d - b, residual
  * history, iteration count) to a host buffer of air_state_snapshot_size bytes.
  * The copy is asynchronous: synchronise `stream` before reading the buffer.
  * Restore admits it into a free slot of a state with the same geometry and

@@ -178,9 +178,17 @@ struct CgArgs {
     const double* alpha;        // [batch] (update_xr)
     const double* beta;         // [batch] (update_p)
     double* partial;            // [batch][tiles16(n)] partial sums of r . r (update_xr)
+    float* c;                   // carried residual g - M x (update_xc)
+    const float* e;             // [batch][9][n][n] d - b, or null (update_xc)
+    float mu;                   // (update_xc)
 };
 hipError_t launch_cg_update_xr(const CgArgs& a, int batch, hipStream_t s);   // x += a p, r -= a q; partials of r.r
-hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s);    // p = r + b p, and its pad
+hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s);    // p = r + b p (p = r if !beta), and its pad
+// last CG step: x += a p, c = (r - a q) - mu W^T e (no partials)
+hipError_t launch_cg_update_xc(const CgArgs& a, int batch, hipStream_t s);
+// start of an L2 sub-problem: r = c + mu W^T e (r = c if e is null); partials of r.r
+hipError_t launch_cg_start(int n, const float* c, const float* e, float mu, float* r, double* partial, int batch,
+                           hipStream_t s);
 
 // Fixed-order sums of the block partials [batch][nblk] and the scalars derived from them:
 enum FinalizeMode {
@@ -195,8 +203,6 @@ hipError_t launch_finalize(int mode, const double* partial, int nblk, int batch,
 // Framelet kernels.
 hipError_t launch_framelet_fwd(int n, const float* x, float* z, int batch, hipStream_t s);
 hipError_t launch_framelet_adj(int n, const float* z, float* x, int batch, hipStream_t s);
-// rhs = g + mu W^T e
-hipError_t launch_tf_rhs(int n, const float* g, const float* e, float mu, float* rhs, int batch, hipStream_t s);
 // v = W x + b (bands 1..8 of b), d = shrink(v, thr) (band 0: d = v), b <- v - d, e <- d - b;
 // partial sums of ||W x - d||^2.
 struct TfArgs {

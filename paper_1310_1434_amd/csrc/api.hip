@@ -474,7 +474,7 @@ static air_status part_begin(air_plan p, const float* Y, float* X, int b0, int n
     } else {
         B.iters = nullptr;          // residual norms go to scratch, one slot per image
     }
-    return solve_init(p, B, Y + b0 * nyv, nb, solve_setup(prm), s);
+    return solve_init(p, B, Y + b0 * nyv, nb, solve_setup(prm), false, s);
 }
 
 static air_status check_solve(air_plan p, const float* Y, float* X, int32_t batch, const air_solve_params* prm) {

@@ -30,7 +30,8 @@ __global__ __launch_bounds__(256) void k_cg_xr(CgArgs a) {
     block_partial<256>(part, a.partial + (size_t)b * nblk + blk);
 }
 
-// p = r + beta p for a group of G images; p also goes to its padded line sets.
+// p = r + beta p (p = r without beta) for a group of G images; p also goes to
+// its padded line sets.
 template <int G>
 __global__ __launch_bounds__(256) void k_cg_p(CgArgs a, int batch) {
     __shared__ float lds[16 * 17 * G];
@@ -45,7 +46,8 @@ __global__ __launch_bounds__(256) void k_cg_p(CgArgs a, int batch) {
         const int b = b0 + q;
         if (valid && b < batch) {
             const size_t idx = (size_t)b * n * n + (size_t)j * n + i;
-            pn[q] = (float)fma(a.beta[b], (double)a.p[idx], (double)a.r[idx]);
+            // (no beta: the first direction of a CG run, p = r)
+            pn[q] = a.beta ? (float)fma(a.beta[b], (double)a.p[idx], (double)a.r[idx]) : a.r[idx];
             a.p[idx] = pn[q];
         }
     }
@@ -201,15 +203,42 @@ __global__ __launch_bounds__(256) void k_framelet_adj(const float* __restrict__ 
     x[b * np + (size_t)j * n + i] = framelet_adj_at(z + (size_t)b * 9 * np, n, i, j);
 }
 
-// rhs = g + mu W^T e
-__global__ __launch_bounds__(256) void k_tf_rhs(const float* __restrict__ g, const float* __restrict__ e, float mu,
-                                                float* __restrict__ rhs, int n) {
+// Start residual of an L2 sub-problem: r = c + mu W^T e (r = c without e),
+// where c = g - M x carries the data part of the residual from the previous
+// sub-problem (M = A'^T A + mu I); partial sums of r . r.
+__global__ __launch_bounds__(256) void k_cg_start(const float* __restrict__ c, const float* __restrict__ e, float mu,
+                                                  float* __restrict__ r, double* __restrict__ partial, int n) {
     int i0, j0;
     framelet_tile(i0, j0);
     const int i = i0 + (threadIdx.x & 15), j = j0 + (threadIdx.x >> 4), b = blockIdx.z;
+    const size_t np = (size_t)n * n;
+    double part = 0.0;
+    if (i < n && j < n) {
+        const size_t idx = b * np + (size_t)j * n + i;
+        const float rv = e ? fmaf(mu, framelet_adj_at(e + (size_t)b * 9 * np, n, i, j), c[idx]) : c[idx];
+        r[idx] = rv;
+        part = (double)rv * (double)rv;
+    }
+    const int nblk = gridDim.x * gridDim.y, blk = (j0 / 16) * gridDim.x + i0 / 16;
+    block_partial<256>(part, partial + (size_t)b * nblk + blk);
+}
+
+// Last CG step of an L2 sub-problem: x += alpha p, and instead of r the carried
+// part c = (r - alpha q) - mu W^T e (c = r - alpha q without e).  r - alpha q
+// is the step's recursive residual g + mu W^T e - M x, so c = g - M x for the
+// new x up to rounding, and the next sub-problem starts from c + mu W^T e'.
+__global__ __launch_bounds__(256) void k_cg_xc(CgArgs a) {
+    int i0, j0;
+    framelet_tile(i0, j0);
+    const int i = i0 + (threadIdx.x & 15), j = j0 + (threadIdx.x >> 4), b = blockIdx.z;
+    const int n = a.n;
     if (i >= n || j >= n) return;
     const size_t np = (size_t)n * n, idx = b * np + (size_t)j * n + i;
-    rhs[idx] = fmaf(mu, framelet_adj_at(e + (size_t)b * 9 * np, n, i, j), g[idx]);
+    const double alpha = a.alpha[b];
+    const float xn = (float)fma(alpha, (double)a.p[idx], (double)a.x[idx]);
+    const float rn = (float)fma(-alpha, (double)a.q[idx], (double)a.r[idx]);
+    a.x[idx] = xn;
+    a.c[idx] = a.e ? fmaf(-a.mu, framelet_adj_at(a.e + (size_t)b * 9 * np, n, i, j), rn) : rn;
 }
 
 // Bregman update after the L2 step: z = W x; v = z + b; d = shrink(v, thr) on
@@ -308,9 +337,16 @@ hipError_t launch_framelet_adj(int n, const float* z, float* x, int batch, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_tf_rhs(int n, const float* g, const float* e, float mu, float* rhs, int batch, hipStream_t s) {
+hipError_t launch_cg_start(int n, const float* c, const float* e, float mu, float* r, double* partial, int batch,
+                           hipStream_t s) {
     dim3 grid((n + 15) / 16, (n + 15) / 16, batch);
-    hipLaunchKernelGGL(k_tf_rhs, grid, dim3(256), 0, s, g, e, mu, rhs, n);
+    hipLaunchKernelGGL(k_cg_start, grid, dim3(256), 0, s, c, e, mu, r, partial, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update_xc(const CgArgs& a, int batch, hipStream_t s) {
+    dim3 grid((a.n + 15) / 16, (a.n + 15) / 16, batch);
+    hipLaunchKernelGGL(k_cg_xc, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -203,8 +203,8 @@ struct SolveBufs {
     float* s1;      // [batch][n_views][ds] projections
     float* s2;      // group-interleaved backprojector input (G = image_group(batch))
     float* rscale;  // [batch][n_views] per-row scales of the float16 split ramp
-    float* g;       // [batch][n][n]  A'^T Y
-    float* r;       // [batch][n][n]  right-hand side, then CG residual
+    float* g;       // [batch][n][n]  A'^T Y; split Bregman and L2: g - M X after solve_init (M = A'^T A + mu I)
+    float* r;       // [batch][n][n]  CG residual
     float* p;       // [batch][n][n]
     float* q;       // [batch][n][n]
     float* bb;      // [batch][8][n][n] Bregman b (bands 1..8)
@@ -238,7 +238,10 @@ PadBuf plan_pad(const air_plan_s* p, float* pad, float* scale);
 air_status build_pad(air_plan p, const float* x, const PadBuf& pad, double* partial, int batch, hipStream_t s);
 
 // g = A'^T Y (or A^T Y); zero b and e.  Y: [batch][V][D] (public layout).
-air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch, const SolveSetup& st, hipStream_t s);
+// Split Bregman and L2: then g -= M X (one operator apply; none if x_zero,
+// X = 0), the carried residual every L2 sub-problem starts from.
+air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch, const SolveSetup& st, bool x_zero,
+                      hipStream_t s);
 // One outer iteration (split Bregman) or the whole CG run (L2) for images [0, batch).
 air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSetup& st, hipStream_t s);
 

@@ -56,7 +56,8 @@ SolveBufs solve_bufs(const air_plan_s* p, const SolveLayout& L, char* w, float* 
     return B;
 }
 
-air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch, const SolveSetup& st, hipStream_t s) {
+air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch, const SolveSetup& st, bool x_zero,
+                      hipStream_t s) {
     const KGeom kg = p->kgeom();
     const int rows = batch * p->g.n_views;
     const size_t np = (size_t)p->g.n * p->g.n;
@@ -75,6 +76,24 @@ air_status solve_init(air_plan p, const SolveBufs& B, const float* Y, int batch,
         AIR_K(AIR_K_OTHER, launch_fill(B.e, (size_t)batch * 9 * np, 0.f, s));
     }
     if (B.iters) AIR_K(AIR_K_OTHER, launch_fill(reinterpret_cast<float*>(B.iters), (size_t)batch, 0.f, s));
+    // carried residual c = g - M X of the start image, in place of g (the
+    // iterations never read g itself again); M 0 = 0, so c = g for X = 0
+    if (st.reg != 2 && !x_zero) {
+        const PadBuf pad = plan_pad(p, B.pad, B.pscale);
+        if (air_status e = build_pad(p, B.X, pad, B.part, batch, s)) return e;
+        AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, s));
+        if (st.filter)
+            AIR_K(AIR_K_RAMP, launch_ramp(p->prec, p->ramp_tables(B.rscale), B.s1, B.s2, rows, p->ds, RAMP_POST, grp, s));
+        else AIR_K(AIR_K_OTHER, launch_scale(kg, B.s1, B.s2, batch, grp, s));
+        BpArgs r{};
+        r.mode = BP_RESIDUAL;
+        r.mu = (float)(st.reg == 0 ? st.mu : st.lambda);
+        r.aux = B.X;
+        r.out = B.g;
+        r.p_out = B.p;      // (scratch here)
+        r.partial = B.part;
+        AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, B.s2, r, batch, s));
+    }
     return AIR_OK;
 }
 
@@ -140,7 +159,6 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
     const KGeom kg = p->kgeom();
     const RampTables rt = p->ramp_tables(B.rscale);
     const int n = p->g.n, rows = batch * p->g.n_views, nblk = tiles16(n), nblk_bp = bp_blocks(n, batch);
-    const size_t np = (size_t)n * n;
     const int grp = image_group(batch);
     const bool tf = st.reg == 0;
     const float mu_op = (float)(tf ? st.mu : st.lambda);
@@ -155,25 +173,20 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
         else AIR_K(AIR_K_OTHER, launch_scale(kg, B.s1, B.s2, batch, grp, s));
         return AIR_OK;
     };
-    if (tf) AIR_K(AIR_K_FRAMELET, launch_tf_rhs(n, B.g, B.e, (float)st.mu, B.r, batch, s));
-    else AIR_HIP(hipMemcpyAsync(B.r, B.g, (size_t)batch * np * sizeof(float), hipMemcpyDeviceToDevice, s));
-    // r = rhs - M X, p = r, rho = r.r (the padded copies of X are rebuilt here,
-    // so they never outlive a step and follow the current batch's grouping)
-    if (air_status e = build_pad(p, B.X, pad, B.part, batch, s)) return e;
-    AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, s));
-    if (air_status e = filtered()) return e;
-    {
-        BpArgs a{};
-        a.mode = BP_RESIDUAL;
-        a.mu = mu_op;
-        a.aux = B.X;
-        a.out = B.r;
-        a.p_out = B.p;
-        a.pad_out = fused;
-        a.partial = B.part;
-        AIR_K(AIR_K_BACKPROJECT, launch_backproject(kg, B.s2, a, batch, s));
-        AIR_K(AIR_K_CG, launch_finalize(FIN_RHO, B.part, nblk_bp, batch, B.rho, nullptr, nullptr, 0, nullptr, s));
-        if (pad.half && st.n_cg > 0)
+    // r = c + mu W^T e (L2: r = c), rho = r.r, p = r.  c = g - M X is carried
+    // from the last CG step of the previous outer iteration (solve_init for the
+    // first), so the start residual costs no operator apply: in exact
+    // arithmetic it is the right-hand side g + mu W^T e minus M X.
+    AIR_K(AIR_K_CG, launch_cg_start(n, B.g, tf ? B.e : nullptr, (float)st.mu, B.r, B.part, batch, s));
+    AIR_K(AIR_K_CG, launch_finalize(FIN_RHO, B.part, nblk, batch, B.rho, nullptr, nullptr, 0, nullptr, s));
+    if (st.n_cg > 0) {
+        CgArgs c0{};
+        c0.n = n;
+        c0.r = B.r;
+        c0.p = B.p;
+        c0.pad = fused;
+        AIR_K(AIR_K_CG, launch_cg_update_p(c0, batch, s));
+        if (pad.half)
             if (air_status e = build_pad(p, B.p, pad, B.part, batch, s)) return e;
     }
     for (int it = 0; it < st.n_cg; it++) {
@@ -196,14 +209,20 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
         cg.alpha = B.alpha;
         cg.beta = B.beta;
         cg.partial = B.part;
-        AIR_K(AIR_K_CG, launch_cg_update_xr(cg, batch, s));
-        if (it < st.n_cg - 1) {
-            AIR_K(AIR_K_CG, launch_finalize(FIN_BETA, B.part, nblk, batch, B.rho, B.beta, nullptr, 0, nullptr, s));
-            cg.pad = fused;
-            AIR_K(AIR_K_CG, launch_cg_update_p(cg, batch, s));
-            if (pad.half)
-                if (air_status e = build_pad(p, B.p, pad, B.part, batch, s)) return e;
+        if (it == st.n_cg - 1) {
+            // the last step leaves c = g - M X for the next outer iteration
+            cg.c = B.g;
+            cg.e = tf ? B.e : nullptr;
+            cg.mu = (float)st.mu;
+            AIR_K(AIR_K_CG, launch_cg_update_xc(cg, batch, s));
+            break;
         }
+        AIR_K(AIR_K_CG, launch_cg_update_xr(cg, batch, s));
+        AIR_K(AIR_K_CG, launch_finalize(FIN_BETA, B.part, nblk, batch, B.rho, B.beta, nullptr, 0, nullptr, s));
+        cg.pad = fused;
+        AIR_K(AIR_K_CG, launch_cg_update_p(cg, batch, s));
+        if (pad.half)
+            if (air_status e = build_pad(p, B.p, pad, B.part, batch, s)) return e;
     }
     if (tf) {
         TfArgs t{};

@@ -1,10 +1,11 @@
 // Device-resident solve slots for continuous batching (air_state_*).
 //
 // A state holds up to `capacity` split-Bregman reconstructions of one plan's
-// geometry.  Every slot keeps its image X, g = A'^T Y, the Bregman variables
-// b and e = d - b, its residual history and its iteration counter on the
-// device; the CG state is rebuilt at the start of every outer iteration, so
-// nothing else needs to persist.  Active slots are kept packed at positions
+// geometry.  Every slot keeps its image X, the carried residual
+// c = A'^T Y - (A'^T A + mu I) X, the Bregman variables b and e = d - b, its
+// residual history and its iteration counter on the device; the CG state is
+// rebuilt from them at the start of every outer iteration, so nothing else
+// needs to persist.  Active slots are kept packed at positions
 // [0, nact): retiring a slot moves the last active one into its place (a few
 // device copies), so every step runs the batched kernels on a dense batch.
 // Each image's arithmetic does not depend on its neighbours, so a slot's
@@ -207,7 +208,7 @@ air_status air_state_admit(air_state st, const float* Y, const float* X0, int32_
         const hipError_t h = launch_fill(reinterpret_cast<float*>(b.resid), 2 * (size_t)st->max_outer, 0.f, s);
         if (h != hipSuccess) e = fail(AIR_E_HIP, std::string("admit: ") + hipGetErrorString(h));
     }
-    if (e == AIR_OK) e = solve_init(p, b, Y, 1, st->setup, s);
+    if (e == AIR_OK) e = solve_init(p, b, Y, 1, st->setup, X0 == nullptr, s);
     if (e != AIR_OK) {     // give the position back
         st->pos_of[slot] = -1;
         st->slot_at[pos] = -1;

@@ -48,6 +48,26 @@ def test_single_slot_matches_solve(env):
     assert st.active == 0
 
 
+def test_start_image_slot_matches_solve(env):
+    """A slot admitted with a start image (whose carried residual g - M X0
+    takes one operator apply at admission) gives the solve's bits, and a zero
+    start image the same bits as none (M 0 = 0 exactly)."""
+    torch, air, plan, ys = env
+    x0 = torch.from_numpy(np.random.default_rng(5).uniform(0, 0.02, (128, 128)).astype(np.float32)).cuda()
+    st = air.State(plan, 2, LAM, MU, NCG, max_outer=4, stream=torch.cuda.Stream())
+    a = st.admit(ys[1], x0=x0, n_outer=4)
+    z = st.admit(ys[1], x0=torch.zeros_like(x0), n_outer=4)
+    while st.query(a)[0] < 4:
+        st.step(4)
+    xa, ra = finish(st, a)
+    xz, rz = finish(st, z)
+    xs, rs = plan.solve(ys[1][None], LAM, MU, 4, NCG, x0=x0[None].clone())
+    torch.cuda.synchronize()
+    assert np.array_equal(xa, xs[0].cpu().numpy()) and np.array_equal(ra, rs[0].cpu().numpy())
+    xn, rn = solo(env, ys[1], 4)
+    assert np.array_equal(xz, xn) and np.array_equal(rz, rn)
+
+
 def test_continuous_batching_is_bit_identical_to_solo(env):
     """Requests join and leave between steps (slot ids are reused); every result
     equals its solo solve bit for bit."""
