@@ -178,16 +178,17 @@ struct CgArgs {
     const double* alpha;        // [batch] (update_xr)
     const double* beta;         // [batch] (update_p)
     double* partial;            // [batch][tiles16(n)] partial sums of r . r (update_xr)
-    float* c;                   // carried residual g - M x (update_xc)
-    const float* e;             // [batch][9][n][n] d - b, or null (update_xc)
+    float* c;                   // in: W^T e (with framelet); out: carried residual g - M x (update_xc)
+    bool framelet;              // split Bregman: subtract mu W^T e (update_xc)
     float mu;                   // (update_xc)
 };
 hipError_t launch_cg_update_xr(const CgArgs& a, int batch, hipStream_t s);   // x += a p, r -= a q; partials of r.r
 hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s);    // p = r + b p (p = r if !beta), and its pad
-// last CG step: x += a p, c = (r - a q) - mu W^T e (no partials)
+// last CG step: x += a p, c = (r - a q) - mu W^T e, W^T e read from c (no partials)
 hipError_t launch_cg_update_xc(const CgArgs& a, int batch, hipStream_t s);
-// start of an L2 sub-problem: r = c + mu W^T e (r = c if e is null); partials of r.r
-hipError_t launch_cg_start(int n, const float* c, const float* e, float mu, float* r, double* partial, int batch,
+// start of an L2 sub-problem: r = c + mu W^T e (r = c if e is null), then W^T e
+// written over c (if e); partials of r.r
+hipError_t launch_cg_start(int n, float* c, const float* e, float mu, float* r, double* partial, int batch,
                            hipStream_t s);
 
 // Fixed-order sums of the block partials [batch][nblk] and the scalars derived from them:

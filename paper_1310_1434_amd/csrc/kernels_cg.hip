@@ -160,21 +160,35 @@ __device__ __forceinline__ void framelet_at(const float* __restrict__ xb, int n,
             z[3 * my + mx] = fl_h(my, -1) * rowf[0][mx] + fl_h(my, 0) * rowf[1][mx] + fl_h(my, 1) * rowf[2][mx];
 }
 
-// (W^T z)(i, j) = sum_band sum_{dy,dx} h_{my}(dy) h_{mx}(dx) z_band(j - dy, i - dx)
+// (W^T z)(i, j) = sum_band sum_{dy,dx} h_{my}(dy) h_{mx}(dx) z_band(j - dy, i - dx).
+// The 3 x 3 neighbourhood is addressed by 32-bit byte offsets from the bands'
+// (uniform) bases (n <= 16384, so n^2 floats span less than 2^32 bytes), and
+// the terms whose filter tap is zero are left out (adding 0 * z changes no
+// finite sum).
 __device__ __forceinline__ float framelet_adj_at(const float* __restrict__ zb, int n, int i, int j) {
     const size_t np = (size_t)n * n;
+    uint32_t off[3][3];
+#pragma unroll
+    for (int dy = -1; dy <= 1; dy++) {
+        const uint32_t ro = (uint32_t)wrap(j - dy, n) * (uint32_t)n;
+#pragma unroll
+        for (int dx = -1; dx <= 1; dx++) off[dy + 1][dx + 1] = (ro + (uint32_t)wrap(i - dx, n)) * 4u;
+    }
     float s = 0.f;
 #pragma unroll
     for (int dy = -1; dy <= 1; dy++) {
-        const size_t roff = (size_t)wrap(j - dy, n) * n;
 #pragma unroll
         for (int dx = -1; dx <= 1; dx++) {
-            const size_t off = roff + wrap(i - dx, n);
 #pragma unroll
             for (int my = 0; my < 3; my++) {
+                if (fl_h(my, dy) == 0.f) continue;
                 float t = 0.f;
 #pragma unroll
-                for (int mx = 0; mx < 3; mx++) t = fmaf(fl_h(mx, dx), zb[(3 * my + mx) * np + off], t);
+                for (int mx = 0; mx < 3; mx++) {
+                    if (fl_h(mx, dx) == 0.f) continue;
+                    const char* band = reinterpret_cast<const char*>(zb + (3 * my + mx) * np);
+                    t = fmaf(fl_h(mx, dx), *reinterpret_cast<const float*>(band + off[dy + 1][dx + 1]), t);
+                }
                 s = fmaf(fl_h(my, dy), t, s);
             }
         }
@@ -205,8 +219,10 @@ __global__ __launch_bounds__(256) void k_framelet_adj(const float* __restrict__ 
 
 // Start residual of an L2 sub-problem: r = c + mu W^T e (r = c without e),
 // where c = g - M x carries the data part of the residual from the previous
-// sub-problem (M = A'^T A + mu I); partial sums of r . r.
-__global__ __launch_bounds__(256) void k_cg_start(const float* __restrict__ c, const float* __restrict__ e, float mu,
+// sub-problem (M = A'^T A + mu I); partial sums of r . r.  With e, W^T e then
+// takes c's place (in ct: c is not read again before the sub-problem's last
+// CG step writes the next c there, and that step needs W^T e).
+__global__ __launch_bounds__(256) void k_cg_start(float* __restrict__ ct, const float* __restrict__ e, float mu,
                                                   float* __restrict__ r, double* __restrict__ partial, int n) {
     int i0, j0;
     framelet_tile(i0, j0);
@@ -215,7 +231,12 @@ __global__ __launch_bounds__(256) void k_cg_start(const float* __restrict__ c, c
     double part = 0.0;
     if (i < n && j < n) {
         const size_t idx = b * np + (size_t)j * n + i;
-        const float rv = e ? fmaf(mu, framelet_adj_at(e + (size_t)b * 9 * np, n, i, j), c[idx]) : c[idx];
+        float rv = ct[idx];
+        if (e) {
+            const float adj = framelet_adj_at(e + (size_t)b * 9 * np, n, i, j);
+            rv = fmaf(mu, adj, rv);
+            ct[idx] = adj;
+        }
         r[idx] = rv;
         part = (double)rv * (double)rv;
     }
@@ -224,21 +245,20 @@ __global__ __launch_bounds__(256) void k_cg_start(const float* __restrict__ c, c
 }
 
 // Last CG step of an L2 sub-problem: x += alpha p, and instead of r the carried
-// part c = (r - alpha q) - mu W^T e (c = r - alpha q without e).  r - alpha q
-// is the step's recursive residual g + mu W^T e - M x, so c = g - M x for the
-// new x up to rounding, and the next sub-problem starts from c + mu W^T e'.
+// part c = (r - alpha q) - mu W^T e (c = r - alpha q without e; W^T e is what
+// k_cg_start left in c's place).  r - alpha q is the step's recursive residual
+// g + mu W^T e - M x, so c = g - M x for the new x up to rounding, and the next
+// sub-problem starts from c + mu W^T e'.
 __global__ __launch_bounds__(256) void k_cg_xc(CgArgs a) {
-    int i0, j0;
-    framelet_tile(i0, j0);
-    const int i = i0 + (threadIdx.x & 15), j = j0 + (threadIdx.x >> 4), b = blockIdx.z;
+    const int i = blockIdx.x * 16 + (threadIdx.x & 15), j = blockIdx.y * 16 + (threadIdx.x >> 4), b = blockIdx.z;
     const int n = a.n;
     if (i >= n || j >= n) return;
-    const size_t np = (size_t)n * n, idx = b * np + (size_t)j * n + i;
+    const size_t idx = b * (size_t)n * n + (size_t)j * n + i;
     const double alpha = a.alpha[b];
     const float xn = (float)fma(alpha, (double)a.p[idx], (double)a.x[idx]);
     const float rn = (float)fma(-alpha, (double)a.q[idx], (double)a.r[idx]);
     a.x[idx] = xn;
-    a.c[idx] = a.e ? fmaf(-a.mu, framelet_adj_at(a.e + (size_t)b * 9 * np, n, i, j), rn) : rn;
+    a.c[idx] = a.framelet ? fmaf(-a.mu, a.c[idx], rn) : rn;
 }
 
 // Bregman update after the L2 step: z = W x; v = z + b; d = shrink(v, thr) on
@@ -337,7 +357,7 @@ hipError_t launch_framelet_adj(int n, const float* z, float* x, int batch, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_cg_start(int n, const float* c, const float* e, float mu, float* r, double* partial, int batch,
+hipError_t launch_cg_start(int n, float* c, const float* e, float mu, float* r, double* partial, int batch,
                            hipStream_t s) {
     dim3 grid((n + 15) / 16, (n + 15) / 16, batch);
     hipLaunchKernelGGL(k_cg_start, grid, dim3(256), 0, s, c, e, mu, r, partial, n);

@@ -177,9 +177,10 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
     // from the last CG step of the previous outer iteration (solve_init for the
     // first), so the start residual costs no operator apply: in exact
     // arithmetic it is the right-hand side g + mu W^T e minus M X.
-    AIR_K(AIR_K_CG, launch_cg_start(n, B.g, tf ? B.e : nullptr, (float)st.mu, B.r, B.part, batch, s));
-    AIR_K(AIR_K_CG, launch_finalize(FIN_RHO, B.part, nblk, batch, B.rho, nullptr, nullptr, 0, nullptr, s));
+    // (with no CG step X stays as it is, and so does c)
     if (st.n_cg > 0) {
+        AIR_K(AIR_K_CG, launch_cg_start(n, B.g, tf ? B.e : nullptr, (float)st.mu, B.r, B.part, batch, s));
+        AIR_K(AIR_K_CG, launch_finalize(FIN_RHO, B.part, nblk, batch, B.rho, nullptr, nullptr, 0, nullptr, s));
         CgArgs c0{};
         c0.n = n;
         c0.r = B.r;
@@ -212,7 +213,7 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
         if (it == st.n_cg - 1) {
             // the last step leaves c = g - M X for the next outer iteration
             cg.c = B.g;
-            cg.e = tf ? B.e : nullptr;
+            cg.framelet = tf;
             cg.mu = (float)st.mu;
             AIR_K(AIR_K_CG, launch_cg_update_xc(cg, batch, s));
             break;
