@@ -552,6 +552,13 @@ __device__ __forceinline__ float2 uniform_f2(const float2* p) {
 
 // Continuous detector bin of the projection of point (px, py) in view (c, s),
 // in float32 (k_bp_windows bounds its rounding); BEAM: 0 parallel, 1 fan.
+// floor(x) as an int in one instruction (x finite, within the int range).
+__device__ __forceinline__ int floor_i32(float x) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 template <int BEAM>
 __device__ __forceinline__ float bin_of(const KGeom& g, float px, float py, float c, float s) {
     if constexpr (BEAM == 0) return fmaf(fmaf(px, c, py * s), g.inv_bin, g.half_d);
@@ -652,14 +659,14 @@ hipError_t launch_bp_windows(const KGeom& g, BpWin* win, float2* winx, hipStream
 }
 
 // Weights of ray e for the pixels (i, j + q), q < PIX (scaled by 2^32, see
-// fx_wfrac), or all zero if !use.
+// fx_wfrac): exactly zero for a ray that samples none of them.
 // AX: 0 = the ray is x-driven, 1 = y-driven, 2 = either (read from the
 // table).  A pixel takes G if the first sample of the pair is the pixel's own
 // (in its interpolated index) and W if it is the one before.  Only
 // a sample with -1 <= j0 < n can match an in-image pixel: exactly the samples
 // the forward projector weights, so no range test is needed.
 template <int AX, int PIX>
-__device__ __forceinline__ void joseph_column(const RayEntry& e, bool use, int i, int j, int c0, float (&w)[PIX]) {
+__device__ __forceinline__ void joseph_column(const RayEntry& e, int i, int j, int c0, float (&w)[PIX]) {
     // (the first sample's padded index s is compared with the pixels' own,
     // which are constants of the thread)
     if constexpr (AX == 0) {
@@ -669,7 +676,7 @@ __device__ __forceinline__ void joseph_column(const RayEntry& e, bool use, int i
         const int s = fx_index(t);
         bool at[PIX + 1];     // at[k]: the first sample is on row j + k - 1
 #pragma unroll
-        for (int k = 0; k <= PIX; k++) at[k] = use && s == j + kPad + k - 1;
+        for (int k = 0; k <= PIX; k++) at[k] = s == j + kPad + k - 1;
 #pragma unroll
         for (int q = 0; q < PIX; q++) w[q] = at[q + 1] ? wg : (at[q] ? wf : 0.f);
     } else {
@@ -684,15 +691,18 @@ __device__ __forceinline__ void joseph_column(const RayEntry& e, bool use, int i
             asm volatile("" : "+v"(wg));    // keep the selection branch-free (G is not sunk into a branch)
             const int s = fx_index(t);
             const int o = (ydrv ? i : j + q) + kPad;
-            w[q] = (use && s == o) ? wg : ((use && s == o - 1) ? wf : 0.f);
+            w[q] = s == o ? wg : (s == o - 1 ? wf : 0.f);
         }
     }
 }
 
 // Accumulate the candidates [wlo, whi] (staged bins of one view, SV floats per
 // slot) into the pixels, two at a time.  The second of the last pair may be
-// slot whi + 1 (at most the spare slot past the staged bins): it holds a
-// finite value and takes weight zero.
+// slot whi + 1: a ray outside the window (the window holds every ray that
+// samples the pair, so this one samples neither pixel and its weights are
+// exactly zero), a zero-filled slot past the staged bins or the spare slot
+// (a zero ray entry samples index 0, which no pixel's index matches).  Its
+// value is finite, so it adds exactly nothing (0 * y + acc = acc).
 template <int AX, int BT, int PIX, int SV>
 __device__ __forceinline__ void bp_candidates(const RayEntry* rays, const float* vals, int wlo, int whi, int i,
                                               int j, int c0, float (&acc)[PIX][BT]) {
@@ -702,8 +712,8 @@ __device__ __forceinline__ void bp_candidates(const RayEntry* rays, const float*
         load_group<BT>(vals + w * SV, y0);
         load_group<BT>(vals + (w + 1) * SV, y1);
         float wt0[PIX], wt1[PIX];
-        joseph_column<AX, PIX>(e0, true, i, j, c0, wt0);
-        joseph_column<AX, PIX>(e1, w + 1 <= whi, i, j, c0, wt1);
+        joseph_column<AX, PIX>(e0, i, j, c0, wt0);
+        joseph_column<AX, PIX>(e1, i, j, c0, wt1);
 #pragma unroll
         for (int r = 0; r < PIX; r++)
 #pragma unroll
@@ -723,17 +733,17 @@ __device__ __forceinline__ void bp_candidates(const RayEntry* rays, const float*
 // perform the same operations in the same order.
 constexpr int kBpInLoopMin = 8;
 template <int PIX>
-__device__ __forceinline__ void joseph_pair(int axes, const RayEntry& e0, const RayEntry& e1, bool two, int i, int j,
-                                            int c0, float (&wt0)[PIX], float (&wt1)[PIX]) {
+__device__ __forceinline__ void joseph_pair(int axes, const RayEntry& e0, const RayEntry& e1, int i, int j, int c0,
+                                            float (&wt0)[PIX], float (&wt1)[PIX]) {
     if (axes == 0) {
-        joseph_column<0, PIX>(e0, true, i, j, c0, wt0);
-        joseph_column<0, PIX>(e1, two, i, j, c0, wt1);
+        joseph_column<0, PIX>(e0, i, j, c0, wt0);
+        joseph_column<0, PIX>(e1, i, j, c0, wt1);
     } else if (axes == 1) {
-        joseph_column<1, PIX>(e0, true, i, j, c0, wt0);
-        joseph_column<1, PIX>(e1, two, i, j, c0, wt1);
+        joseph_column<1, PIX>(e0, i, j, c0, wt0);
+        joseph_column<1, PIX>(e1, i, j, c0, wt1);
     } else {
-        joseph_column<2, PIX>(e0, true, i, j, c0, wt0);
-        joseph_column<2, PIX>(e1, two, i, j, c0, wt1);
+        joseph_column<2, PIX>(e0, i, j, c0, wt0);
+        joseph_column<2, PIX>(e1, i, j, c0, wt1);
     }
 }
 template <int BT, int PIX, int SV>
@@ -746,7 +756,7 @@ __device__ __forceinline__ void bp_candidates_any(int axes, const RayEntry* rays
     load_group<BT>(vals + (wlo + 1) * SV, y1);
     for (int w = wlo; w <= whi; w += 2) {
         float wt0[PIX], wt1[PIX];
-        joseph_pair<PIX>(axes, e0, e1, w + 1 <= whi, i, j, c0, wt0, wt1);
+        joseph_pair<PIX>(axes, e0, e1, i, j, c0, wt0, wt1);
 #pragma unroll
         for (int r = 0; r < PIX; r++)
 #pragma unroll
@@ -892,9 +902,10 @@ __global__ __launch_bounds__(256, BT <= 8 ? 4 : 3) void k_backproject(KGeom g, c
             // the staged slots [wlo, whi] within the window of a pixel pair whose
             // midpoint projects to km
             const int base = p * BINS;
+            // (ceil(km - lo) = -floor(lo - km): one rounding convert each)
             auto window = [&](float km, float lo, float hi, int meta, int& wlo, int& whi) {
-                wlo = max((int)ceilf(km - lo) - base, 0);
-                whi = min((int)floorf(km + hi) - base, min((meta & 0xFFFF) - 1 - base, BINS - 1));
+                wlo = max(-floor_i32(lo - km) - base, 0);
+                whi = min(floor_i32(km + hi) - base, min((meta & 0xFFFF) - 1 - base, BINS - 1));
             };
             if (mode == 1) {
 #pragma unroll
