@@ -696,21 +696,24 @@ __device__ __forceinline__ void joseph_column(const RayEntry& e, int i, int j, i
     }
 }
 
-// Accumulate the candidates [wlo, whi] (staged bins of one view, SV floats per
-// slot) into the pixels, two at a time.  The second of the last pair may be
-// slot whi + 1: a ray outside the window (the window holds every ray that
-// samples the pair, so this one samples neither pixel and its weights are
-// exactly zero), a zero-filled slot past the staged bins or the spare slot
-// (a zero ray entry samples index 0, which no pixel's index matches).  Its
-// value is finite, so it adds exactly nothing (0 * y + acc = acc).
-template <int AX, int BT, int PIX, int SV>
-__device__ __forceinline__ void bp_candidates(const RayEntry* rays, const float* vals, int wlo, int whi, int i,
-                                              int j, int c0, float (&acc)[PIX][BT]) {
+// Accumulate the candidates [wlo, whi] (the staged slots of one view, SF floats
+// each: the bin's ray entry, then its BT values) into the pixels, two at a
+// time.  The second of the last pair may be slot whi + 1: a ray outside the
+// window (the window holds every ray that samples the pair, so this one samples
+// neither pixel and its weights are exactly zero), a zero-filled slot past the
+// staged bins or the spare slot (a zero ray entry samples index 0, which no
+// pixel's index matches).  Its values are finite, so it adds exactly nothing
+// (0 * y + acc = acc).
+__device__ __forceinline__ RayEntry slot_ray(const float* p) { return *reinterpret_cast<const RayEntry*>(p); }
+template <int AX, int BT, int PIX, int SF>
+__device__ __forceinline__ void bp_candidates(const float* slots, int wlo, int whi, int i, int j, int c0,
+                                              float (&acc)[PIX][BT]) {
     for (int w = wlo; w <= whi; w += 2) {
-        const RayEntry e0 = rays[w], e1 = rays[w + 1];
+        const float* p0 = slots + w * SF;
+        const RayEntry e0 = slot_ray(p0), e1 = slot_ray(p0 + SF);
         float y0[BT], y1[BT];
-        load_group<BT>(vals + w * SV, y0);
-        load_group<BT>(vals + (w + 1) * SV, y1);
+        load_group<BT>(p0 + 4, y0);
+        load_group<BT>(p0 + SF + 4, y1);
         float wt0[PIX], wt1[PIX];
         joseph_column<AX, PIX>(e0, i, j, c0, wt0);
         joseph_column<AX, PIX>(e1, i, j, c0, wt1);
@@ -746,27 +749,21 @@ __device__ __forceinline__ void joseph_pair(int axes, const RayEntry& e0, const 
         joseph_column<2, PIX>(e1, i, j, c0, wt1);
     }
 }
-template <int BT, int PIX, int SV>
-__device__ __forceinline__ void bp_candidates_any(int axes, const RayEntry* rays, const float* vals, int wlo, int whi,
-                                                  int i, int j, int c0, float (&acc)[PIX][BT]) {
-    if (wlo > whi) return;
-    RayEntry e0 = rays[wlo], e1 = rays[wlo + 1];
-    float y0[BT], y1[BT];
-    load_group<BT>(vals + wlo * SV, y0);
-    load_group<BT>(vals + (wlo + 1) * SV, y1);
-    for (int w = wlo; w <= whi; w += 2) {
+template <int BT, int PIX, int SF>
+__device__ __forceinline__ void bp_candidates_any(int axes, const float* slots, int wlo, int whi, int i, int j,
+                                                  int c0, float (&acc)[PIX][BT]) {
+    const float* const last = slots + whi * SF;
+    for (const float* p = slots + wlo * SF; p <= last; p += 2 * SF) {
+        const RayEntry e0 = slot_ray(p), e1 = slot_ray(p + SF);
+        float y0[BT], y1[BT];
+        load_group<BT>(p + 4, y0);
+        load_group<BT>(p + SF + 4, y1);
         float wt0[PIX], wt1[PIX];
         joseph_pair<PIX>(axes, e0, e1, i, j, c0, wt0, wt1);
 #pragma unroll
         for (int r = 0; r < PIX; r++)
 #pragma unroll
             for (int q = 0; q < BT; q++) acc[r][q] = fmaf(wt1[r], y1[q], fmaf(wt0[r], y0[q], acc[r][q]));
-        if (w + 2 <= whi) {
-            e0 = rays[w + 2];
-            e1 = rays[w + 3];
-            load_group<BT>(vals + (w + 2) * SV, y0);
-            load_group<BT>(vals + (w + 3) * SV, y1);
-        }
     }
 }
 
@@ -786,11 +783,12 @@ __global__ __launch_bounds__(256, BT <= 8 ? 4 : 3) void k_backproject(KGeom g, c
     static_assert(BINS % kWave == 0, "whole wavefronts stage a view");
     // one spare slot past the staged bins, read by the second candidate of a pair
     constexpr int SLOTS = BINS + 1;
-    __shared__ __align__(16) RayEntry s_ray[NV][SLOTS];
-    // slot stride: BT floats, padded by 4 from 8 images up so that the 16-byte
-    // reads of 8 consecutive slots fall in distinct LDS banks
-    constexpr int SV = BT >= 8 ? BT + 4 : BT;
-    __shared__ __align__(16) float s_val[NV][SLOTS * SV];
+    // a slot is its bin's ray entry (4 words) and the BT values (8 words at
+    // least, so that entries stay 16-byte aligned): 12 words at 8 images, 20
+    // at 16, strides at which the 16-byte reads of 8 consecutive slots fall in
+    // distinct LDS banks; one address per candidate serves both
+    constexpr int SF = BT >= 4 ? 4 + BT : 8;
+    __shared__ __align__(16) float s_slot[NV][SLOTS * SF];
     // A group of views whose staged rays are all x-driven runs one loop
     // with no axis test.  One whose rays are all y-driven runs the same
     // loop over horizontal pixel tuples instead, which then share each
@@ -838,10 +836,6 @@ __global__ __launch_bounds__(256, BT <= 8 ? 4 : 3) void k_backproject(KGeom g, c
     const int ih = i0 + PIX * (threadIdx.x % (16 / PIX)), jh = j0 + threadIdx.x / (16 / PIX);
     const float pxhm = ((float)min(ih, max(n - PIX, 0)) - g.half_n + 0.5f * (PIX - 1)) * g.pixel;
     const float pyh = ((float)min(jh, n - 1) - g.half_n) * g.pixel;
-    // the spare slots start as zeros (afterwards they hold zeros or finite sums)
-    if (threadIdx.x < NV) reinterpret_cast<int4*>(s_ray[threadIdx.x])[BINS] = make_int4(0, 0, 0, 0);
-    static_assert(NV * SV <= 256, "one pass zeroes the spare value slots");
-    if (threadIdx.x < NV * SV) s_val[threadIdx.x / SV][BINS * SV + threadIdx.x % SV] = 0.f;
     // group-interleaved input [group][v][k][BT]: this thread's BT images are
     // contiguous and 4 * BT-byte aligned
     const float* yg = y + (size_t)blockIdx.z * g.n_views * g.ds * BT;
@@ -894,8 +888,19 @@ __global__ __launch_bounds__(256, BT <= 8 ? 4 : 3) void k_backproject(KGeom g, c
                         e = reinterpret_cast<const int4*>(g.rays)[(size_t)v * g.n_bins + k];
                         load_group<BT>(yg + ((size_t)v * g.ds + k) * BT, t);
                     }
-                    reinterpret_cast<int4*>(s_ray[sv])[slot] = e;
-                    store_group<BT>(&s_val[sv][slot * SV], t);
+                    float* sl = &s_slot[sv][slot * SF];
+                    *reinterpret_cast<int4*>(sl) = e;
+                    store_group<BT>(sl + 4, t);
+                }
+                // the spare slot: a zero ray entry and zero values (staged with
+                // every pass: the horizontal tuples' exchange reuses this memory)
+                if (lane == 0) {
+                    float* sl = &s_slot[sv][BINS * SF];
+                    float z[BT];
+#pragma unroll
+                    for (int q = 0; q < BT; q++) z[q] = 0.f;
+                    *reinterpret_cast<int4*>(sl) = make_int4(0, 0, 0, 0);
+                    store_group<BT>(sl + 4, z);
                 }
             }
             __syncthreads();
@@ -916,7 +921,7 @@ __global__ __launch_bounds__(256, BT <= 8 ? 4 : 3) void k_backproject(KGeom g, c
                     const float2 cs = uniform_f2(&g.views[v]);
                     int wlo, whi;
                     window(bin_of<BEAM>(g, px, pym, cs.x, cs.y), r.lo, r.hi, r.meta, wlo, whi);
-                    bp_candidates<0, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
+                    bp_candidates<0, BT, PIX, SF>(s_slot[s], wlo, whi, i, j, g.c0, acc);
                 }
                 __syncthreads();
                 continue;
@@ -933,12 +938,12 @@ __global__ __launch_bounds__(256, BT <= 8 ? 4 : 3) void k_backproject(KGeom g, c
                     int wlo, whi;
                     window(bin_of<BEAM>(g, pxhm, pyh, cs.x, cs.y), lh.x, lh.y, meta, wlo, whi);
                     // the x-driven loop with the roles of rows and columns exchanged
-                    bp_candidates<0, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, jh, ih, g.c0, acc);
+                    bp_candidates<0, BT, PIX, SF>(s_slot[s], wlo, whi, jh, ih, g.c0, acc);
                 }
                 __syncthreads();
                 // tuple sums -> [row][column][image] in the value buffer -> vertical owners
-                float* xb = &s_val[0][0];
-                static_assert(NV * SLOTS * SV >= 16 * TH * BT, "exchange fits the value buffer");
+                float* xb = &s_slot[0][0];
+                static_assert(NV * SLOTS * SF >= 16 * TH * BT, "exchange fits the slot buffer");
 #pragma unroll
                 for (int q = 0; q < PIX; q++) store_group<BT>(xb + ((jh - j0) * 16 + (ih - i0) + q) * BT, acc[q]);
                 __syncthreads();
@@ -959,13 +964,13 @@ __global__ __launch_bounds__(256, BT <= 8 ? 4 : 3) void k_backproject(KGeom g, c
                 const int am = (r.meta >> 16) & 3;
                 const int axes = am == 1 ? 0 : (am == 2 ? 1 : 2);
                 if constexpr (BT >= kBpInLoopMin)
-                    bp_candidates_any<BT, PIX, SV>(axes, s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
+                    bp_candidates_any<BT, PIX, SF>(axes, s_slot[s], wlo, whi, i, j, g.c0, acc);
                 else if (axes == 0)
-                    bp_candidates<0, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
+                    bp_candidates<0, BT, PIX, SF>(s_slot[s], wlo, whi, i, j, g.c0, acc);
                 else if (axes == 1)
-                    bp_candidates<1, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
+                    bp_candidates<1, BT, PIX, SF>(s_slot[s], wlo, whi, i, j, g.c0, acc);
                 else
-                    bp_candidates<2, BT, PIX, SV>(s_ray[s], s_val[s], wlo, whi, i, j, g.c0, acc);
+                    bp_candidates<2, BT, PIX, SF>(s_slot[s], wlo, whi, i, j, g.c0, acc);
             }
             __syncthreads();
         }
