@@ -774,7 +774,7 @@ int bp_blocks(int n, int batch) { return ((n + 15) / 16) * ((n + 16 * bp_pix(bat
 // The beam type is a template parameter: as a run-time test it cost three
 // uniform branches per view (about 5% of the launch).
 template <int MODE, bool REDUCE, int BT, int PIX, int BEAM>
-__global__ __launch_bounds__(256, BT <= 8 ? 4 : 3) void k_backproject(KGeom g, const float* __restrict__ y, BpArgs a, int batch) {
+__global__ __launch_bounds__(256, BT == 8 ? 5 : (BT < 8 ? 4 : 3)) void k_backproject(KGeom g, const float* __restrict__ y, BpArgs a, int batch) {
     constexpr int NV = 8;                  // views per pass (the same for every group size)
     constexpr int VW = NV / 4;             // views staged per wavefront
     constexpr int BINS = 32 * PIX;         // staged bins per view and pass
@@ -839,11 +839,11 @@ __global__ __launch_bounds__(256, BT <= 8 ? 4 : 3) void k_backproject(KGeom g, c
     // group-interleaved input [group][v][k][BT]: this thread's BT images are
     // contiguous and 4 * BT-byte aligned
     const float* yg = y + (size_t)blockIdx.z * g.n_views * g.ds * BT;
-    double tot[PIX][BT];
+    float tot[PIX][BT];
 #pragma unroll
     for (int r = 0; r < PIX; r++)
 #pragma unroll
-        for (int q = 0; q < BT; q++) tot[r][q] = 0.0;
+        for (int q = 0; q < BT; q++) tot[r][q] = 0.f;
     for (int v0 = 0; v0 < g.n_views; v0 += NV) {
         // staging passes over the widest window of the eight views, and the
         // union of their axis bits (bit 0: some ray x-driven, bit 1: some y-driven)
@@ -977,7 +977,7 @@ __global__ __launch_bounds__(256, BT <= 8 ? 4 : 3) void k_backproject(KGeom g, c
 #pragma unroll
         for (int r = 0; r < PIX; r++)
 #pragma unroll
-            for (int q = 0; q < BT; q++) tot[r][q] += (double)acc[r][q];
+            for (int q = 0; q < BT; q++) tot[r][q] += acc[r][q];
     }
 #pragma unroll
     for (int r = 0; r < PIX; r++)
@@ -998,16 +998,16 @@ __global__ __launch_bounds__(256, BT <= 8 ? 4 : 3) void k_backproject(KGeom g, c
             if (i >= n || j + r >= n) continue;
             const size_t idx = (size_t)b * n * n + (size_t)(j + r) * n + i;
             if (MODE == BP_PLAIN) {
-                a.out[idx] = (float)tot[r][q];
+                a.out[idx] = tot[r][q];
             } else if (MODE == BP_MATVEC) {
                 const float pv = a.aux[idx];
-                const float qv = (float)fma((double)a.mu, (double)pv, tot[r][q]);
+                const float qv = (float)fma((double)a.mu, (double)pv, (double)tot[r][q]);
                 a.out[idx] = qv;
                 part += (double)pv * (double)qv;
             } else if (MODE == BP_STEP) {
-                a.out[idx] = (float)fma((double)a.mu, (double)a.rhs[idx] - tot[r][q], (double)a.aux[idx]);
+                a.out[idx] = (float)fma((double)a.mu, (double)a.rhs[idx] - (double)tot[r][q], (double)a.aux[idx]);
             } else {  // BP_RESIDUAL
-                const float rv = (float)((double)a.out[idx] - fma((double)a.mu, (double)a.aux[idx], tot[r][q]));
+                const float rv = (float)((double)a.out[idx] - fma((double)a.mu, (double)a.aux[idx], (double)tot[r][q]));
                 a.out[idx] = rv;
                 a.p_out[idx] = rv;
                 res[r][q] = rv;
