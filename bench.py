@@ -90,7 +90,7 @@ def parse():
     ap.add_argument("--serve-capacity", type=int, default=8, help="slots per geometry group")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="GPU_MAX_HW_QUEUES for this process (1-32; 0 keeps the environment's value)")
-    ap.add_argument("--serve-max-active", type=int, default=4,
+    ap.add_argument("--serve-max-active", type=int, default=5,
                     help="groups stepping at a time, those holding the oldest requests (0: all)")
     ap.add_argument("--serve-precision", default="mixed_f16", choices=["fp32", "mixed_f16", "mixed_bf16"])
     ap.add_argument("--quality", action="store_true",
