@@ -727,12 +727,12 @@ __device__ __forceinline__ void bp_candidates(const float* slots, int wlo, int w
 // The same with the axis choice (uniform over the block) inside the candidate
 // loop: one loop, so the accumulators keep one set of registers across views
 // (the per-axis loops make the compiler move them between register sets at
-// every view), and the next pair is read at the end of an iteration.  Used
-// from 8-image groups: with 8 images it needs 127 VGPRs against 167, which
+// every view).  Used from 8-image groups: it needs far fewer registers than
+// the per-axis loops (at 8 images it fits five wavefronts per SIMD), which
 // leaves room on each CU for the kernels of the other sub-batch stream of a
 // split solve (8-image halves of a 16-image batch), though on its own the
-// 8-image kernel is about 5% slower than the per-axis loops; with 16 images it
-// is faster alone too, with 4 or fewer the per-axis loops win either way.  Both
+// 8-image kernel is slower than the per-axis loops; with 16 images it is
+// faster alone too, with 4 or fewer the per-axis loops win either way.  Both
 // perform the same operations in the same order.
 constexpr int kBpInLoopMin = 8;
 template <int PIX>
@@ -783,10 +783,10 @@ __global__ __launch_bounds__(256, BT == 8 ? 5 : (BT < 8 ? 4 : 3)) void k_backpro
     static_assert(BINS % kWave == 0, "whole wavefronts stage a view");
     // one spare slot past the staged bins, read by the second candidate of a pair
     constexpr int SLOTS = BINS + 1;
-    // a slot is its bin's ray entry (4 words) and the BT values (8 words at
-    // least, so that entries stay 16-byte aligned): 12 words at 8 images, 20
-    // at 16, strides at which the 16-byte reads of 8 consecutive slots fall in
-    // distinct LDS banks; one address per candidate serves both
+    // a slot is its bin's ray entry (4 words) followed by its BT values, 8
+    // words at least (so that entries stay 16-byte aligned): 12 words at 8
+    // images, 20 at 16, strides at which the 16-byte reads of 8 consecutive
+    // slots fall in distinct LDS banks; one address per candidate serves both
     constexpr int SF = BT >= 4 ? 4 + BT : 8;
     __shared__ __align__(16) float s_slot[NV][SLOTS * SF];
     // A group of views whose staged rays are all x-driven runs one loop
@@ -796,11 +796,12 @@ __global__ __launch_bounds__(256, BT == 8 ? 5 : (BT < 8 ? 4 : 3)) void k_backpro
     // reach the vertical owners through LDS.  Every pixel takes the same
     // terms in the same order either way.  Groups of both kinds, and
     // windows wider than one pass, take the per-view axis test.  Only
-    // up to 4 images: the extra loops raise 8-image groups from 127 to
-    // 165 VGPRs and 16-image ones from 195 to 243, and the halves of a
+    // up to 4 images: the extra loops cost 8- and 16-image groups about 40
+    // VGPRs (measured when the totals were float64 and rays and values sat
+    // in separate arrays: 127 -> 165 and 195 -> 243), and the halves of a
     // two-stream solve (8 or 16 images) then leave less room for the
     // other stream's kernels (slower overall, though an 8-image launch
-    // alone is 13% faster).
+    // alone was 13% faster).
     constexpr bool kModes = BT <= 4;
     static_assert(!kModes || BT < kBpInLoopMin, "single-axis groups use the per-axis loop");
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
