@@ -117,6 +117,44 @@ def test_snapshot_resume_is_exact(env):
     assert np.array_equal(x, xs) and np.array_equal(r, rs)
 
 
+def _snapshot_x_and_c(buf, n, max_outer):
+    """The image X and the carried residual c = A'^T Y - (A'^T A + mu I) X from a
+    slot snapshot (header, X, c, b, d - b, residual history)."""
+    np_ = n * n
+    head = buf.size - 19 * np_ * 4 - max_outer * 8
+    words = buf[head:head + 2 * np_ * 4].view(np.float32)
+    return words[:np_].reshape(n, n), words[np_:].reshape(n, n)
+
+
+@pytest.mark.parametrize("wname,prec,tol", [("c1", "fp32", 1e-5), ("c2", "fp32", 1e-5), ("c2", "mixed_f16", 1e-3)])
+def test_carried_residual_tracks_the_true_one(wname, prec, tol, record):
+    """After 50 Bregman iterations (250 CG steps) the residual a slot carries
+    from one CG run to the next, c (updated by the CG recurrence instead of an
+    operator apply), still equals A'^T Y - (A'^T A + mu I) X recomputed from the
+    slot's X with the operators themselves, to the path's per-apply accuracy."""
+    import torch
+    from paper_1310_1434_amd import air
+    w = synth.workload(wname)
+    g = w.geom
+    plan = air.Plan(g, max_batch=1, precision=prec)
+    y = torch.from_numpy(synth.make_case(w, 1)["y"].astype(np.float32)).cuda()
+    n_outer = 50
+    st = air.State(plan, 1, w.lam, w.mu, w.n_cg, max_outer=n_outer, stream=torch.cuda.Stream())
+    s = st.admit(y, n_outer=n_outer)
+    while st.query(s)[0] < n_outer:
+        st.step(n_outer)
+    buf = st.snapshot(s)
+    st.retire(s)
+    x, c = _snapshot_x_and_c(buf, g.n, n_outer)
+    xt = torch.from_numpy(x.copy()).cuda()[None]
+    g_ = plan.filtered_backproject(y[None])
+    c_true = (g_ - plan.normal_apply(xt, w.mu)).double().cpu().numpy()[0]
+    torch.cuda.synchronize()
+    err = np.linalg.norm(c.astype(np.float64) - c_true) / np.linalg.norm(g_.double().cpu().numpy())
+    record(f"carried_residual_{wname}_{prec}", err)
+    assert err < tol, err
+
+
 def test_nonfinite_slot_is_isolated(env):
     """A slot whose sinogram holds a NaN: air_state_retire reports
     AIR_E_NONFINITE (and still copies it out and frees it); the other slot is
