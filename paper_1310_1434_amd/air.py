@@ -204,7 +204,8 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        # (at interpreter exit the module's globals may already be gone)
+        if h is not None and h.value and lib is not None:
             lib.air_plan_destroy(h)
             self._h = None
 
@@ -354,7 +355,7 @@ class State:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:
             lib.air_state_destroy(h)
             self._h = None
 
