@@ -178,6 +178,7 @@ struct CgArgs {
     const double* alpha;        // [batch] (update_xr)
     const double* beta;         // [batch] (update_p)
     double* partial;            // [batch][tiles16(n)] partial sums of r . r (update_xr)
+    double* amax;               // or null: [batch][tiles16(n)] per-tile max |p| (update_p)
     float* c;                   // in: W^T e (with framelet); out: carried residual g - M x (update_xc)
     bool framelet;              // split Bregman: subtract mu W^T e (update_xc)
     float mu;                   // (update_xc)

@@ -51,6 +51,27 @@ __global__ __launch_bounds__(256) void k_cg_p(CgArgs a, int batch) {
             a.p[idx] = pn[q];
         }
     }
+    if (a.amax) {
+        // per-tile max |p| of each image (the layout k_absmax writes), for the
+        // scales of the float16 copies; a maximum takes no rounding, so the
+        // order of the reduction is free
+        __shared__ float mx[4][G];
+        float m[G];
+#pragma unroll
+        for (int q = 0; q < G; q++) {
+            m[q] = valid ? fabsf(pn[q]) : 0.f;
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) m[q] = fmaxf(m[q], __shfl_xor(m[q], off, kWave));
+        }
+        if ((threadIdx.x & 63) == 0)
+#pragma unroll
+            for (int q = 0; q < G; q++) mx[threadIdx.x >> 6][q] = m[q];
+        __syncthreads();
+        if (threadIdx.x < G && b0 + (int)threadIdx.x < batch) {
+            const int q = threadIdx.x, nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
+            a.amax[(size_t)(b0 + q) * nblk + blk] = (double)fmaxf(fmaxf(mx[0][q], mx[1][q]), fmaxf(mx[2][q], mx[3][q]));
+        }
+    }
     if (!a.pad.base) return;    // float16 copies are built separately (uniform over the block)
     const int line = n + 2 * kPad;
     constexpr int P = G < 2 ? G : 2;    // pad_group(batch)

@@ -235,7 +235,9 @@ SolveBufs solve_bufs(const air_plan_s* p, const SolveLayout& L, char* ws, float*
 // plans) float16 groups with per-image power-of-two scales from max |x|
 // (partial: [batch][tiles16(n)] scratch).
 PadBuf plan_pad(const air_plan_s* p, float* pad, float* scale);
-air_status build_pad(air_plan p, const float* x, const PadBuf& pad, double* partial, int batch, hipStream_t s);
+// have_max: partial already holds x's per-tile max |x| (k_cg_p writes it).
+air_status build_pad(air_plan p, const float* x, const PadBuf& pad, double* partial, int batch, hipStream_t s,
+                     bool have_max = false);
 
 // g = A'^T Y (or A^T Y); zero b and e.  Y: [batch][V][D] (public layout).
 // Split Bregman and L2: then g -= M X (one operator apply; none if x_zero,

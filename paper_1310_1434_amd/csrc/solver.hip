@@ -108,10 +108,11 @@ PadBuf plan_pad(const air_plan_s* p, float* pad, float* scale) {
     return b;
 }
 
-air_status build_pad(air_plan p, const float* x, const PadBuf& pad, double* partial, int batch, hipStream_t s) {
+air_status build_pad(air_plan p, const float* x, const PadBuf& pad, double* partial, int batch, hipStream_t s,
+                     bool have_max) {
     const KGeom kg = p->kgeom();
     if (pad.half) {
-        AIR_K(AIR_K_OTHER, launch_absmax(kg.n, x, partial, batch, s));
+        if (!have_max) AIR_K(AIR_K_OTHER, launch_absmax(kg.n, x, partial, batch, s));
         AIR_K(AIR_K_OTHER, launch_pad_scale(partial, tiles16(kg.n), batch, pad.scale, s));
         AIR_K(AIR_K_OTHER, launch_pad16(kg, x, pad, batch, s));
     } else {
@@ -186,9 +187,10 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
         c0.r = B.r;
         c0.p = B.p;
         c0.pad = fused;
+        c0.amax = pad.half ? B.part : nullptr;     // (the float16 copies' maxima, free with p)
         AIR_K(AIR_K_CG, launch_cg_update_p(c0, batch, s));
         if (pad.half)
-            if (air_status e = build_pad(p, B.p, pad, B.part, batch, s)) return e;
+            if (air_status e = build_pad(p, B.p, pad, B.part, batch, s, true)) return e;
     }
     for (int it = 0; it < st.n_cg; it++) {
         AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, s));
@@ -221,9 +223,10 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
         AIR_K(AIR_K_CG, launch_cg_update_xr(cg, batch, s));
         AIR_K(AIR_K_CG, launch_finalize(FIN_BETA, B.part, nblk, batch, B.rho, B.beta, nullptr, 0, nullptr, s));
         cg.pad = fused;
+        cg.amax = pad.half ? B.part : nullptr;
         AIR_K(AIR_K_CG, launch_cg_update_p(cg, batch, s));
         if (pad.half)
-            if (air_status e = build_pad(p, B.p, pad, B.part, batch, s)) return e;
+            if (air_status e = build_pad(p, B.p, pad, B.part, batch, s, true)) return e;
     }
     if (tf) {
         TfArgs t{};
