@@ -178,19 +178,22 @@ struct CgArgs {
     const double* alpha;        // [batch] (update_xr)
     const double* beta;         // [batch] (update_p)
     double* partial;            // [batch][tiles16(n)] partial sums of r . r (update_xr)
-    double* amax;               // or null: [batch][tiles16(n)] per-tile max |p| (update_p)
+    float* rmax;                // or null: [batch][tiles16(n)] per-tile max |r| (update_xr)
+    float* pmax;                // or null: [batch][tiles16(n)] per-tile max |p| (update_p)
     float* c;                   // in: W^T e (with framelet); out: carried residual g - M x (update_xc)
     bool framelet;              // split Bregman: subtract mu W^T e (update_xc)
     float mu;                   // (update_xc)
 };
 hipError_t launch_cg_update_xr(const CgArgs& a, int batch, hipStream_t s);   // x += a p, r -= a q; partials of r.r
-hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s);    // p = r + b p (p = r if !beta), and its pad
+// p = r + b p (p = r if !beta), and its pad (float16 copies scaled by pad.scale,
+// which must hold the scales k_finalize derived for this p)
+hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s);
 // last CG step: x += a p, c = (r - a q) - mu W^T e, W^T e read from c (no partials)
 hipError_t launch_cg_update_xc(const CgArgs& a, int batch, hipStream_t s);
 // start of an L2 sub-problem: r = c + mu W^T e (r = c if e is null), then W^T e
-// written over c (if e); partials of r.r
-hipError_t launch_cg_start(int n, float* c, const float* e, float mu, float* r, double* partial, int batch,
-                           hipStream_t s);
+// written over c (if e); partials of r.r, and per-tile max |r| if rmax
+hipError_t launch_cg_start(int n, float* c, const float* e, float mu, float* r, double* partial, float* rmax,
+                           int batch, hipStream_t s);
 
 // Fixed-order sums of the block partials [batch][nblk] and the scalars derived from them:
 enum FinalizeMode {
@@ -199,8 +202,18 @@ enum FinalizeMode {
     FIN_BETA = 2,   // rho' = sum; beta[b] = rho' / rho (0 if rho is 0); rho[b] = rho'
     FIN_RESID = 3,  // out[b * stride + k] = sqrt(sum), k = iters[b]++ (k = 0 if iters is null)
 };
+// With scale (FIN_RHO, FIN_BETA only): also scale[b], the power-of-two scale
+// of the float16 copies of the next CG direction, from the bound
+// max |r| + beta max |p_old| (rmax, pmax: [batch][nblk] block maxima; pmax
+// unused for FIN_RHO, where p = r).
+struct HalfScaleArgs {
+    const float* rmax = nullptr;
+    const float* pmax = nullptr;
+    float* scale = nullptr;
+};
 hipError_t launch_finalize(int mode, const double* partial, int nblk, int batch, double* rho, double* coef,
-                           double* out, int stride, int* iters, hipStream_t s);
+                           double* out, int stride, int* iters, hipStream_t s,
+                           const HalfScaleArgs& sc = HalfScaleArgs{});
 
 // Framelet kernels.
 hipError_t launch_framelet_fwd(int n, const float* x, float* z, int batch, hipStream_t s);

@@ -19,19 +19,23 @@ __global__ __launch_bounds__(256) void k_cg_xr(CgArgs a) {
     const double alpha = a.alpha[b];
     const size_t idx = (size_t)b * n * n + (size_t)j * n + i;
     double part = 0.0;
+    float rn = 0.f;
     if (i < n && j < n) {
         const float xn = (float)fma(alpha, (double)a.p[idx], (double)a.x[idx]);
-        const float rn = (float)fma(-alpha, (double)a.q[idx], (double)a.r[idx]);
+        rn = (float)fma(-alpha, (double)a.q[idx], (double)a.r[idx]);
         a.x[idx] = xn;
         a.r[idx] = rn;
         part = (double)rn * (double)rn;
     }
     const int nblk = gridDim.x * gridDim.y, blk = (j0 / 16) * gridDim.x + i0 / 16;
     block_partial<256>(part, a.partial + (size_t)b * nblk + blk);
+    if (a.rmax) block_max<256>(fabsf(rn), a.rmax + (size_t)b * nblk + blk);
 }
 
 // p = r + beta p (p = r without beta) for a group of G images; p also goes to
-// its padded line sets.
+// its padded line sets (float16 ones scaled by the image's scale, which
+// k_finalize derived from a bound on max |p|), and the block's max |p| of each
+// image to pmax (the next bound needs it).
 template <int G>
 __global__ __launch_bounds__(256) void k_cg_p(CgArgs a, int batch) {
     __shared__ float lds[16 * 17 * G];
@@ -51,15 +55,13 @@ __global__ __launch_bounds__(256) void k_cg_p(CgArgs a, int batch) {
             a.p[idx] = pn[q];
         }
     }
-    if (a.amax) {
-        // per-tile max |p| of each image (the layout k_absmax writes), for the
-        // scales of the float16 copies; a maximum takes no rounding, so the
-        // order of the reduction is free
+    if (a.pmax) {
+        // the block's max |p| of each image, reduced for all G at once
         __shared__ float mx[4][G];
         float m[G];
 #pragma unroll
         for (int q = 0; q < G; q++) {
-            m[q] = valid ? fabsf(pn[q]) : 0.f;
+            m[q] = fabsf(pn[q]);
 #pragma unroll
             for (int off = kWave / 2; off > 0; off >>= 1) m[q] = fmaxf(m[q], __shfl_xor(m[q], off, kWave));
         }
@@ -69,13 +71,20 @@ __global__ __launch_bounds__(256) void k_cg_p(CgArgs a, int batch) {
         __syncthreads();
         if (threadIdx.x < G && b0 + (int)threadIdx.x < batch) {
             const int q = threadIdx.x, nblk = gridDim.x * gridDim.y, blk = blockIdx.y * gridDim.x + blockIdx.x;
-            a.amax[(size_t)(b0 + q) * nblk + blk] = (double)fmaxf(fmaxf(mx[0][q], mx[1][q]), fmaxf(mx[2][q], mx[3][q]));
+            a.pmax[(size_t)(b0 + q) * nblk + blk] = fmaxf(fmaxf(mx[0][q], mx[1][q]), fmaxf(mx[2][q], mx[3][q]));
         }
     }
-    if (!a.pad.base) return;    // float16 copies are built separately (uniform over the block)
     const int line = n + 2 * kPad;
-    constexpr int P = G < 2 ? G : 2;    // pad_group(batch)
-    store_padded_group<G, P>(a.pad.base + (size_t)b0 * 2 * n * line, n, line, i0, j0, tx, ty, pn, lds);
+    if (a.pad.half) {
+        constexpr int P = G < 4 ? G : 4;    // pad_group16(batch)
+        float h[G];
+#pragma unroll
+        for (int q = 0; q < G; q++) h[q] = b0 + q < batch ? pn[q] * a.pad.scale[b0 + q] : 0.f;   // (exact: 2^k)
+        store_padded_group<G, P>(a.pad.half + (size_t)b0 * 2 * n * line, n, line, i0, j0, tx, ty, h, lds);
+    } else if (a.pad.base) {
+        constexpr int P = G < 2 ? G : 2;    // pad_group(batch)
+        store_padded_group<G, P>(a.pad.base + (size_t)b0 * 2 * n * line, n, line, i0, j0, tx, ty, pn, lds);
+    }
 }
 
 hipError_t launch_cg_update_xr(const CgArgs& a, int batch, hipStream_t s) {
@@ -86,6 +95,8 @@ hipError_t launch_cg_update_xr(const CgArgs& a, int batch, hipStream_t s) {
 
 hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s) {
     const int grp = image_group(batch);
+    // (the kernel writes float16 copies in sub-groups of min(G, 4) images)
+    if (a.pad.half && (std::min(grp, 4) != pad_group16(batch) || !a.pad.scale)) return hipErrorInvalidValue;
     dim3 grid((a.n + 15) / 16, (a.n + 15) / 16, (batch + grp - 1) / grp), block(256);
     if (grp == 16) hipLaunchKernelGGL(k_cg_p<16>, grid, block, 0, s, a, batch);
     else if (grp == 8) hipLaunchKernelGGL(k_cg_p<8>, grid, block, 0, s, a, batch);
@@ -97,19 +108,43 @@ hipError_t launch_cg_update_p(const CgArgs& a, int batch, hipStream_t s) {
 
 // One block per batch item: sum the block partials in index order (each
 // thread a fixed stride, then a fixed tree) and derive the CG scalar.
+// With sc.scale (FIN_RHO, FIN_BETA), also the scale of the float16 copies of
+// the direction p = r + beta p that k_cg_p builds next: from the bound
+// max |r| + beta max |p_old| on max |p| (max |r| for p = r), over the block
+// maxima sc.rmax and sc.pmax ([batch][nblk]), as in k_pad_scale.
 __global__ __launch_bounds__(256) void k_finalize(int mode, const double* __restrict__ partial, int nblk,
                                                   double* __restrict__ rho, double* __restrict__ coef,
-                                                  double* __restrict__ out, int stride, int* __restrict__ iters) {
+                                                  double* __restrict__ out, int stride, int* __restrict__ iters,
+                                                  HalfScaleArgs sc) {
     __shared__ double sh[4];
+    __shared__ float shm[2][4];
     const int b = blockIdx.x, tid = threadIdx.x;
     const double* pb = partial + (size_t)b * nblk;
     double s = 0.0;
     for (int i = tid; i < nblk; i += 256) s += pb[i];
     s = wave_sum(s);
     if (tid % kWave == 0) sh[tid / kWave] = s;
+    if (sc.scale) {     // (uniform)
+        float mr = 0.f, mp = 0.f;
+        for (int i = tid; i < nblk; i += 256) {
+            mr = fmaxf(mr, sc.rmax[(size_t)b * nblk + i]);
+            if (mode == FIN_BETA) mp = fmaxf(mp, sc.pmax[(size_t)b * nblk + i]);
+        }
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            mr = fmaxf(mr, __shfl_xor(mr, off, kWave));
+            mp = fmaxf(mp, __shfl_xor(mp, off, kWave));
+        }
+        if (tid % kWave == 0) {
+            shm[0][tid / kWave] = mr;
+            shm[1][tid / kWave] = mp;
+        }
+    }
     __syncthreads();
     if (tid != 0) return;
     const double sum = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    double bound = 0.0;
+    if (sc.scale) bound = fmaxf(fmaxf(shm[0][0], shm[0][1]), fmaxf(shm[0][2], shm[0][3]));
     switch (mode) {
     case FIN_RHO:
         rho[b] = sum;
@@ -123,6 +158,8 @@ __global__ __launch_bounds__(256) void k_finalize(int mode, const double* __rest
         const double r = rho[b];
         coef[b] = r == 0.0 ? 0.0 : sum / r;
         rho[b] = sum;
+        if (sc.scale)
+            bound += coef[b] * (double)fmaxf(fmaxf(shm[1][0], shm[1][1]), fmaxf(shm[1][2], shm[1][3]));
         break;
     }
     default: {
@@ -131,11 +168,26 @@ __global__ __launch_bounds__(256) void k_finalize(int mode, const double* __rest
         if (iters) iters[b] = k + 1;
     }
     }
+    if (sc.scale) {
+        // |p| <= max |r| + beta max |p_old| up to one rounding (|p| (1 + 2^-24)),
+        // so p's scaled copy stays below 2^14 (1 + 2^-24), far from float16's
+        // overflow; the bound is at most twice max |p|, which only moves values
+        // below 2^-26 max |p| into float16's subnormal range
+        float sv = 1.f;
+        if (bound > 0.0 && isfinite(bound)) {
+            int e;
+            frexp(bound, &e);                                // bound = f 2^e, f in [0.5, 1)
+            sv = ldexpf(1.f, min(max(14 - e, -126), 126));   // bound * s in [2^13, 2^14)
+        }
+        sc.scale[b] = sv;
+    }
 }
 
 hipError_t launch_finalize(int mode, const double* partial, int nblk, int batch, double* rho, double* coef,
-                           double* out, int stride, int* iters, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(256), 0, s, mode, partial, nblk, rho, coef, out, stride, iters);
+                           double* out, int stride, int* iters, hipStream_t s, const HalfScaleArgs& sc) {
+    if (sc.scale && (mode != FIN_RHO && mode != FIN_BETA)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(256), 0, s, mode, partial, nblk, rho, coef, out, stride, iters,
+                       sc);
     return hipGetLastError();
 }
 
@@ -244,15 +296,17 @@ __global__ __launch_bounds__(256) void k_framelet_adj(const float* __restrict__ 
 // takes c's place (in ct: c is not read again before the sub-problem's last
 // CG step writes the next c there, and that step needs W^T e).
 __global__ __launch_bounds__(256) void k_cg_start(float* __restrict__ ct, const float* __restrict__ e, float mu,
-                                                  float* __restrict__ r, double* __restrict__ partial, int n) {
+                                                  float* __restrict__ r, double* __restrict__ partial,
+                                                  float* __restrict__ rmax, int n) {
     int i0, j0;
     framelet_tile(i0, j0);
     const int i = i0 + (threadIdx.x & 15), j = j0 + (threadIdx.x >> 4), b = blockIdx.z;
     const size_t np = (size_t)n * n;
     double part = 0.0;
+    float rv = 0.f;
     if (i < n && j < n) {
         const size_t idx = b * np + (size_t)j * n + i;
-        float rv = ct[idx];
+        rv = ct[idx];
         if (e) {
             const float adj = framelet_adj_at(e + (size_t)b * 9 * np, n, i, j);
             rv = fmaf(mu, adj, rv);
@@ -263,6 +317,7 @@ __global__ __launch_bounds__(256) void k_cg_start(float* __restrict__ ct, const 
     }
     const int nblk = gridDim.x * gridDim.y, blk = (j0 / 16) * gridDim.x + i0 / 16;
     block_partial<256>(part, partial + (size_t)b * nblk + blk);
+    if (rmax) block_max<256>(fabsf(rv), rmax + (size_t)b * nblk + blk);
 }
 
 // Last CG step of an L2 sub-problem: x += alpha p, and instead of r the carried
@@ -378,10 +433,10 @@ hipError_t launch_framelet_adj(int n, const float* z, float* x, int batch, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_cg_start(int n, float* c, const float* e, float mu, float* r, double* partial, int batch,
-                           hipStream_t s) {
+hipError_t launch_cg_start(int n, float* c, const float* e, float mu, float* r, double* partial, float* rmax,
+                           int batch, hipStream_t s) {
     dim3 grid((n + 15) / 16, (n + 15) / 16, batch);
-    hipLaunchKernelGGL(k_cg_start, grid, dim3(256), 0, s, c, e, mu, r, partial, n);
+    hipLaunchKernelGGL(k_cg_start, grid, dim3(256), 0, s, c, e, mu, r, partial, rmax, n);
     return hipGetLastError();
 }
 

@@ -65,16 +65,6 @@ hipError_t launch_pad(const KGeom& g, const float* x, PadBuf pad, int batch, hip
 // float16 copies: 16x16 tiles of P images, scaled per image; the column copy
 // goes through shared memory so both copies are written as contiguous runs.
 template <int P>
-__device__ __forceinline__ void store_half_group(uint16_t* p, const float (&v)[P]) {
-    uint16_t h[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int q = 0; q < P; q++) h[q] = __half_as_ushort(__float2half_rn(v[q]));
-    if constexpr (P == 4) *reinterpret_cast<uint2*>(p) = make_uint2(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16);
-    else if constexpr (P == 2) *reinterpret_cast<uint32_t*>(p) = h[0] | (uint32_t)h[1] << 16;
-    else p[0] = h[0];
-}
-
-template <int P>
 __global__ __launch_bounds__(256) void k_pad16(const float* __restrict__ x, uint16_t* __restrict__ pad,
                                                const float* __restrict__ scale, int n, int line, int batch) {
     __shared__ float lds[16 * 17 * P];

@@ -210,6 +210,8 @@ struct SolveBufs {
     float* bb;      // [batch][8][n][n] Bregman b (bands 1..8)
     float* e;       // [batch][9][n][n] d - b
     double* part;   // [batch][tiles16(n)] block partial sums
+    float* rmax;    // [batch][tiles16(n)] block maxima of |r| (float16 scales of p)
+    float* pmax;    // [batch][tiles16(n)] block maxima of |p|
     double* rho;    // [batch]
     double* alpha;  // [batch]
     double* beta;   // [batch]
@@ -227,7 +229,7 @@ struct SolveSetup {
 
 // Bytes of the per-image buffers of SolveBufs (excluding the sinogram scratch).
 struct SolveLayout {
-    size_t pad, pscale, s1, s2, rscale, g, r, p, q, bb, e, part, scal, iters, total;
+    size_t pad, pscale, s1, s2, rscale, g, r, p, q, bb, e, part, mx, scal, iters, total;
 };
 SolveLayout solve_layout(const air_plan_s* p, int batch);
 SolveBufs solve_bufs(const air_plan_s* p, const SolveLayout& L, char* ws, float* X, int batch);
@@ -235,9 +237,7 @@ SolveBufs solve_bufs(const air_plan_s* p, const SolveLayout& L, char* ws, float*
 // plans) float16 groups with per-image power-of-two scales from max |x|
 // (partial: [batch][tiles16(n)] scratch).
 PadBuf plan_pad(const air_plan_s* p, float* pad, float* scale);
-// have_max: partial already holds x's per-tile max |x| (k_cg_p writes it).
-air_status build_pad(air_plan p, const float* x, const PadBuf& pad, double* partial, int batch, hipStream_t s,
-                     bool have_max = false);
+air_status build_pad(air_plan p, const float* x, const PadBuf& pad, double* partial, int batch, hipStream_t s);
 
 // g = A'^T Y (or A^T Y); zero b and e.  Y: [batch][V][D] (public layout).
 // Split Bregman and L2: then g -= M X (one operator apply; none if x_zero,

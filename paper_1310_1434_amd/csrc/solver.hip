@@ -23,6 +23,7 @@ SolveLayout solve_layout(const air_plan_s* p, int batch) {
     L.bb = c.take(B * 8 * np * sizeof(float));
     L.e = c.take(B * 9 * np * sizeof(float));
     L.part = c.take(B * tiles16((int)n) * sizeof(double));
+    L.mx = c.take(2 * B * tiles16((int)n) * sizeof(float));
     L.scal = c.take(B * 4 * sizeof(double));
     L.iters = c.take(B * sizeof(int));
     L.total = c.off;
@@ -30,7 +31,6 @@ SolveLayout solve_layout(const air_plan_s* p, int batch) {
 }
 
 SolveBufs solve_bufs(const air_plan_s* p, const SolveLayout& L, char* w, float* X, int batch) {
-    (void)p;
     auto F = [&](size_t off) { return reinterpret_cast<float*>(w + off); };
     SolveBufs B;
     B.X = X;
@@ -46,6 +46,8 @@ SolveBufs solve_bufs(const air_plan_s* p, const SolveLayout& L, char* w, float* 
     B.bb = F(L.bb);
     B.e = F(L.e);
     B.part = reinterpret_cast<double*>(w + L.part);
+    B.rmax = reinterpret_cast<float*>(w + L.mx);
+    B.pmax = B.rmax + (size_t)batch * tiles16(p->g.n);
     double* scal = reinterpret_cast<double*>(w + L.scal);
     B.rho = scal;
     B.alpha = scal + batch;
@@ -108,11 +110,10 @@ PadBuf plan_pad(const air_plan_s* p, float* pad, float* scale) {
     return b;
 }
 
-air_status build_pad(air_plan p, const float* x, const PadBuf& pad, double* partial, int batch, hipStream_t s,
-                     bool have_max) {
+air_status build_pad(air_plan p, const float* x, const PadBuf& pad, double* partial, int batch, hipStream_t s) {
     const KGeom kg = p->kgeom();
     if (pad.half) {
-        if (!have_max) AIR_K(AIR_K_OTHER, launch_absmax(kg.n, x, partial, batch, s));
+        AIR_K(AIR_K_OTHER, launch_absmax(kg.n, x, partial, batch, s));
         AIR_K(AIR_K_OTHER, launch_pad_scale(partial, tiles16(kg.n), batch, pad.scale, s));
         AIR_K(AIR_K_OTHER, launch_pad16(kg, x, pad, batch, s));
     } else {
@@ -164,9 +165,11 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
     const bool tf = st.reg == 0;
     const float mu_op = (float)(tf ? st.mu : st.lambda);
     const PadBuf pad = plan_pad(p, B.pad, B.pscale);
-    // float32 copies of p come out of the epilogues that produce p; float16
-    // copies need p's maximum first, so they are built by build_pad
-    const PadBuf fused = pad.half ? PadBuf{} : pad;
+    // the padded copies of p come out of k_cg_p, which produces p; float16
+    // copies take a power-of-two scale per image, which the k_finalize before
+    // it derives from a bound on max |p| (block maxima of r and of the last p)
+    HalfScaleArgs hs{};
+    if (pad.half) hs = HalfScaleArgs{B.rmax, B.pmax, pad.scale};
     // operator A'^T A + mu I = J^T (S C S) J + mu I (IR arm: J^T S^2 J + mu I)
     auto filtered = [&]() -> air_status {
         if (st.filter)
@@ -180,17 +183,16 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
     // arithmetic it is the right-hand side g + mu W^T e minus M X.
     // (with no CG step X stays as it is, and so does c)
     if (st.n_cg > 0) {
-        AIR_K(AIR_K_CG, launch_cg_start(n, B.g, tf ? B.e : nullptr, (float)st.mu, B.r, B.part, batch, s));
-        AIR_K(AIR_K_CG, launch_finalize(FIN_RHO, B.part, nblk, batch, B.rho, nullptr, nullptr, 0, nullptr, s));
+        AIR_K(AIR_K_CG, launch_cg_start(n, B.g, tf ? B.e : nullptr, (float)st.mu, B.r, B.part,
+                                        pad.half ? B.rmax : nullptr, batch, s));
+        AIR_K(AIR_K_CG, launch_finalize(FIN_RHO, B.part, nblk, batch, B.rho, nullptr, nullptr, 0, nullptr, s, hs));
         CgArgs c0{};
         c0.n = n;
         c0.r = B.r;
         c0.p = B.p;
-        c0.pad = fused;
-        c0.amax = pad.half ? B.part : nullptr;     // (the float16 copies' maxima, free with p)
+        c0.pad = pad;
+        c0.pmax = pad.half ? B.pmax : nullptr;
         AIR_K(AIR_K_CG, launch_cg_update_p(c0, batch, s));
-        if (pad.half)
-            if (air_status e = build_pad(p, B.p, pad, B.part, batch, s, true)) return e;
     }
     for (int it = 0; it < st.n_cg; it++) {
         AIR_K(AIR_K_PROJECT, launch_project(kg, pad, B.s1, batch, s));
@@ -220,13 +222,12 @@ air_status solve_outer(air_plan p, const SolveBufs& B, int batch, const SolveSet
             AIR_K(AIR_K_CG, launch_cg_update_xc(cg, batch, s));
             break;
         }
+        cg.rmax = pad.half ? B.rmax : nullptr;
         AIR_K(AIR_K_CG, launch_cg_update_xr(cg, batch, s));
-        AIR_K(AIR_K_CG, launch_finalize(FIN_BETA, B.part, nblk, batch, B.rho, B.beta, nullptr, 0, nullptr, s));
-        cg.pad = fused;
-        cg.amax = pad.half ? B.part : nullptr;
+        AIR_K(AIR_K_CG, launch_finalize(FIN_BETA, B.part, nblk, batch, B.rho, B.beta, nullptr, 0, nullptr, s, hs));
+        cg.pad = pad;
+        cg.pmax = pad.half ? B.pmax : nullptr;
         AIR_K(AIR_K_CG, launch_cg_update_p(cg, batch, s));
-        if (pad.half)
-            if (air_status e = build_pad(p, B.p, pad, B.part, batch, s, true)) return e;
     }
     if (tf) {
         TfArgs t{};

@@ -66,6 +66,8 @@ struct air_state_s {
         b.bb += pos * 8 * n;
         b.e += pos * 9 * n;
         b.part += (size_t)pos * tiles16(plan->g.n);
+        b.rmax += (size_t)pos * tiles16(plan->g.n);
+        b.pmax += (size_t)pos * tiles16(plan->g.n);
         b.rho += pos;
         b.alpha += pos;
         b.beta += pos;
