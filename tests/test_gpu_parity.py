@@ -588,6 +588,36 @@ def test_mixed_plan_projection_of_zero_and_tiny_images(air, torch_mod):
     assert rel(y[1], ref[1]) < 5e-4 and rel(y[2], ref[2]) < 5e-4
 
 
+@pytest.mark.parametrize("prec", ["fp32", "mixed_f16"])
+@pytest.mark.parametrize("reg", [0, 1])
+def test_solve_commutes_with_power_of_two_scales(air, torch_mod, reg, prec):
+    """Every float16 copy in a mixed solve takes a power-of-two scale relative to
+    its own maximum: the image's from max |X|, each CG direction's from the
+    bound max |r| + beta max |p_old| on max |p|, the split ramp's per row.  So a
+    solve of 2^k Y is 2^k times the solve of Y, bit for bit, with sinograms of
+    1e12 and 1e-12, far outside float16's range (split Bregman with 2^k lambda:
+    its shrinkage threshold lambda / (2 mu) scales with the image; the L2
+    problem's lambda weights X itself and stays).  The float32 path, specified
+    below 2^80, does the same."""
+    w = synth.workload("c1")
+    y = np.stack([synth.make_case(w, s)["y"] for s in range(2)]).astype(np.float32)
+    plan = air.Plan(w.geom, max_batch=2, precision=prec)
+    lam = 0.05 if reg == 1 else w.lam
+    n_outer, n_cg = (0, 8) if reg == 1 else (4, 4)
+
+    def solve(k):
+        f = 2.0 ** k
+        lk = lam * f if reg == 0 else lam
+        x, _ = plan.solve(dev(torch_mod, y * np.float32(f)), lk, w.mu, n_outer, n_cg, reg=reg, with_resid=False)
+        return host(x)
+
+    x0 = solve(0)
+    assert np.isfinite(x0).all() and np.abs(x0).max() > 0
+    for k in (40, -40):
+        xk = solve(k)
+        assert np.array_equal(xk, x0 * 2.0 ** k), k
+
+
 @pytest.mark.parametrize("name", ["ragged", "c1"])
 def test_float32_operators_commute_with_power_of_two_scales(air, torch_mod, name):
     """Within the float32 plans' range (below 2^80) the projector and the
