@@ -65,8 +65,9 @@ typedef enum { AIR_PARALLEL = 0, AIR_FAN_FLAT = 1 } air_beam;
  *                   float32 accumulation
  * In the two mixed modes the forward projector also reads its image copies
  * in float16 (each image scaled by a power of two so that its largest value
- * lies in [2^13, 2^14); the scale is undone exactly on the float32 sums), which
- * halves the bytes of its gathers.  Projector accumulation, images,
+ * lies in [2^13, 2^14); inside a solve's CG steps, so that a bound on the
+ * direction's largest value, at most twice that value, does; the scale is
+ * undone exactly on the float32 sums), which halves the bytes of its gathers.  Projector accumulation, images,
  * sinograms and CG vectors are float32 in all modes; CG inner products, the
  * step sizes alpha/beta and the Bregman residual norm are float64.
  * Range: the projector and backprojector sum interpolation weights scaled by
