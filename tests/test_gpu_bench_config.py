@@ -1,7 +1,8 @@
-"""GPU parity of the configuration the benchmark times: sixteen 512^2 fan-beam
-cases (720 views x 736 bins, split Bregman 50 x 5 CG) in one air_solve call,
-which runs them as two 8-image sub-batches on two streams (the 8-image
-backprojector groups and the image-pair forward projector).
+"""GPU parity of the configurations the benchmark times: sixteen 512^2 fan-beam
+cases (720 views x 736 bins, and the 25% data of 180 of those views; split
+Bregman 50 x 5 CG) in one air_solve call, which runs them as two 8-image
+sub-batches on two streams (the 8-image backprojector groups and the
+image-pair forward projector).
 
 Seed 0's sinogram sits in slot 0 (first image of the first sub-batch) and
 slot 15 (last image of the second), other seeds elsewhere.  Both copies of seed 0 are compared with the
@@ -29,30 +30,33 @@ def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
-@pytest.fixture(scope="module")
-def c2_batch():
+GOLDEN = {"c2": "c2_fan_512_720_seed0", "c2_25": "c2_fan_512_180_seed0"}
+
+
+@pytest.fixture(scope="module", params=["c2", "c2_25"])
+def c2_batch(request):
     import torch
     assert torch.cuda.is_available()
-    w = synth.workload("c2")
+    w = synth.workload(request.param)
     cases = {s: synth.make_case(w, s)["y"].astype(np.float32) for s in sorted(set(SEEDS))}
     ys = np.stack([cases[s] for s in SEEDS])
-    return torch, w, ys
+    return torch, w, ys, request.param
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("mixed_f16", 1e-3)])
 def test_benched_c2_batch16_two_streams(c2_batch, record, prec, tol):
-    torch, w, ys = c2_batch
+    torch, w, ys, name = c2_batch
     from paper_1310_1434_amd import air
-    ref = np.load(os.path.join(HERE, "golden", "c2_fan_512_720_seed0.npz"))
+    ref = np.load(os.path.join(HERE, "golden", GOLDEN[name] + ".npz"))
     plan = air.Plan(w.geom, max_batch=BATCH, precision=prec)
-    print(f"C2 batch {BATCH} two-stream solve, {prec}", flush=True)
+    print(f"{name} batch {BATCH} two-stream solve, {prec}", flush=True)
     x, resid = plan.solve(torch.from_numpy(ys).cuda(), w.lam, w.mu, w.n_outer, w.n_cg)
     torch.cuda.synchronize()
     xb = x.cpu().numpy()
     rb = resid.cpu().numpy()
     for b in (0, BATCH - 1):
         e = rel(xb[b], ref["x"])
-        record(f"rel_l2_final_c2_b16_{prec}_slot{b}", e)
+        record(f"rel_l2_final_{name}_b16_{prec}_slot{b}", e)
         assert e < tol, (b, e)
         np.testing.assert_allclose(rb[b], ref["resid"], rtol=1e-2 if prec == "fp32" else 5e-2)
     assert np.array_equal(xb[0], xb[BATCH - 1])          # the two sub-batches give seed 0 the same bits
